@@ -1,0 +1,203 @@
+#!/usr/bin/env python3
+"""Throughput of the Lanczos full-frequency GW self-energy on one MI355X.
+
+Workload (grid64_v128c512): 64^3 grid in a 24 bohr box, 128 occupied + 512
+empty seeded orthonormal real orbitals (pair dimension 65,536), Lanczos on
+p_7(C) with L = 200 steps, 2,000 frequencies in [-20, 20] eV, broadening
+0.05 eV, full reorthogonalisation.  Arithmetic: GEMM operands BF16 with FP32
+accumulation, FP32 FFT, FP64 Lanczos recurrence / Chebyshev combination /
+continued fraction.
+
+One step = one block of B start vectors (m, n) of one quasiparticle state m
+through the whole path: coupling vectors P_nm, L Lanczos steps on p_g(C)
+(g factored C-products each), continued fraction at every frequency and the
+sum over n.  N_orb / B steps make one spectrum Sigma_mm(omega); the metric is
+spectra per second.
+
+Also reported: the plain FP64 GPU path on a steady-state window (B vectors,
+a few Lanczos steps) extrapolated to spectra/s, the mixed-vs-FP64 error on a
+sample, the roofline fraction of the dominant kernel (HIP events on the
+library's stream), and the FP64 CPU oracle on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_BF16_TFLOPS = 2500.0   # MI355X dense BF16 MFMA
+PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 matrix
+METRIC = "Sigma_c spectra/s & matvec TFLOP/s, mixed vs FP64 on 1 GPU at 1e-3 eV"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(wl, phi, eps, m, n, steps, lo, hi):
+    """The FP64 oracle (matrix-free route) on a bounded sample: one start
+    vector, `steps` Lanczos steps, extrapolated to spectra/s."""
+    import oracle
+    cores = os.cpu_count() or 1
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 0) for i in threadpool_info()] + [1])
+    except Exception:
+        pass
+    t0 = time.perf_counter()
+    pr = oracle.Problem(phi, eps, wl.n_occ, wl.grid, wl.h, dense=False)
+    t_coup0 = time.perf_counter()
+    coeffs = pr.lanczos_coeffs(m, steps, lo, hi, wl.poly_degree, reorth="full",
+                               route="matfree", n_list=[n])
+    t1 = time.perf_counter()
+    per_step = (t1 - t_coup0) / steps
+    per_spectrum = per_step * wl.n_lanczos * wl.n_orb
+    return {
+        "value": 1.0 / per_spectrum, "unit": "spectra/s", "cores": int(cores), "kind": "oracle",
+        "sample": (f"oracle matrix-free Lanczos on p_{wl.poly_degree}(C), 1 start vector "
+                   f"(m={m}, n={n}), {steps} steps incl. its coupling vector, "
+                   f"{t1 - t_coup0:.1f} s, extrapolated x {wl.n_lanczos} steps x "
+                   f"{wl.n_orb} vectors"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--block", type=int, default=128)
+    ap.add_argument("--workload", default="grid64_v128c512")
+    ap.add_argument("--fp64-window", type=int, default=2, help="Lanczos steps of the FP64 window")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import gw_inputs as gi
+    import paper_2310_20103_amd as G
+
+    assert torch.cuda.is_available(), "needs a GPU"
+    wl = gi.workload(args.workload)
+    t = time.perf_counter()
+    phi = gi.make_orbitals(wl)
+    eps = gi.make_energies(wl)
+    qp = gi.frontier_states(eps, wl.n_occ, wl.n_qp_occ, wl.n_qp_emp)
+    omega = gi.omega_grid(wl)
+    log(f"inputs {time.perf_counter() - t:.1f}s")
+    B = min(args.block, wl.n_orb)
+    box = tuple(n * wl.h for n in wl.grid)
+    t = time.perf_counter()
+    ctx = G.Context(phi, eps, wl.n_occ, wl.grid, box, precision="mixed",
+                    poly_degree=wl.poly_degree, reorth="full", block=B)
+    lo, hi = ctx.interval
+    log(f"setup {time.perf_counter() - t:.1f}s, interval [{lo:.4g}, {hi:.4g}] Ha^2")
+
+    blocks_per_spectrum = (wl.n_orb + B - 1) // B
+
+    def step_args(s):
+        m = int(qp[(s // blocks_per_spectrum) % len(qp)])
+        nb = (s % blocks_per_spectrum) * B
+        return m, nb, min(wl.n_orb, nb + B)
+
+    # buffers and code objects: one Lanczos step over B vectors
+    ctx.lanczos_pairs([int(qp[0])] * B, list(range(B)), [1] * B)
+    for s in range(args.warmup):
+        m, n0, n1 = step_args(s)
+        ctx.sigma_c_range([m], n0, n1, omega, wl.eta, wl.n_lanczos)
+    ctx.set_option(G.KEY_PROFILE, 1)
+    prof = {"gemm1": [0.0, 0, 0], "gemm2": [0.0, 0, 0], "fft": [0.0, 0, 0]}
+    n_vec = 0
+    n_prod = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        m, n0, n1 = step_args(s)
+        ctx.sigma_c_range([m], n0, n1, omega, wl.eta, wl.n_lanczos)
+        n_vec += n1 - n0
+        n_prod += ctx.query(G.KEY_LAST_C_MATVECS)
+        for k, (ms, cnt, vec) in ctx.profile_totals().items():
+            prof[k][0] += ms
+            prof[k][1] += cnt
+            prof[k][2] += vec
+        log(f"step {s}: m={m} n=[{n0},{n1}) done")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ctx.set_option(G.KEY_PROFILE, 0)
+    spectra = n_vec / wl.n_orb
+    value = spectra / elapsed
+    flop_vec = 4.0 * wl.n_r * wl.n_occ * wl.n_emp     # both GEMMs, one C-product
+    matvec_tflops = flop_vec * n_prod / elapsed / 1e12
+
+    # dominant kernel (largest event time) and its roofline
+    dom = max(("gemm1", "gemm2"), key=lambda k: prof[k][0])
+    ms, cnt, vec = prof[dom]
+    flop_launch = 2.0 * wl.n_r * wl.n_occ * wl.n_emp * (vec / max(cnt, 1))
+    achieved = flop_launch / (ms / max(cnt, 1) / 1e3) / 1e12 if cnt else 0.0
+    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4),
+                "traffic": None, "kernel": f"{dom}_bf16", "launches": int(cnt),
+                "avg_launch_ms": round(ms / max(cnt, 1), 4)}
+    kernel_ms = {k: round(v[0], 2) for k, v in prof.items()}
+
+    # plain FP64 GPU path on a steady-state window, extrapolated
+    ctx.set_precision("fp64")
+    mw = int(qp[0])
+    ctx.lanczos_pairs([mw] * B, list(range(B)), [1] * B)
+    t = time.perf_counter()
+    ctx.lanczos_pairs([mw] * B, list(range(B)), [args.fp64_window] * B)
+    t64 = time.perf_counter() - t
+    per_vec_step64 = t64 / (B * args.fp64_window)
+    fp64_value = 1.0 / (per_vec_step64 * wl.n_lanczos * wl.n_orb)
+    fp64_tflops = flop_vec * ctx.query(G.KEY_LAST_C_MATVECS) / t64 / 1e12
+
+    # accuracy: mixed vs FP64 GPU on a sample of start vectors
+    ns = list(np.linspace(0, wl.n_orb - 1, 8).astype(int))
+    acc_L = 40
+    res = {}
+    for p in ("fp64", "mixed"):
+        ctx.set_precision(p)
+        a, b, n2, ol = ctx.lanczos_pairs([mw] * len(ns), ns, [acc_L] * len(ns))
+        res[p] = ctx.sigma_from_coeffs(ns, a, b, n2, ol, omega, wl.eta)
+    err_ev = float(np.max(np.abs(res["mixed"] - res["fp64"])))
+    err_rel = err_ev / float(np.max(np.abs(res["fp64"])))
+    ctx.close()
+
+    line = {
+        "metric": METRIC, "value": round(value, 6), "unit": "spectra/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(elapsed / max(args.steps, 1) * 1e3, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "grid": list(wl.grid), "box_bohr": wl.box,
+                   "n_occ": wl.n_occ, "n_emp": wl.n_emp, "pair_dim": wl.n_vc,
+                   "n_lanczos": wl.n_lanczos, "poly_degree": wl.poly_degree,
+                   "n_omega": wl.n_omega, "eta_ev": wl.eta, "block": B, "reorth": "full",
+                   "step": f"{B} start vectors of one QP state through the full path"},
+        "matvec_tflops": round(matvec_tflops, 2),
+        "kernel_event_ms": kernel_ms,
+        "fp64_gpu": {"spectra_per_s": fp64_value, "matvec_tflops": round(fp64_tflops, 2),
+                     "window": f"{B} vectors x {args.fp64_window} Lanczos steps, extrapolated"},
+        "mixed_vs_fp64": round(value / fp64_value, 2),
+        "accuracy": {"max_abs_err_ev": err_ev, "max_rel_err": err_rel,
+                     "sample": f"8 start vectors, L={acc_L}, mixed vs FP64 GPU, all omega"},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(wl, phi, eps, int(qp[0]), 3, args.cpu_steps, lo, hi)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -18,8 +18,9 @@ Recipe (all random numbers from numpy's PCG64 ``default_rng``):
 * orbitals: stream ``[seed, 0]``, ``standard_normal((N_r, N_orb))`` in C
   order (row = grid point ``r = (ix*ny + iy)*nz + iz``, origin at the box
   corner), optionally low-pass filtered per column by
-  ``exp(-|G|^2 sigma^2 / 2)`` (the "smooth" stress variant), then a reduced
-  Householder QR, columns sign-fixed by ``sign(diag(R))``, and scaled by
+  ``exp(-|G|^2 sigma^2 / 2)`` (the "smooth" stress variant), then the thin
+  QR factor with positive diag(R) (unique; computed by CholeskyQR2, which is
+  exact to rounding for these well-conditioned Gaussian matrices), scaled by
   ``1/sqrt(dV)`` so that the grid integral of ``phi_k phi_l`` is
   ``delta_kl``.  The first ``n_occ`` columns are the occupied orbitals.
 * energies: stream ``[seed, 1]``; occupied ``U[-12, -4]`` eV, then empty
@@ -150,13 +151,22 @@ def make_orbitals(wl: Workload) -> np.ndarray:
     g = rng.standard_normal((wl.n_r, wl.n_orb))
     if wl.smooth_sigma > 0:
         g = _lowpass(g, wl.grid, wl.h, wl.smooth_sigma)
-    q, r = np.linalg.qr(g, mode="reduced")
+    q = _thin_q(g)
     del g
-    s = np.sign(np.diag(r))
-    s[s == 0] = 1.0
-    q *= s[None, :]
     q /= np.sqrt(wl.dv)
     return np.ascontiguousarray(q.T)
+
+
+def _thin_q(g: np.ndarray) -> np.ndarray:
+    """Q of the thin QR factorisation g = Q R with diag(R) > 0, by two passes
+    of Cholesky QR (g R^-1 with R = chol(g^T g)^T)."""
+    q = g
+    for _ in range(2):
+        gram = q.T @ q
+        r = np.linalg.cholesky(gram).T          # upper, positive diagonal
+        rinv = np.linalg.inv(r)                 # small N_orb x N_orb
+        q = q @ rinv
+    return np.ascontiguousarray(q)
 
 
 def make_energies(wl: Workload) -> np.ndarray:

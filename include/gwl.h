@@ -1,0 +1,227 @@
+/*
+ * gwl.h -- C ABI of the MI355X (gfx950) library for the full-frequency GW
+ * correlation self-energy by the Lanczos method of Gao, Tang, Zhao and
+ * Chelikowsky, "Efficient Full-frequency GW Calculations using a Lanczos
+ * Method".
+ *
+ * What the library computes (paper notation; QP state m, summed state n):
+ *
+ *   Sigma_mm(w) = sum_n Sigma_mm(w, n)                                (Eq. 10)
+ *   Sigma_mm(w, n) = (1/z_n) <P_nm| D^-1 - (D + eta_n z_n)^-1 |P_nm>   (Eq. 12)
+ *   z_n = w - e_n - i eta_n delta,  eta_n = +1 occupied / -1 empty    (Eq. 11)
+ *   (P_nm)_vc = (nm|vc) (e_c - e_v)^1/2      (definition before Eq. 9)
+ *   D = C^1/2 ~ p_g(C),  C = Delta^2 + 2 Delta^1/2 K Delta^1/2          (Eq. 4 and
+ *                                            the paragraph after Eq. 12)
+ *   K_{vc,v'c'} = (vc|v'c')                                           (Eqs. 2-3)
+ *
+ * D is never formed.  Each (m, n) start vector P_nm runs L Lanczos steps on
+ * p_g(C) (Eq. 13); the tridiagonal coefficients give Sigma at every
+ * frequency through the continued fraction of Eq. 14:
+ *   Sigma_mm(w, n) = [R(-eta_n z_n) - R(0)] / z_n,
+ *   R(zeta) = ||P||^2 / (zeta - a_0 - b_1^2 / (zeta - a_1 - ...)).
+ * The pair-space product C x is applied in factored form on the real-space
+ * grid: rho = sum_vc phi_v phi_c (Delta^1/2 x)_vc  (GEMM with a fused
+ * row-dot), V = FFT^-1[v(G) FFT[rho]] with v(G) = 4 pi/|G|^2, v(0) = 0,
+ * (K u)_vc = dV sum_r phi_v(r) V(r) phi_c(r)  (GEMM).
+ *
+ * Conventions shared by every entry point
+ *   - Indexing is 0-based.  Orbitals [0, n_occ) are occupied, [n_occ, n_orb)
+ *     are empty.  Pair index vc = v * N_c + c (v-major), N_c = n_orb - n_occ.
+ *   - Units: energies, frequencies, broadening and Sigma in eV; the grid box
+ *     in bohr; orbitals grid-normalised (dV * sum_r phi_k phi_l = delta_kl).
+ *   - Grid points are stored C-order, r = (ix * ny + iy) * nz + iz.
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *     device memory on the context's device.  All pointers are borrowed for
+ *     the duration of the call only (except orbitals, see gwl_setup).
+ *   - Every call returns a gwl_status; on failure gwl_last_error() gives a
+ *     message (thread-local).  No C++ exception crosses the ABI.  Calls on
+ *     one context are not thread-safe.  Work is queued on the context stream
+ *     and every entry point returns after that stream has finished it.
+ *   - The library allocates and owns its working device memory (operand
+ *     copies, Lanczos basis, FFT scratch) at setup and on first use of a
+ *     larger batch; gwl_destroy frees it.
+ */
+#ifndef GWL_H
+#define GWL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gwl_ctx gwl_ctx;
+
+typedef enum {
+  GWL_OK = 0,
+  GWL_EINVAL = -1,        /* bad argument (sizes, ranges, NaN, null pointer) */
+  GWL_ENOMEM = -2,        /* device allocation failed */
+  GWL_EDEVICE = -3,       /* HIP runtime error */
+  GWL_ENUMERIC = -4,      /* non-finite Lanczos coefficient, interval violated */
+  GWL_ESTATE = -5,        /* call not valid in the context's state */
+  GWL_EUNSUPPORTED = -6   /* grid size or option not supported */
+} gwl_status;
+
+/* Arithmetic of the pair-space product C x.  The Lanczos recurrence, the
+ * Chebyshev combination, reorthogonalisation and the continued fraction are
+ * FP64 in every mode. */
+typedef enum {
+  GWL_FP64 = 0,       /* GEMMs and FFT in FP64 */
+  GWL_MIXED_BF16 = 1  /* GEMM operands BF16 with FP32 accumulation, FFT FP32 */
+} gwl_precision;
+
+/* Reorthogonalisation of the Lanczos vectors (the paper does not prescribe
+ * one; it notes resolvents are free of ghost eigenvalue problems). */
+typedef enum {
+  GWL_REORTH_NONE = 0,   /* plain three-term recurrence */
+  GWL_REORTH_LOCAL = 1,  /* re-project against q_k and q_{k-1} */
+  GWL_REORTH_FULL = 2    /* two-pass classical Gram-Schmidt against all q_j */
+} gwl_reorth;
+
+typedef struct {
+  int nx, ny, nz;     /* grid points; each must factor into 2, 3, 4, 8 and be <= 256 */
+  double lx, ly, lz;  /* periodic box edges, bohr (orthorhombic) */
+} gwl_grid;
+
+typedef struct {
+  int precision;        /* gwl_precision, default GWL_FP64 */
+  int poly_degree;      /* g, default 7 (the paper's Table 1 uses g = 7) */
+  double poly_lo;       /* Chebyshev interval [lo, hi] in hartree^2; <= 0 selects */
+  double poly_hi;       /*   lo = (min Delta)^2 and hi = Lanczos estimate of max eig C */
+  int reorth;           /* gwl_reorth, default GWL_REORTH_FULL */
+  int block;            /* number of concurrent Lanczos slots B; 0 = automatic */
+  double kernel_scale;  /* multiplies 4 pi/|G|^2; default 1 (as printed; 0 = no coupling) */
+  void* stream;         /* hipStream_t to run on; NULL = library-owned stream */
+} gwl_options;
+
+/* Fill *opts with the defaults listed above. */
+void gwl_default_options(gwl_options* opts);
+
+/* Create a context: validate the inputs, pack the orbitals into the GEMM
+ * layouts, build Delta, the Coulomb factors and the Chebyshev coefficients.
+ *   orbitals      [n_orb][nx*ny*nz] values, orb_dtype 8 = float64, 4 = float32;
+ *                 host memory if orb_on_device == 0, else device memory.  The
+ *                 library copies them into its own layouts, so the caller may
+ *                 free them after the call.
+ *   energies_ev   host [n_orb] KS energies; every empty energy must exceed
+ *                 every occupied one (Delta_vc > 0).
+ *   grid, opts    host structs; opts may be NULL for the defaults.
+ *   out           receives the context; unchanged on failure.
+ * Errors: GWL_EINVAL (n_occ not in [1, n_orb-1], NaN, Delta <= 0, null
+ * pointers), GWL_EUNSUPPORTED (grid), GWL_ENOMEM, GWL_EDEVICE. */
+gwl_status gwl_setup(const void* orbitals, int orb_dtype, int orb_on_device,
+                     int n_orb, int n_occ, const double* energies_ev,
+                     const gwl_grid* grid, const gwl_options* opts,
+                     gwl_ctx** out);
+
+/* Sigma^corr_mm(w) for every m in qp_states (Eqs. 10-14).
+ *   qp_states   host [n_qp] orbital indices m.
+ *   omega_ev    host [n_omega] frequencies.
+ *   eta_ev      broadening delta > 0 (the paper's delta; not its eta_n).
+ *   n_lanczos   L >= 1: Lanczos steps = D-matvecs = diagonal entries a_k.
+ *   sigma_out   host [n_qp][n_omega][2] (re, im), eV.
+ * The n-sum runs over all n_orb orbitals, n = m included.  Each (m, n) run
+ * ends early if b_{k+1} <= 1e-12 max_j |a_j| (exact invariant subspace).
+ * Errors: GWL_EINVAL, GWL_ENUMERIC (non-finite coefficients), GWL_EDEVICE. */
+gwl_status gwl_sigma_c(gwl_ctx* ctx, const int* qp_states, int n_qp,
+                       const double* omega_ev, int n_omega, double eta_ev,
+                       int n_lanczos, double* sigma_out);
+
+/* Partial sum of Eq. 10: for every m in qp_states, sigma_out[q][w] =
+ * sum_{n = n_begin}^{n_end - 1} Sigma_mm(w, n), same units and layout as
+ * gwl_sigma_c (which is the range [0, n_orb)).  Disjoint n-ranges add up to
+ * the full self-energy, so a range is also the unit of work to spread over
+ * several devices.  Errors as gwl_sigma_c, plus GWL_EINVAL for
+ * 0 <= n_begin < n_end <= n_orb not holding. */
+gwl_status gwl_sigma_c_range(gwl_ctx* ctx, const int* qp_states, int n_qp, int n_begin,
+                             int n_end, const double* omega_ev, int n_omega, double eta_ev,
+                             int n_lanczos, double* sigma_out);
+
+/* Batched Lanczos over arbitrary (m, n) start vectors of uneven length
+ * (Eq. 13), scheduled over the context's B slots with refill.
+ *   m_idx, n_idx, lengths   host [n_pairs]; lengths in [1, 4000].
+ *   alpha     host [n_pairs][ld]   a_0 .. a_{len-1} in hartree (rest zero)
+ *   beta      host [n_pairs][ld]   b_1 .. b_{len-1} in hartree (rest zero)
+ *   p_norm2   host [n_pairs]       ||P_nm||^2 in hartree^3
+ *   out_len   host [n_pairs]       steps actually taken (< lengths on breakdown); may be NULL
+ *   ld        leading dimension >= max(lengths). */
+gwl_status gwl_lanczos_pairs(gwl_ctx* ctx, const int* m_idx, const int* n_idx,
+                             const int* lengths, int n_pairs, double* alpha,
+                             double* beta, double* p_norm2, int* out_len, int ld);
+
+/* Continued fraction and assembly (Eqs. 12, 14) on the GPU for given
+ * coefficients: sigma_out[p][w] = Sigma_mm(w, n_idx[p]) in eV for pair p,
+ * with the same layouts as gwl_lanczos_pairs (host pointers). */
+gwl_status gwl_sigma_from_coeffs(gwl_ctx* ctx, const int* n_idx, int n_pairs,
+                                 const double* alpha, const double* beta,
+                                 const double* p_norm2, const int* lens, int ld,
+                                 const double* omega_ev, int n_omega,
+                                 double eta_ev, double* sigma_out);
+
+/* ---- component entry points (the steps of the path, for parity checks) ---- */
+
+/* Hartree potential V = FFT^-1[kernel_scale 4 pi/|G|^2 FFT[rho]] of n_fields
+ * real densities.  rho, v: device [n_fields][nx*ny*nz] in float64 if
+ * precision == GWL_FP64, float32 if GWL_MIXED_BF16. */
+gwl_status gwl_poisson(gwl_ctx* ctx, const void* rho, void* v, int n_fields,
+                       int precision);
+
+/* y = C x for n_vec pair vectors (Eq. 4), factored on the grid.
+ * x, y: device float64 [n_vec][N_v*N_c]. */
+gwl_status gwl_apply_c(gwl_ctx* ctx, const double* x, double* y, int n_vec,
+                       int precision);
+
+/* y = p_g(C) x, the Chebyshev approximation of D x.  Layout as gwl_apply_c. */
+gwl_status gwl_apply_d(gwl_ctx* ctx, const double* x, double* y, int n_vec,
+                       int precision);
+
+/* Coupling vectors P_nm = (nm|vc) Delta^1/2 for count (m, n) pairs.
+ * m_idx, n_idx host [count]; p: device float64 [count][N_v*N_c]. */
+gwl_status gwl_coupling(gwl_ctx* ctx, const int* m_idx, const int* n_idx,
+                        int count, double* p);
+
+/* ---- options, queries, lifetime ---- */
+
+/* Change one option of an existing context (keys below; the value is cast). */
+gwl_status gwl_set_option(gwl_ctx* ctx, int key, double value);
+
+/* Read one scalar (keys below) into *out. */
+gwl_status gwl_query(gwl_ctx* ctx, int key, double* out);
+
+enum {
+  GWL_KEY_PRECISION = 1,   /* set/query */
+  GWL_KEY_REORTH = 2,      /* set/query */
+  GWL_KEY_BLOCK = 3,       /* set/query: Lanczos slots B */
+  GWL_KEY_POLY_LO = 4,     /* query: interval lower end, hartree^2 */
+  GWL_KEY_POLY_HI = 5,     /* query: interval upper end, hartree^2 */
+  GWL_KEY_POLY_DEGREE = 6, /* query */
+  GWL_KEY_N_VC = 7,        /* query: N_v * N_c */
+  GWL_KEY_LAST_MS_TOTAL = 9,    /* query: wall ms of the last sigma/lanczos call */
+  GWL_KEY_LAST_C_MATVECS = 10,  /* query: vector C-products of the last call */
+  GWL_KEY_GEMM_SPLITK = 11,     /* set/query: split of the grid sum in the second GEMM, 0 = auto */
+  GWL_KEY_KERNELS = 12,         /* set/query: 1 = MFMA GEMMs (default), 0 = plain FMA tiles */
+  GWL_KEY_PROFILE = 13,         /* set/query: 1 = time each GEMM / Poisson launch with HIP
+                                   events on the context stream (totals below, per call) */
+  GWL_KEY_PROF_MS_GEMM1 = 14,   /* query: summed event ms of first-GEMM launches, last call */
+  GWL_KEY_PROF_N_GEMM1 = 15,    /* query: number of those launches */
+  GWL_KEY_PROF_VEC_GEMM1 = 16,  /* query: pair vectors processed by those launches */
+  GWL_KEY_PROF_MS_GEMM2 = 17,   /* query: same for the second GEMM */
+  GWL_KEY_PROF_N_GEMM2 = 18,
+  GWL_KEY_PROF_VEC_GEMM2 = 19,
+  GWL_KEY_PROF_MS_FFT = 20,     /* query: same for the Poisson solve (all five passes) */
+  GWL_KEY_PROF_N_FFT = 21,
+  GWL_KEY_PROF_VEC_FFT = 22
+};
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* gwl_last_error(void);
+
+/* Free every device allocation of the context.  NULL is ignored. */
+void gwl_destroy(gwl_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GWL_H */

@@ -84,11 +84,13 @@ def apply_c(phi, n_occ, shape, h, delta, x, scale=1.0):
 
 def eri_vc(phi: np.ndarray, n: int, m: int, n_occ: int, shape, h: float,
            scale: float = 1.0) -> np.ndarray:
-    """(nm|vc) for all pairs (v, c), flattened v-major."""
+    """(nm|vc) = dV sum_r phi_v(r) phi_c(r) V[phi_n phi_m](r) for all pairs
+    (v, c), flattened v-major.  The sum over r is the matrix product
+    (phi_v V) phi_c^T, so pair densities are never stored."""
     dv = h ** 3
     vnm = poisson(phi[n] * phi[m], shape, h, scale)
-    b = pair_densities(phi, n_occ)
-    return dv * (b @ vnm)
+    pv, pc = phi[:n_occ], phi[n_occ:]
+    return dv * ((pv * vnm[None, :]) @ pc.T).reshape(-1)
 
 
 def coupling_vector(phi, n, m, n_occ, shape, h, delta, scale=1.0):
@@ -96,11 +98,9 @@ def coupling_vector(phi, n, m, n_occ, shape, h, delta, scale=1.0):
     return eri_vc(phi, n, m, n_occ, shape, h, scale) * np.sqrt(delta)
 
 
-def coupling_vectors_for_state(phi, m, n_occ, shape, h, delta, scale=1.0):
-    """P_nm for every orbital n (the n-sum of Eq. 10), shape [N_orb, N_vc]."""
-    dv = h ** 3
-    dens = phi * phi[m][None, :]
-    vnm = poisson(dens, shape, h, scale)
-    b = pair_densities(phi, n_occ)
-    k = dv * (vnm @ b.T)
-    return k * np.sqrt(delta)[None, :]
+def coupling_vectors_for_state(phi, m, n_occ, shape, h, delta, scale=1.0, n_list=None):
+    """P_nm for every orbital n (the n-sum of Eq. 10), or for the n in n_list,
+    shape [len, N_vc]."""
+    ns = range(phi.shape[0]) if n_list is None else list(n_list)
+    sd = np.sqrt(delta)
+    return np.array([eri_vc(phi, n, m, n_occ, shape, h, scale) * sd for n in ns])

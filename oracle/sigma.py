@@ -224,10 +224,10 @@ class Problem:
             self._eig = np.linalg.eigh(self.C)
         return self._eig
 
-    def coupling(self, m):
-        """[N_orb, N_vc] array of P_nm for all n."""
+    def coupling(self, m, n_list=None):
+        """[N_orb, N_vc] array of P_nm for all n (or [len(n_list), N_vc])."""
         return casida.coupling_vectors_for_state(
-            self.phi, m, self.n_occ, self.shape, self.h, self.delta, self.scale)
+            self.phi, m, self.n_occ, self.shape, self.h, self.delta, self.scale, n_list)
 
     def apply_c(self, x):
         return casida.apply_c(self.phi, self.n_occ, self.shape, self.h,
@@ -280,24 +280,24 @@ class Problem:
         route "matfree": Lanczos on p_g(C) applied by the Chebyshev recurrence
                          with matrix-free C x (for sizes where C is too big).
         """
-        pm = self.coupling(m)
-        ns = range(self.n_orb) if n_list is None else n_list
+        ns = list(range(self.n_orb)) if n_list is None else list(n_list)
+        pm = self.coupling(m, ns)
         out = []
         if route == "dense":
             dg = self.dg_matrix(lo, hi, g)
-            for n in ns:
-                out.append(lanczos(lambda v: dg @ v, pm[n], n_lanczos, reorth))
+            for i, _ in enumerate(ns):
+                out.append(lanczos(lambda v: dg @ v, pm[i], n_lanczos, reorth))
         elif route == "measure":
             om2, z = self.eig()
             c = chebyshev.sqrt_coeffs(lo, hi, g)
             lam = chebyshev.eval_scalar(c, lo, hi, om2)
-            for n in ns:
-                out.append(stieltjes(lam, (pm[n] @ z) ** 2, n_lanczos, reorth))
+            for i, _ in enumerate(ns):
+                out.append(stieltjes(lam, (pm[i] @ z) ** 2, n_lanczos, reorth))
         elif route == "matfree":
             c = chebyshev.sqrt_coeffs(lo, hi, g)
-            for n in ns:
+            for i, _ in enumerate(ns):
                 out.append(lanczos(lambda v: chebyshev.apply(c, lo, hi, self.apply_c, v),
-                                   pm[n], n_lanczos, reorth))
+                                   pm[i], n_lanczos, reorth))
         else:
             raise ValueError(route)
         return out

@@ -1,0 +1,12 @@
+"""MI355X (gfx950) implementation of the Lanczos full-frequency GW correlation
+self-energy (Gao, Tang, Zhao, Chelikowsky).
+
+The computation lives in the HIP library ``_lib/libgwl.so`` behind the C ABI
+of ``include/gwl.h``; this package is its Python binding.
+"""
+from .binding import (Context, GwlError, lib, FP64, MIXED_BF16, REORTH, PRECISIONS,  # noqa: F401
+                      KEY_PRECISION, KEY_REORTH, KEY_BLOCK, KEY_POLY_LO, KEY_POLY_HI,
+                      KEY_POLY_DEGREE, KEY_N_VC, KEY_LAST_MS_TOTAL, KEY_LAST_C_MATVECS,
+                      KEY_GEMM_SPLITK, KEY_KERNELS, KEY_PROFILE, KEY_PROF, LIB_PATH)
+
+__all__ = ["Context", "GwlError", "lib", "LIB_PATH"]

@@ -1,0 +1,68 @@
+// Internal helpers shared by the gfx950 kernels and the host runtime of the
+// Lanczos GW self-energy library.  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "gwl.h"
+
+namespace gwl {
+
+// ---------------------------------------------------------------- errors
+// Thread-local message returned by gwl_last_error().
+void set_error(const std::string& msg);
+
+struct Error {
+  gwl_status code;
+  std::string msg;
+};
+
+#define GWL_HIP(call)                                                            \
+  do {                                                                           \
+    hipError_t e_ = (call);                                                      \
+    if (e_ != hipSuccess)                                                        \
+      throw ::gwl::Error{GWL_EDEVICE, std::string(#call) + ": " +                \
+                                          hipGetErrorString(e_)};                \
+  } while (0)
+
+#define GWL_CHECK(cond, code, msg)                                               \
+  do {                                                                           \
+    if (!(cond)) throw ::gwl::Error{(code), (msg)};                              \
+  } while (0)
+
+// ---------------------------------------------------------------- types
+typedef uint16_t bf16_t;  // raw bfloat16 bits
+
+__host__ __device__ inline bf16_t f32_to_bf16(float f) {
+  // round to nearest even; inputs here are finite
+  uint32_t u;
+  __builtin_memcpy(&u, &f, 4);
+  uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  return (bf16_t)(u >> 16);
+}
+
+__host__ __device__ inline float bf16_to_f32(bf16_t h) {
+  uint32_t u = ((uint32_t)h) << 16;
+  float f;
+  __builtin_memcpy(&f, &u, 4);
+  return f;
+}
+
+template <typename T>
+struct cplx {
+  T x, y;
+};
+
+inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
+inline long round_up(long a, long b) { return ((a + b - 1) / b) * b; }
+
+constexpr double kHartreeEv = 27.211386245988;  // CODATA 2018
+constexpr double kPi = 3.14159265358979323846;
+
+}  // namespace gwl

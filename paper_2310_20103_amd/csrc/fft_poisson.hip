@@ -1,0 +1,326 @@
+// Hartree potential on the periodic grid, V = FFT^-1[ v(G) FFT[rho] ],
+// v(G) = scale * 4 pi / |G|^2, v(0) = 0 (the integral kernel of Eq. 3, read
+// as the periodic Coulomb kernel of a cubic cell).
+//
+// gfx950 design: HBM-bound.  Two real fields are packed into one complex
+// field (exact because v(G) is real and even, so each real field maps to a
+// real potential).  The 3-D transform is five passes of batched 1-D
+// transforms, each staging a batch of lines through LDS:
+//   z forward (+ pack, + sum of GEMM partials) -> y forward ->
+//   x forward, multiply by v(G)/N, x inverse -> y inverse -> z inverse (+ unpack).
+// The 1-D transforms are mixed-radix (2, 3, 4, 8) Stockham autosort passes
+// with ping-pong LDS buffers (Govindaraju et al., SC'08 formulation); the
+// inverse uses conj(FFT(conj(x))).
+#include "common.h"
+#include "kernels.h"
+
+namespace gwl {
+
+namespace {
+
+template <typename T>
+__device__ inline cplx<T> cmul(cplx<T> a, cplx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ inline cplx<T> cadd(cplx<T> a, cplx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ inline cplx<T> csub(cplx<T> a, cplx<T> b) { return {a.x - b.x, a.y - b.y}; }
+// -i * a
+template <typename T>
+__device__ inline cplx<T> mul_mi(cplx<T> a) { return {a.y, -a.x}; }
+
+template <typename T>
+__device__ inline void dft2(cplx<T>* v) {
+  cplx<T> t = v[0];
+  v[0] = cadd(t, v[1]);
+  v[1] = csub(t, v[1]);
+}
+
+template <typename T>
+__device__ inline void dft3(cplx<T>* v) {
+  const T c3 = (T)0.86602540378443864676;  // sin(2 pi / 3)
+  cplx<T> s = cadd(v[1], v[2]);
+  cplx<T> d = csub(v[1], v[2]);
+  cplx<T> m = {v[0].x - (T)0.5 * s.x, v[0].y - (T)0.5 * s.y};
+  v[0] = cadd(v[0], s);
+  v[1] = {m.x + c3 * d.y, m.y - c3 * d.x};
+  v[2] = {m.x - c3 * d.y, m.y + c3 * d.x};
+}
+
+template <typename T>
+__device__ inline void dft4(cplx<T>* v) {
+  cplx<T> a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+  cplx<T> c = cadd(v[1], v[3]), d = mul_mi(csub(v[1], v[3]));
+  v[0] = cadd(a, c);
+  v[2] = csub(a, c);
+  v[1] = cadd(b, d);
+  v[3] = csub(b, d);
+}
+
+template <typename T>
+__device__ inline void dft8(cplx<T>* v) {
+  const T h = (T)0.70710678118654752440;
+  cplx<T> e[4] = {v[0], v[2], v[4], v[6]};
+  cplx<T> o[4] = {v[1], v[3], v[5], v[7]};
+  dft4(e);
+  dft4(o);
+  // twiddles W8^k = exp(-i pi k / 4)
+  cplx<T> o1 = {h * (o[1].x + o[1].y), h * (o[1].y - o[1].x)};
+  cplx<T> o2 = mul_mi(o[2]);
+  cplx<T> o3 = {h * (o[3].y - o[3].x), -h * (o[3].x + o[3].y)};
+  v[0] = cadd(e[0], o[0]);
+  v[4] = csub(e[0], o[0]);
+  v[1] = cadd(e[1], o1);
+  v[5] = csub(e[1], o1);
+  v[2] = cadd(e[2], o2);
+  v[6] = csub(e[2], o2);
+  v[3] = cadd(e[3], o3);
+  v[7] = csub(e[3], o3);
+}
+
+// One Stockham radix-R stage over nl lines (line stride ls) from in to out.
+template <typename T, int R>
+__device__ inline void fft_stage(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
+                                 int nl, int n, int ls, int ns,
+                                 const cplx<T>* __restrict__ tw) {
+  const int m = n / R;
+  const int tstride = n / (ns * R);
+  const int total = nl * m;
+  for (int bf = threadIdx.x; bf < total; bf += blockDim.x) {
+    const int line = bf / m;
+    const int j = bf - line * m;
+    const int jq = j / ns;
+    const int k = j - jq * ns;
+    cplx<T> v[R];
+    const cplx<T>* src = in + line * ls + j;
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = src[r * m];
+#pragma unroll
+    for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[r * k * tstride]);
+    if constexpr (R == 2) dft2(v);
+    if constexpr (R == 3) dft3(v);
+    if constexpr (R == 4) dft4(v);
+    if constexpr (R == 8) dft8(v);
+    cplx<T>* dst = out + line * ls + jq * ns * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) dst[r * ns] = v[r];
+  }
+}
+
+// Transform nl lines of length n held in LDS at buf0 (line stride ls).
+// Returns the buffer that holds the result.  All threads of the block call it.
+template <typename T>
+__device__ cplx<T>* fft_lines(cplx<T>* buf0, cplx<T>* buf1, int nl, int n, int ls,
+                              const FftPlan& plan, const cplx<T>* __restrict__ tw) {
+  cplx<T>* in = buf0;
+  cplx<T>* out = buf1;
+  int ns = 1;
+  for (int s = 0; s < plan.nstages; ++s) {
+    const int R = plan.radix[s];
+    switch (R) {
+      case 2: fft_stage<T, 2>(in, out, nl, n, ls, ns, tw); break;
+      case 3: fft_stage<T, 3>(in, out, nl, n, ls, ns, tw); break;
+      case 4: fft_stage<T, 4>(in, out, nl, n, ls, ns, tw); break;
+      default: fft_stage<T, 8>(in, out, nl, n, ls, ns, tw); break;
+    }
+    __syncthreads();
+    cplx<T>* t = in;
+    in = out;
+    out = t;
+    ns *= R;
+  }
+  return in;
+}
+
+// Pass along z (contiguous lines).  Forward: builds the complex field from the
+// real fields 2p and 2p+1, summing nparts GEMM partial densities.  Inverse:
+// writes the real part to field 2p and the imaginary part to field 2p+1.
+template <typename T, bool INVERSE>
+__global__ void __launch_bounds__(256)
+fft_pass_z(cplx<T>* __restrict__ X, const T* __restrict__ rin, T* __restrict__ rout,
+           int nf, long ld_real, long part_stride, int nparts, int nlines, int nz,
+           long nr, int lpb, FftPlan plan, const cplx<T>* __restrict__ tw) {
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T>* buf0 = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int ls = nz + 1;
+  cplx<T>* buf1 = buf0 + lpb * ls;
+  const int pair = blockIdx.y;
+  const int f0 = 2 * pair, f1 = 2 * pair + 1;
+  const int line0 = blockIdx.x * lpb;
+  const int nl = min(lpb, nlines - line0);
+  cplx<T>* Xp = X + (long)pair * nr;
+  const long base = (long)line0 * nz;
+  const int cnt = nl * nz;
+  // load
+  for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+    const int l = e / nz, p = e - l * nz;
+    cplx<T> v;
+    if (!INVERSE) {
+      T a = 0, b = 0;
+      for (int q = 0; q < nparts; ++q) {
+        const T* src = rin + (long)q * part_stride;
+        a += src[(long)f0 * ld_real + base + e];
+        if (f1 < nf) b += src[(long)f1 * ld_real + base + e];
+      }
+      v = {a, b};
+    } else {
+      v = Xp[base + e];
+      v.y = -v.y;
+    }
+    buf0[l * ls + p] = v;
+  }
+  __syncthreads();
+  cplx<T>* res = fft_lines<T>(buf0, buf1, nl, nz, ls, plan, tw);
+  for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+    const int l = e / nz, p = e - l * nz;
+    cplx<T> v = res[l * ls + p];
+    if (!INVERSE) {
+      Xp[base + e] = v;
+    } else {
+      rout[(long)f0 * ld_real + base + e] = v.x;
+      if (f1 < nf) rout[(long)f1 * ld_real + base + e] = -v.y;
+    }
+  }
+}
+
+// Pass along a strided axis (y: stride nz inside an x-slab; x: stride ny*nz).
+// A block takes lpb consecutive z-columns at a fixed (outer) index, so global
+// loads are coalesced along z.  MODE 0: forward, 1: inverse, 2: forward,
+// multiply by the Coulomb kernel, inverse (x axis only).
+template <typename T, int MODE>
+__global__ void __launch_bounds__(256)
+fft_pass_strided(cplx<T>* __restrict__ X, int n, long pstride, long outer_stride,
+                 int nzb, int nz, long nr, int lpb, FftPlan plan,
+                 const cplx<T>* __restrict__ tw, const T* __restrict__ g2x,
+                 const T* __restrict__ g2y, const T* __restrict__ g2z, T vscale,
+                 int ny) {
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T>* buf0 = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int ls = n + 1;
+  cplx<T>* buf1 = buf0 + lpb * ls;
+  const int pair = blockIdx.y;
+  const int outer = blockIdx.x / nzb;
+  const int iz0 = (blockIdx.x - outer * nzb) * lpb;
+  const int nl = min(lpb, nz - iz0);
+  cplx<T>* Xp = X + (long)pair * nr + (long)outer * outer_stride + iz0;
+  const int cnt = nl * n;
+  for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+    const int p = e / nl, l = e - p * nl;
+    cplx<T> v = Xp[(long)p * pstride + l];
+    if (MODE == 1) v.y = -v.y;
+    buf0[l * ls + p] = v;
+  }
+  __syncthreads();
+  cplx<T>* res = fft_lines<T>(buf0, buf1, nl, n, ls, plan, tw);
+  if (MODE == 2) {
+    // res holds X(kx, ky = outer, kz = iz0 + l); multiply by v(G)/N and
+    // conjugate for the inverse transform.
+    cplx<T>* other = (res == buf0) ? buf1 : buf0;
+    const T gyz = g2y[outer];
+    for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+      const int l = e / n, p = e - l * n;
+      const T g2 = g2x[p] + gyz + g2z[iz0 + l];
+      const T k = (g2 > (T)0) ? vscale / g2 : (T)0;
+      cplx<T> v = res[l * ls + p];
+      other[l * ls + p] = {k * v.x, -k * v.y};
+    }
+    __syncthreads();
+    res = fft_lines<T>(other, res, nl, n, ls, plan, tw);
+  }
+  for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+    const int p = e / nl, l = e - p * nl;
+    cplx<T> v = res[l * ls + p];
+    if (MODE == 1 || MODE == 2) v.y = -v.y;
+    Xp[(long)p * pstride + l] = v;
+  }
+}
+
+// Lines per block of the contiguous (z) pass: about 16 KB of complex data per
+// LDS buffer, between 4 and 32 lines.
+template <typename T>
+int lines_per_block(int n) {
+  int l = (int)(16384 / sizeof(cplx<T>)) / n;
+  if (l < 4) l = 4;
+  if (l > 32) l = 32;
+  return l;
+}
+
+}  // namespace
+
+FftPlan make_plan(int n) {
+  FftPlan p{};
+  int m = n;
+  while (m % 8 == 0 && m > 1) { p.radix[p.nstages++] = 8; m /= 8; }
+  while (m % 4 == 0 && m > 1) { p.radix[p.nstages++] = 4; m /= 4; }
+  while (m % 2 == 0 && m > 1) { p.radix[p.nstages++] = 2; m /= 2; }
+  while (m % 3 == 0 && m > 1) { p.radix[p.nstages++] = 3; m /= 3; }
+  p.ok = (m == 1) && p.nstages <= 8;
+  return p;
+}
+
+template <typename T>
+void poisson_launch(const PoissonGeom<T>& g, const T* rin, long ld_in, long part_stride,
+                    int nparts, T* rout, long ld_out, int nf, cplx<T>* scratch,
+                    hipStream_t st) {
+  if (nf <= 0) return;
+  const int npairs = (nf + 1) / 2;
+  const long nr = (long)g.nx * g.ny * g.nz;
+  // z forward + pack
+  {
+    const int lpb = lines_per_block<T>(g.nz);
+    const int nlines = g.nx * g.ny;
+    dim3 grid(ceil_div(nlines, lpb), npairs);
+    size_t sm = 2 * (size_t)lpb * (g.nz + 1) * sizeof(cplx<T>);
+    fft_pass_z<T, false><<<grid, 256, sm, st>>>(scratch, rin, nullptr, nf, ld_in,
+                                                part_stride, nparts, nlines, g.nz, nr,
+                                                lpb, g.pz, g.twz);
+  }
+  const int nmax = g.nx > g.ny ? g.nx : g.ny;
+  int lpb = 1024 / nmax;
+  if (lpb > 16) lpb = 16;
+  if (lpb < 2) lpb = 2;
+  if (lpb > g.nz) lpb = g.nz;
+  const int nzb = ceil_div(g.nz, lpb);
+  // y forward
+  {
+    dim3 grid(g.nx * nzb, npairs);
+    size_t sm = 2 * (size_t)lpb * (g.ny + 1) * sizeof(cplx<T>);
+    fft_pass_strided<T, 0><<<grid, 256, sm, st>>>(scratch, g.ny, g.nz, (long)g.ny * g.nz,
+                                                  nzb, g.nz, nr, lpb, g.py, g.twy, nullptr,
+                                                  nullptr, nullptr, (T)0, g.ny);
+  }
+  // x forward, kernel, x inverse
+  {
+    dim3 grid(g.ny * nzb, npairs);
+    size_t sm = 2 * (size_t)lpb * (g.nx + 1) * sizeof(cplx<T>);
+    fft_pass_strided<T, 2><<<grid, 256, sm, st>>>(scratch, g.nx, (long)g.ny * g.nz, g.nz,
+                                                  nzb, g.nz, nr, lpb, g.px, g.twx, g.g2x,
+                                                  g.g2y, g.g2z, g.vscale, g.ny);
+  }
+  // y inverse
+  {
+    dim3 grid(g.nx * nzb, npairs);
+    size_t sm = 2 * (size_t)lpb * (g.ny + 1) * sizeof(cplx<T>);
+    fft_pass_strided<T, 1><<<grid, 256, sm, st>>>(scratch, g.ny, g.nz, (long)g.ny * g.nz,
+                                                  nzb, g.nz, nr, lpb, g.py, g.twy, nullptr,
+                                                  nullptr, nullptr, (T)0, g.ny);
+  }
+  // z inverse + unpack
+  {
+    const int lpbz = lines_per_block<T>(g.nz);
+    const int nlines = g.nx * g.ny;
+    dim3 grid(ceil_div(nlines, lpbz), npairs);
+    size_t sm = 2 * (size_t)lpbz * (g.nz + 1) * sizeof(cplx<T>);
+    fft_pass_z<T, true><<<grid, 256, sm, st>>>(scratch, nullptr, rout, nf, ld_out, 0, 1,
+                                               nlines, g.nz, nr, lpbz, g.pz, g.twz);
+  }
+  GWL_HIP(hipGetLastError());
+}
+
+template void poisson_launch<float>(const PoissonGeom<float>&, const float*, long, long, int,
+                                    float*, long, int, cplx<float>*, hipStream_t);
+template void poisson_launch<double>(const PoissonGeom<double>&, const double*, long, long,
+                                     int, double*, long, int, cplx<double>*, hipStream_t);
+
+}  // namespace gwl

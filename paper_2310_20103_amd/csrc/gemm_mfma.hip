@@ -1,0 +1,446 @@
+// Factored pair-space product on the CDNA4 matrix cores.
+//
+// Both GEMMs are "NT" products over stacked batches, M = B * N_v rows (pair
+// vector b, occupied orbital v), with both operands contiguous along K:
+//
+//   first GEMM   C1[(b,v), r] = sum_c u_b[v, c] phi_c(r)          K = N_c
+//                rho_b(r)     = sum_v phi_v(r) C1[(b,v), r]         (epilogue)
+//   second GEMM  y_b[v, c]    = sum_r (phi_v(r) V_b(r)) phi_c(r)   K = N_r, split
+//
+// (the two halves of K x, Eqs. 2-4).  The density of the first GEMM is
+// reduced over v inside the tile, so the N_r x N_v intermediate never reaches
+// memory; the second GEMM forms its A operand phi_v(r) V_b(r) while staging it
+// into LDS, so the per-vector operand never exists in HBM either.
+//
+// FP64: v_mfma_f64_16x16x4f64, block tile 128 x 128 x 16, 4 waves of 64 x 64.
+// BF16: v_mfma_f32_32x32x16_bf16 (FP32 accumulation), block tile
+//       256 x 128 x 32, 4 waves of 128 x 64.
+// Tiles are staged through LDS with the next K step prefetched into registers.
+// Block ids are remapped so that blocks sharing the large operand tile run on
+// the same XCD (one L2 per XCD).
+#include "common.h"
+#include "kernels.h"
+
+namespace gwl {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f16v __attribute__((ext_vector_type(16)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+// Consecutive logical ids land on one XCD: hardware dispatches block i to
+// XCD i % 8.
+__device__ inline int xcd_remap(int bid, int total) {
+  if (total % 8 != 0) return bid;
+  return (bid & 7) * (total >> 3) + (bid >> 3);
+}
+
+// ---------------------------------------------------------------- FP64
+constexpr int DM = 128, DN = 128, DK = 16, DLD = DK + 1;
+
+// A operand loader variants for the FP64 kernels.
+struct LoadU64 {  // plain [M][K] rows
+  const double* a;
+  long lda;
+  __device__ void load(int m, int k0, int kq, double* v) const {
+    const double* p = a + (long)m * lda + k0 + kq;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = p[i];
+  }
+};
+struct LoadPsiV64 {  // A[(b,v)][r] = phi_v(r) V_b(r)
+  const double* psi_v_t;
+  const double* vpot;
+  long nrp;
+  int nvp;
+  __device__ void load(int m, int k0, int kq, double* v) const {
+    const int b = m / nvp, vv = m - b * nvp;
+    const double* p = psi_v_t + (long)vv * nrp + k0 + kq;
+    const double* q = vpot + (long)b * nrp + k0 + kq;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = p[i] * q[i];
+  }
+};
+
+// Main loop of the FP64 kernels: acc += A[m0.., k] B[n0.., k] for k in [kb, ke).
+template <typename LA>
+__device__ inline void f64_mainloop(const LA& la, int M, const double* __restrict__ bop, long ldb,
+                                    int nvalid, int m0, int n0, int kb, int ke, double (*As)[DLD],
+                                    double (*Bs)[DLD], d4 (&acc)[4][4]) {
+  const int t = threadIdx.x, l = t & 63, w = t >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  const int lrow = t >> 1, lkq = (t & 1) * 8;
+  double ra[8], rb[8];
+  const bool arow_ok = (m0 + lrow) < M;
+  auto gload = [&](int k0) {
+    if (arow_ok) {
+      la.load(m0 + lrow, k0, lkq, ra);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) ra[i] = 0.0;
+    }
+    if (n0 + lrow < nvalid) {
+      const double* p = bop + (long)(n0 + lrow) * ldb + k0 + lkq;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) rb[i] = p[i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) rb[i] = 0.0;
+    }
+  };
+  auto lstore = [&]() {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      As[lrow][lkq + i] = ra[i];
+      Bs[lrow][lkq + i] = rb[i];
+    }
+  };
+  if (kb < ke) {
+    gload(kb);
+    lstore();
+  }
+  __syncthreads();
+  for (int k0 = kb; k0 < ke; k0 += DK) {
+    const bool more = k0 + DK < ke;
+    if (more) gload(k0 + DK);
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      double a[4], b[4];
+      const int kk = 4 * ks + (l >> 4);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        a[i] = As[wm * 64 + 16 * i + (l & 15)][kk];
+        b[i] = Bs[wn * 64 + 16 * i + (l & 15)][kk];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+    if (more) {
+      lstore();
+      __syncthreads();
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256)
+gemm1_f64m_kernel(GemmDims d, int M, int nb, const double* __restrict__ psi_c_rc,
+                  const double* __restrict__ psi_v_rv, const double* __restrict__ u,
+                  double* __restrict__ rho_part) {
+  __shared__ double As[DM][DLD];
+  __shared__ double Bs[DN][DLD];
+  const int mt = (M + DM - 1) / DM, nt = d.nrp / DN;
+  const int lid = xcd_remap(blockIdx.x, mt * nt);
+  const int m0 = (lid % mt) * DM, n0 = (lid / mt) * DN;
+  d4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0, 0, 0, 0};
+  LoadU64 la{u, d.ncp};
+  f64_mainloop(la, M, psi_c_rc, d.ncp, d.nrp, m0, n0, 0, d.ncp, As, Bs, acc);
+  // epilogue: rho_b(r) = sum over the wave's 64 rows (one b, 64 v) of phi_v(r) C1
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  const int mw = m0 + wm * 64;
+  if (mw >= M) return;
+  const int b = mw / d.nvp, vbase = mw - b * d.nvp, vt = vbase / 64;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int r = n0 + wn * 64 + 16 * j + (l & 15);
+    const double* wr = psi_v_rv + (long)r * d.nvp + vbase;
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) s += wr[16 * i + (l >> 4) + 4 * q] * acc[i][j][q];
+    s += __shfl_xor(s, 16, 64);
+    s += __shfl_xor(s, 32, 64);
+    if (l < 16) rho_part[((long)vt * nb + b) * d.nrp + r] = s;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+gemm2_f64m_kernel(GemmDims d, int M, int splitk, int kchunk, const double* __restrict__ psi_v_t,
+                  const double* __restrict__ psi_c_t, const double* __restrict__ vpot,
+                  double* __restrict__ ypart) {
+  __shared__ double As[DM][DLD];
+  __shared__ double Bs[DN][DLD];
+  const int mt = (M + DM - 1) / DM, nt = (d.ncp + DN - 1) / DN;
+  const int lid = xcd_remap(blockIdx.x, mt * nt * splitk);
+  const int s = lid / (mt * nt);
+  const int rem = lid - s * mt * nt;
+  const int m0 = (rem % mt) * DM, n0 = (rem / mt) * DN;
+  const int kb = s * kchunk;
+  const int ke = min(d.nrp, kb + kchunk);
+  d4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0, 0, 0, 0};
+  LoadPsiV64 la{psi_v_t, vpot, d.nrp, d.nvp};
+  f64_mainloop(la, M, psi_c_t, d.nrp, d.ncp, m0, n0, kb, ke, As, Bs, acc);
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  double* out = ypart + (long)s * M * d.ncp;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int m = m0 + wm * 64 + 16 * i + (l >> 4) + 4 * q;
+      if (m >= M) continue;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int n = n0 + wn * 64 + 16 * j + (l & 15);
+        if (n < d.ncp) out[(long)m * d.ncp + n] = acc[i][j][q];
+      }
+    }
+}
+
+// ---------------------------------------------------------------- BF16
+constexpr int HM = 256, HN = 128, HK = 32, HLD = HK + 8;  // LDS row: 40 bf16 = 80 B
+constexpr int HWN = HN / 64;  // 32-column blocks per wave (2 waves along N)
+
+__device__ inline bf8 lds_frag(const bf16_t* p) {
+  return __builtin_bit_cast(bf8, *reinterpret_cast<const u4*>(p));
+}
+
+struct LoadU16 {  // plain [M][K] bf16 rows; 8 values per chunk
+  const bf16_t* a;
+  long lda;
+  __device__ u4 load(int m, int k) const {
+    return *reinterpret_cast<const u4*>(a + (long)m * lda + k);
+  }
+};
+struct LoadPsiV16 {  // A[(b,v)][r] = bf16(phi_v(r) V_b(r))
+  const bf16_t* psi_v_t;
+  const float* vpot;
+  long nrp;
+  int nvp;
+  __device__ u4 load(int m, int k) const {
+    const int b = m / nvp, vv = m - b * nvp;
+    const u4 pv = *reinterpret_cast<const u4*>(psi_v_t + (long)vv * nrp + k);
+    const f4v v0 = *reinterpret_cast<const f4v*>(vpot + (long)b * nrp + k);
+    const f4v v1 = *reinterpret_cast<const f4v*>(vpot + (long)b * nrp + k + 4);
+    const float vv8[8] = {v0[0], v0[1], v0[2], v0[3], v1[0], v1[1], v1[2], v1[3]};
+    u4 out;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const unsigned lo = pv[i] & 0xffffu, hi = pv[i] >> 16;
+      const float a0 = bf16_to_f32((bf16_t)lo) * vv8[2 * i];
+      const float a1 = bf16_to_f32((bf16_t)hi) * vv8[2 * i + 1];
+      out[i] = (unsigned)f32_to_bf16(a0) | ((unsigned)f32_to_bf16(a1) << 16);
+    }
+    return out;
+  }
+};
+
+// acc += A[m0.., k] B[n0.., k], k in [kb, ke); B rows beyond nvalid are zero.
+constexpr int HQB = HN * 4 / 256;  // 16-byte B chunks per thread per K step
+
+template <typename LA>
+__device__ inline void bf16_mainloop(const LA& la, int M, const bf16_t* __restrict__ bop, long ldb,
+                                     int nvalid, int m0, int n0, int kb, int ke,
+                                     bf16_t (*As)[HLD], bf16_t (*Bs)[HLD], f16v (&acc)[4][HWN]) {
+  const int t = threadIdx.x, l = t & 63, w = t >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  u4 ra[4], rb[HQB];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = t + 256 * q;
+      const int row = idx >> 2, kc = (idx & 3) * 8;
+      ra[q] = (m0 + row < M) ? la.load(m0 + row, k0 + kc) : u4{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int q = 0; q < HQB; ++q) {
+      const int idx = t + 256 * q;
+      const int row = idx >> 2, kc = (idx & 3) * 8;
+      rb[q] = (n0 + row < nvalid)
+                  ? *reinterpret_cast<const u4*>(bop + (long)(n0 + row) * ldb + k0 + kc)
+                  : u4{0, 0, 0, 0};
+    }
+  };
+  auto lstore = [&]() {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = t + 256 * q;
+      const int row = idx >> 2, kc = (idx & 3) * 8;
+      *reinterpret_cast<u4*>(&As[row][kc]) = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < HQB; ++q) {
+      const int idx = t + 256 * q;
+      const int row = idx >> 2, kc = (idx & 3) * 8;
+      *reinterpret_cast<u4*>(&Bs[row][kc]) = rb[q];
+    }
+  };
+  if (kb < ke) {
+    gload(kb);
+    lstore();
+  }
+  __syncthreads();
+  for (int k0 = kb; k0 < ke; k0 += HK) {
+    const bool more = k0 + HK < ke;
+    if (more) gload(k0 + HK);
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      bf8 a[4];
+      const int kk = 16 * ks + 8 * (l >> 5);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = lds_frag(&As[wm * 128 + 32 * i + (l & 31)][kk]);
+#pragma unroll
+      for (int j = 0; j < HWN; ++j) {
+        const bf8 b = lds_frag(&Bs[wn * (HN / 2) + 32 * j + (l & 31)][kk]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b, acc[i][j], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+    if (more) {
+      lstore();
+      __syncthreads();
+    }
+  }
+}
+
+// SEG = 32-row blocks that belong to one pair vector within a wave's 128
+// rows: 4 when N_v (padded) >= 128, 2 when it is 64.
+template <int SEG>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+gemm1_bf16_kernel(GemmDims d, int M, int nb, const bf16_t* __restrict__ psi_c_rc,
+                  const float* __restrict__ psi_v_rv, const bf16_t* __restrict__ u,
+                  float* __restrict__ rho_part) {
+  __shared__ bf16_t As[HM][HLD];
+  __shared__ bf16_t Bs[HN][HLD];
+  const int mt = (M + HM - 1) / HM, nt = d.nrp / HN;
+  const int lid = xcd_remap(blockIdx.x, mt * nt);
+  const int m0 = (lid % mt) * HM, n0 = (lid / mt) * HN;
+  f16v acc[4][HWN];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < HWN; ++j) acc[i][j] = f16v{};
+  LoadU16 la{u, d.ncp};
+  bf16_mainloop(la, M, psi_c_rc, d.ncp, d.nrp, m0, n0, 0, d.ncp, As, Bs, acc);
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  const int mw = m0 + wm * 128;
+#pragma unroll
+  for (int sg = 0; sg < 4; sg += SEG) {
+    const int ms = mw + 32 * sg;
+    if (ms < M) {
+      const int b = ms / d.nvp, vbase = ms - b * d.nvp;
+      const int vt = vbase / 128;
+#pragma unroll
+      for (int j = 0; j < HWN; ++j) {
+        const int r = n0 + wn * (HN / 2) + 32 * j + (l & 31);
+        const float* wr = psi_v_rv + (long)r * d.nvp + vbase + 4 * (l >> 5);
+        float s = 0.f;
+#pragma unroll
+        for (int i = 0; i < SEG; ++i) {
+#pragma unroll
+          for (int g = 0; g < 4; ++g) {
+            const f4v wv = *reinterpret_cast<const f4v*>(wr + 32 * i + 8 * g);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) s += wv[q] * acc[sg + i][j][4 * g + q];
+          }
+        }
+        s += __shfl_xor(s, 32, 64);
+        if (l < 32) rho_part[((long)vt * nb + b) * d.nrp + r] = s;
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+gemm2_bf16_kernel(GemmDims d, int M, int splitk, int kchunk, const bf16_t* __restrict__ psi_v_t,
+                  const bf16_t* __restrict__ psi_c_t, const float* __restrict__ vpot,
+                  float* __restrict__ ypart) {
+  __shared__ bf16_t As[HM][HLD];
+  __shared__ bf16_t Bs[HN][HLD];
+  const int mt = (M + HM - 1) / HM, nt = (d.ncp + HN - 1) / HN;
+  const int lid = xcd_remap(blockIdx.x, mt * nt * splitk);
+  const int s = lid / (mt * nt);
+  const int rem = lid - s * mt * nt;
+  const int m0 = (rem % mt) * HM, n0 = (rem / mt) * HN;
+  const int kb = s * kchunk;
+  const int ke = min(d.nrp, kb + kchunk);
+  f16v acc[4][HWN];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < HWN; ++j) acc[i][j] = f16v{};
+  LoadPsiV16 la{psi_v_t, vpot, d.nrp, d.nvp};
+  bf16_mainloop(la, M, psi_c_t, d.nrp, d.ncp, m0, n0, kb, ke, As, Bs, acc);
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  float* out = ypart + (long)s * M * d.ncp;
+#pragma unroll
+  for (int j = 0; j < HWN; ++j) {
+    const int n = n0 + wn * (HN / 2) + 32 * j + (l & 31);
+    if (n >= d.ncp) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int m = m0 + wm * 128 + 32 * i + 8 * (q >> 2) + 4 * (l >> 5) + (q & 3);
+        if (m < M) out[(long)m * d.ncp + n] = acc[i][j][q];
+      }
+  }
+}
+
+}  // namespace
+
+int gemm1_f64m_vtiles(const GemmDims& d) { return d.nvp / 64; }
+
+void gemm1_f64m(const GemmDims& d, int nb, const double* psi_c_rc, const double* psi_v_rv,
+                const double* u, double* rho_part, hipStream_t st) {
+  if (nb <= 0) return;
+  const int M = nb * d.nvp;
+  const int blocks = ceil_div(M, DM) * (d.nrp / DN);
+  gemm1_f64m_kernel<<<blocks, 256, 0, st>>>(d, M, nb, psi_c_rc, psi_v_rv, u, rho_part);
+  GWL_HIP(hipGetLastError());
+}
+
+void gemm2_f64m(const GemmDims& d, int nb, int splitk, const double* psi_v_t,
+                const double* psi_c_t, const double* vpot, double* ypart, hipStream_t st) {
+  if (nb <= 0) return;
+  const int M = nb * d.nvp;
+  const int kchunk = (int)round_up(ceil_div(d.nrp, splitk), DK);
+  const int blocks = ceil_div(M, DM) * ceil_div(d.ncp, DN) * splitk;
+  gemm2_f64m_kernel<<<blocks, 256, 0, st>>>(d, M, splitk, kchunk, psi_v_t, psi_c_t, vpot, ypart);
+  GWL_HIP(hipGetLastError());
+}
+
+int gemm1_bf16_vtiles(const GemmDims& d) { return d.nvp >= 128 ? d.nvp / 128 : 1; }
+
+void gemm1_bf16(const GemmDims& d, int nb, const bf16_t* psi_c_rc, const float* psi_v_rv,
+                const bf16_t* u, float* rho_part, hipStream_t st) {
+  if (nb <= 0) return;
+  const int M = nb * d.nvp;
+  const int blocks = ceil_div(M, HM) * (d.nrp / HN);
+  if (d.nvp >= 128)
+    gemm1_bf16_kernel<4><<<blocks, 256, 0, st>>>(d, M, nb, psi_c_rc, psi_v_rv, u, rho_part);
+  else
+    gemm1_bf16_kernel<2><<<blocks, 256, 0, st>>>(d, M, nb, psi_c_rc, psi_v_rv, u, rho_part);
+  GWL_HIP(hipGetLastError());
+}
+
+void gemm2_bf16(const GemmDims& d, int nb, int splitk, const bf16_t* psi_v_t,
+                const bf16_t* psi_c_t, const float* vpot, float* ypart, hipStream_t st) {
+  if (nb <= 0) return;
+  const int M = nb * d.nvp;
+  const int kchunk = (int)round_up(ceil_div(d.nrp, splitk), HK);
+  const int blocks = ceil_div(M, HM) * ceil_div(d.ncp, HN) * splitk;
+  gemm2_bf16_kernel<<<blocks, 256, 0, st>>>(d, M, splitk, kchunk, psi_v_t, psi_c_t, vpot, ypart);
+  GWL_HIP(hipGetLastError());
+}
+
+}  // namespace gwl

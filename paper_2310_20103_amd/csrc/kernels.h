@@ -1,0 +1,156 @@
+// Internal launch interfaces of the gfx950 kernels.  Not part of the C ABI.
+#pragma once
+
+#include "common.h"
+
+namespace gwl {
+
+// ---------------------------------------------------------------- FFT Poisson
+struct FftPlan {
+  int nstages;
+  int radix[8];
+  int ok;
+};
+FftPlan make_plan(int n);
+
+template <typename T>
+struct PoissonGeom {
+  int nx, ny, nz;
+  FftPlan px, py, pz;
+  const cplx<T>* twx;  // exp(-2 pi i k / n), k < n, per axis
+  const cplx<T>* twy;
+  const cplx<T>* twz;
+  const T* g2x;        // |G_x|^2 per index, fftfreq convention
+  const T* g2y;
+  const T* g2z;
+  T vscale;            // kernel_scale * 4 pi / N_r
+};
+
+// rin: [nparts][nf][ld_in] partial densities (summed); rout: [nf][ld_out].
+// scratch: [(nf+1)/2][N_r] complex.
+template <typename T>
+void poisson_launch(const PoissonGeom<T>& g, const T* rin, long ld_in, long part_stride,
+                    int nparts, T* rout, long ld_out, int nf, cplx<T>* scratch,
+                    hipStream_t st);
+
+// ---------------------------------------------------------------- GEMMs
+// Padded operand layouts (NRp, NVp, NCp multiples of the tile sizes):
+//   psi_c_rc [NRp][NCp]  (GEMM1 B operand, c contiguous)
+//   psi_v_rv [NRp][NVp]  (GEMM1 epilogue weights)
+//   psi_v_t  [NVp][NRp], psi_c_t [NCp][NRp]  (GEMM2 operands, r contiguous)
+//   u        [B][NVp][NCp]  (Delta^1/2 x in operand precision)
+//   rho      [nvt][B][NRp]  partial densities, one per v tile (summed by the FFT)
+//   vpot     [B][NRp]
+//   ypart    [S][B][NVp][NCp] split-K partial sums of the second GEMM
+struct GemmDims {
+  int nr, nrp, nv, nvp, nc, ncp;
+};
+
+// Padding: N_r to 256; N_c to 64; N_v to 64 when N_v <= 64, else to 128 (the
+// BF16 tile reduces over 128 occupied orbitals of one pair vector at a time).
+constexpr int kPadR = 256;
+constexpr int kPadC = 64;
+inline int pad_nv(int nv) { return nv <= 64 ? 64 : (int)round_up(nv, 128); }
+
+// FP64 (plain tiled FMA; reference-quality GPU path).
+int gemm1_f64_vtiles(const GemmDims& d);
+void gemm1_f64(const GemmDims& d, int nb, const double* psi_c_rc, const double* psi_v_rv,
+               const double* u, double* rho_part, hipStream_t st);
+void gemm2_f64(const GemmDims& d, int nb, int splitk, const double* psi_v_t,
+               const double* psi_c_t, const double* vpot, double* ypart, hipStream_t st);
+
+// BF16 operands, FP32 accumulation, plain FMA tiles (checks the MFMA kernels).
+int gemm1_bf16s_vtiles(const GemmDims& d);
+void gemm1_bf16s(const GemmDims& d, int nb, const bf16_t* psi_c_rc, const float* psi_v_rv,
+                 const bf16_t* u, float* rho_part, hipStream_t st);
+void gemm2_bf16s(const GemmDims& d, int nb, int splitk, const bf16_t* psi_v_t,
+                 const bf16_t* psi_c_t, const float* vpot, float* ypart, hipStream_t st);
+
+// FP64 on MFMA (v_mfma_f64_16x16x4).
+int gemm1_f64m_vtiles(const GemmDims& d);
+void gemm1_f64m(const GemmDims& d, int nb, const double* psi_c_rc, const double* psi_v_rv,
+                const double* u, double* rho_part, hipStream_t st);
+void gemm2_f64m(const GemmDims& d, int nb, int splitk, const double* psi_v_t,
+                const double* psi_c_t, const double* vpot, double* ypart, hipStream_t st);
+
+// BF16 operands, FP32 accumulation, on MFMA.
+int gemm1_bf16_vtiles(const GemmDims& d);
+void gemm1_bf16(const GemmDims& d, int nb, const bf16_t* psi_c_rc, const float* psi_v_rv,
+                const bf16_t* u, float* rho_part, hipStream_t st);
+void gemm2_bf16(const GemmDims& d, int nb, int splitk, const bf16_t* psi_v_t,
+                const bf16_t* psi_c_t, const float* vpot, float* ypart, hipStream_t st);
+
+// ---------------------------------------------------------------- pair-space ops
+struct PairGeom {
+  int nv, nc, nvp, ncp;
+  long nvc;
+  const double* delta2;  // Delta^2   [nvc]
+  const double* sdelta;  // Delta^1/2 [nvc]
+  double dv;
+};
+
+// Elementwise orbital products rho_i = phi_{n_i} phi_{m_i} (FP64), [cnt][NRp].
+void pair_product(const double* psi_t, long ld, int nr, const int* m_idx, const int* n_idx,
+                  int cnt, double* rho, hipStream_t st);
+
+// u[b] = cast(Delta^1/2 * x[b]) into the padded operand layout.
+template <typename U>
+void cast_u(const PairGeom& g, int nb, const double* x, long ldx, U* u, hipStream_t st);
+
+// Chebyshev/C combine after the second GEMM.  y = sum_s ypart[s];
+// cx = Delta^2 x + 2 dV Delta^1/2 y.  mode 0: out = cx.  mode 1 (first
+// Chebyshev step): tn = (2 cx - (hi+lo) x)/(hi-lo); acc = c0 x + c1 tn.
+// mode 2: tn = 2 (2 cx - (hi+lo) x)/(hi-lo) - tp; acc += cj tn.
+// If u != null also writes u = cast(Delta^1/2 tn) (mode 1, 2) for the next product.
+template <typename Y, typename U>
+void combine(const PairGeom& g, int nb, int splitk, const Y* ypart, const double* x,
+             const double* tp, double* out_tn, double* acc, int mode, double lo, double hi,
+             double c0, double cj, U* u, hipStream_t st);
+
+// Coupling finish: P_i = dV Delta^1/2 sum_s ypart[s][i]; writes P (compact)
+// to p_out[i] (ld ldp).
+template <typename Y>
+void coupling_finish(const PairGeom& g, int cnt, int splitk, const Y* ypart, double* p_out,
+                     long ldp, hipStream_t st);
+
+// ---------------------------------------------------------------- Lanczos
+struct SlotState {
+  int* pair;       // [B] pair id, -1 = empty slot
+  int* k;          // [B] current step index
+  int* len;        // [B] steps to run
+  int* dead;       // [B] breakdown flag
+  double* amax;    // [B] max |a_j| so far
+  double* bprev;   // [B] b_k of the three-term update
+  double* coef_a;  // [n_pairs][ld]
+  double* coef_b;  // [n_pairs][ld]
+  int* out_len;    // [n_pairs]
+  double* norm2;   // [n_pairs]
+  int ld;
+};
+
+// Start: from P in q (slot rows listed in slots), compute ||P||^2, q = P/||P||,
+// store basis row 0, reset slot state.
+void lz_start(const SlotState& s, int nb_slots, const int* slot_list, int cnt, double* q,
+              double* qprev, double* basis, long basis_slot_stride, long nvc, hipStream_t st);
+// a_k = q.w; w -= a_k q + b_k q_prev.
+void lz_alpha(const SlotState& s, int nb, const double* q, const double* qprev, double* w,
+              long nvc, hipStream_t st);
+// full (two-pass CGS against basis rows 0..k) or local reorthogonalisation.
+void lz_reorth(const SlotState& s, int nb, int kmax, int mode, const double* basis,
+               long basis_slot_stride, const double* q, const double* qprev, double* w,
+               double* hbuf, long nvc, hipStream_t st);
+// b_{k+1} = ||w||; breakdown test; q_prev = q; q = w / b; basis row k+1 = q; k += 1.
+void lz_beta(const SlotState& s, int nb, double* q, double* qprev, double* w, double* basis,
+             long basis_slot_stride, int store_basis, long nvc, hipStream_t st);
+
+// ---------------------------------------------------------------- continued fraction
+// sig[p][w] (complex, eV) for pairs p, Eq. 12 with Eq. 14.
+void cfrac_sigma(int npairs, const double* coef_a, const double* coef_b, const int* lens,
+                 const double* norm2, int ld, const double* e_n, const double* eta_n,
+                 const double* omega_ha, int nomega, double delta_ha, double* sig,
+                 hipStream_t st);
+// out[q][w] = sum_{p in [q*per, (q+1)*per)} sig[p][w], fixed order.
+void sum_groups(const double* sig, int ngroups, int per, int nomega, double* out,
+                hipStream_t st);
+
+}  // namespace gwl

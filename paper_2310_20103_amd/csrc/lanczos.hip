@@ -1,0 +1,361 @@
+// Pair-space kernels: the Chebyshev combination that turns C-products into
+// p_g(C) x (paragraph after Eq. 12), the coupling-vector finish
+// (P_nm = (nm|vc) Delta^1/2), and the batched FP64 Lanczos recurrence of
+// Eq. 13 with optional reorthogonalisation.
+//
+// All reductions are deterministic: a fixed wavefront shuffle tree followed by
+// a fixed-order sum over the block's waves; no atomics.  One block per Lanczos
+// slot for dots and norms (pair vectors are at most a few MB), grid-stride
+// elementwise kernels elsewhere.
+#include "common.h"
+#include "kernels.h"
+
+namespace gwl {
+namespace {
+
+constexpr int NT = 256;
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Deterministic block sum; result broadcast to every thread.
+__device__ inline double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+  const int nw = blockDim.x >> 6;
+  for (int i = 0; i < nw; ++i) t += sh[i];
+  __syncthreads();
+  return t;
+}
+
+template <typename U>
+__device__ inline U to_op(double v);
+template <>
+__device__ inline double to_op<double>(double v) { return v; }
+template <>
+__device__ inline bf16_t to_op<bf16_t>(double v) { return f32_to_bf16((float)v); }
+
+__global__ void pair_product_kernel(const double* __restrict__ psi_t, long ld, int nr,
+                                    const int* __restrict__ m_idx, const int* __restrict__ n_idx,
+                                    double* __restrict__ rho) {
+  const int i = blockIdx.y;
+  const double* a = psi_t + (long)m_idx[i] * ld;
+  const double* b = psi_t + (long)n_idx[i] * ld;
+  double* o = rho + (long)i * ld;
+  for (long r = blockIdx.x * (long)blockDim.x + threadIdx.x; r < ld; r += (long)gridDim.x * blockDim.x)
+    o[r] = a[r] * b[r];
+}
+
+template <typename U>
+__global__ void cast_u_kernel(PairGeom g, const double* __restrict__ x, long ldx, U* __restrict__ u) {
+  const int b = blockIdx.y;
+  const double* xb = x + (long)b * ldx;
+  U* ub = u + (long)b * g.nvp * g.ncp;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < g.nvc; i += (long)gridDim.x * blockDim.x) {
+    const int v = (int)(i / g.nc), c = (int)(i - (long)v * g.nc);
+    ub[(long)v * g.ncp + c] = to_op<U>(g.sdelta[i] * xb[i]);
+  }
+}
+
+template <typename Y, typename U>
+__global__ void combine_kernel(PairGeom g, int nb, int splitk, const Y* __restrict__ ypart,
+                               const double* __restrict__ x, const double* __restrict__ tp,
+                               double* __restrict__ out, double* __restrict__ acc, int mode,
+                               double lo, double hi, double c0, double cj, U* __restrict__ u) {
+  const int b = blockIdx.y;
+  const long stride_s = (long)nb * g.nvp * g.ncp;
+  const Y* yb = ypart + (long)b * g.nvp * g.ncp;
+  const double* xb = x + (long)b * g.nvc;
+  const double inv = 1.0 / (hi - lo);
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < g.nvc; i += (long)gridDim.x * blockDim.x) {
+    const int v = (int)(i / g.nc), c = (int)(i - (long)v * g.nc);
+    const long off = (long)v * g.ncp + c;
+    double y = 0.0;
+    for (int s = 0; s < splitk; ++s) y += (double)yb[s * stride_s + off];
+    const double xi = xb[i];
+    const double sd = g.sdelta[i];
+    const double cx = g.delta2[i] * xi + 2.0 * g.dv * sd * y;
+    const long o = (long)b * g.nvc + i;
+    if (mode == 0) {
+      out[o] = cx;
+      continue;
+    }
+    const double ct = (2.0 * cx - (hi + lo) * xi) * inv;
+    double tn;
+    if (mode == 1) {
+      tn = ct;
+      acc[o] = c0 * xi + cj * tn;
+    } else {
+      tn = 2.0 * ct - tp[o];
+      acc[o] += cj * tn;
+    }
+    out[o] = tn;
+    if (u) u[(long)b * g.nvp * g.ncp + off] = to_op<U>(sd * tn);
+  }
+}
+
+template <typename Y>
+__global__ void coupling_finish_kernel(PairGeom g, int cnt, int splitk, const Y* __restrict__ ypart,
+                                       double* __restrict__ p, long ldp) {
+  const int i = blockIdx.y;
+  const long stride_s = (long)cnt * g.nvp * g.ncp;
+  const Y* yb = ypart + (long)i * g.nvp * g.ncp;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < g.nvc; e += (long)gridDim.x * blockDim.x) {
+    const int v = (int)(e / g.nc), c = (int)(e - (long)v * g.nc);
+    const long off = (long)v * g.ncp + c;
+    double y = 0.0;
+    for (int s = 0; s < splitk; ++s) y += (double)yb[s * stride_s + off];
+    p[(long)i * ldp + e] = g.dv * g.sdelta[e] * y;
+  }
+}
+
+__device__ inline bool slot_active(const SlotState& s, int b) {
+  return s.pair[b] >= 0 && !s.dead[b] && s.k[b] < s.len[b];
+}
+
+__global__ void __launch_bounds__(NT)
+lz_start_kernel(SlotState s, const int* __restrict__ slot_list, double* __restrict__ q,
+                double* __restrict__ qprev, double* __restrict__ basis, long bstride, long nvc) {
+  __shared__ double sh[NT / 64];
+  const int b = slot_list[blockIdx.x];
+  const int pair = s.pair[b];
+  double* qb = q + (long)b * nvc;
+  double part = 0.0;
+  for (long i = threadIdx.x; i < nvc; i += NT) part += qb[i] * qb[i];
+  const double n2 = block_sum(part, sh);
+  const double inv = n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0;
+  double* pb = qprev + (long)b * nvc;
+  double* bb = basis ? basis + (long)b * bstride : nullptr;
+  for (long i = threadIdx.x; i < nvc; i += NT) {
+    const double v = qb[i] * inv;
+    qb[i] = v;
+    pb[i] = 0.0;
+    if (bb) bb[i] = v;
+  }
+  if (threadIdx.x == 0) {
+    s.norm2[pair] = n2;
+    s.k[b] = 0;
+    s.dead[b] = (n2 > 0.0) ? 0 : 1;
+    s.amax[b] = 0.0;
+    s.bprev[b] = 0.0;
+    s.out_len[pair] = 0;
+  }
+}
+
+__global__ void __launch_bounds__(NT)
+lz_alpha_kernel(SlotState s, const double* __restrict__ q, const double* __restrict__ qprev,
+                double* __restrict__ w, long nvc) {
+  __shared__ double sh[NT / 64];
+  const int b = blockIdx.x;
+  if (!slot_active(s, b)) return;
+  const double* qb = q + (long)b * nvc;
+  const double* pb = qprev + (long)b * nvc;
+  double* wb = w + (long)b * nvc;
+  double part = 0.0;
+  for (long i = threadIdx.x; i < nvc; i += NT) part += qb[i] * wb[i];
+  const double a = block_sum(part, sh);
+  const double bp = s.bprev[b];
+  for (long i = threadIdx.x; i < nvc; i += NT) wb[i] = wb[i] - a * qb[i] - bp * pb[i];
+  if (threadIdx.x == 0) {
+    const int pair = s.pair[b], k = s.k[b];
+    s.coef_a[(long)pair * s.ld + k] = a;
+    s.amax[b] = fmax(s.amax[b], fabs(a));
+    s.out_len[pair] = k + 1;
+  }
+}
+
+__device__ inline bool needs_beta(const SlotState& s, int b) {
+  return slot_active(s, b) && s.k[b] < s.len[b] - 1;
+}
+
+// h[b][j] = basis_j . w  (FULL: j <= k; LOCAL: j in {k-1, k} read from q, qprev)
+__global__ void __launch_bounds__(NT)
+lz_dots_kernel(SlotState s, int mode, const double* __restrict__ basis, long bstride,
+               const double* __restrict__ q, const double* __restrict__ qprev,
+               const double* __restrict__ w, double* __restrict__ h, int hld, long nvc) {
+  __shared__ double sh[NT / 64];
+  const int j = blockIdx.x, b = blockIdx.y;
+  if (!needs_beta(s, b)) return;
+  const int k = s.k[b];
+  const double* vb;
+  if (mode == GWL_REORTH_FULL) {
+    if (j > k) return;
+    vb = basis + (long)b * bstride + (long)j * nvc;
+  } else {
+    if (j > 1 || (j == 1 && k == 0)) {
+      if (threadIdx.x == 0) h[(long)b * hld + j] = 0.0;
+      return;
+    }
+    vb = (j == 0 ? q : qprev) + (long)b * nvc;
+  }
+  const double* wb = w + (long)b * nvc;
+  double part = 0.0;
+  for (long i = threadIdx.x; i < nvc; i += NT) part += vb[i] * wb[i];
+  const double t = block_sum(part, sh);
+  if (threadIdx.x == 0) h[(long)b * hld + j] = t;
+}
+
+__global__ void lz_project_kernel(SlotState s, int mode, const double* __restrict__ basis,
+                                  long bstride, const double* __restrict__ q,
+                                  const double* __restrict__ qprev, double* __restrict__ w,
+                                  const double* __restrict__ h, int hld, long nvc) {
+  const int b = blockIdx.y;
+  if (!needs_beta(s, b)) return;
+  const int k = s.k[b];
+  const double* hb = h + (long)b * hld;
+  double* wb = w + (long)b * nvc;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < nvc; i += (long)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    if (mode == GWL_REORTH_FULL) {
+      const double* bb = basis + (long)b * bstride + i;
+      for (int j = 0; j <= k; ++j) acc += hb[j] * bb[(long)j * nvc];
+    } else {
+      acc = hb[0] * q[(long)b * nvc + i];
+      if (k > 0) acc += hb[1] * qprev[(long)b * nvc + i];
+    }
+    wb[i] -= acc;
+  }
+}
+
+__global__ void __launch_bounds__(NT)
+lz_beta_kernel(SlotState s, double* __restrict__ q, double* __restrict__ qprev,
+               double* __restrict__ w, double* __restrict__ basis, long bstride,
+               int store_basis, long nvc) {
+  __shared__ double sh[NT / 64];
+  const int b = blockIdx.x;
+  if (!slot_active(s, b)) return;
+  const int k = s.k[b];
+  if (k >= s.len[b] - 1) {
+    __syncthreads();
+    if (threadIdx.x == 0) s.k[b] = k + 1;
+    return;
+  }
+  double* wb = w + (long)b * nvc;
+  double part = 0.0;
+  for (long i = threadIdx.x; i < nvc; i += NT) part += wb[i] * wb[i];
+  const double bn = sqrt(block_sum(part, sh));
+  const int pair = s.pair[b];
+  if (!(bn > 1e-12 * s.amax[b])) {
+    // exact invariant subspace (or non-finite norm): the fraction ends here
+    if (threadIdx.x == 0) {
+      s.dead[b] = 1;
+      s.k[b] = k + 1;
+    }
+    return;
+  }
+  const double inv = 1.0 / bn;
+  double* qb = q + (long)b * nvc;
+  double* pb = qprev + (long)b * nvc;
+  double* bb = store_basis ? basis + (long)b * bstride + (long)(k + 1) * nvc : nullptr;
+  for (long i = threadIdx.x; i < nvc; i += NT) {
+    const double nq = wb[i] * inv;
+    pb[i] = qb[i];
+    qb[i] = nq;
+    if (bb) bb[i] = nq;
+  }
+  if (threadIdx.x == 0) {
+    s.coef_b[(long)pair * s.ld + k] = bn;
+    s.bprev[b] = bn;
+    s.k[b] = k + 1;
+  }
+}
+
+inline int grid_elems(long n) {
+  long g = (n + NT - 1) / NT;
+  if (g > 1024) g = 1024;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+}  // namespace
+
+void pair_product(const double* psi_t, long ld, int nr, const int* m_idx, const int* n_idx,
+                  int cnt, double* rho, hipStream_t st) {
+  if (cnt <= 0) return;
+  dim3 grid(grid_elems(ld), cnt);
+  pair_product_kernel<<<grid, NT, 0, st>>>(psi_t, ld, nr, m_idx, n_idx, rho);
+  GWL_HIP(hipGetLastError());
+}
+
+template <typename U>
+void cast_u(const PairGeom& g, int nb, const double* x, long ldx, U* u, hipStream_t st) {
+  if (nb <= 0) return;
+  dim3 grid(grid_elems(g.nvc), nb);
+  cast_u_kernel<U><<<grid, NT, 0, st>>>(g, x, ldx, u);
+  GWL_HIP(hipGetLastError());
+}
+template void cast_u<double>(const PairGeom&, int, const double*, long, double*, hipStream_t);
+template void cast_u<bf16_t>(const PairGeom&, int, const double*, long, bf16_t*, hipStream_t);
+
+template <typename Y, typename U>
+void combine(const PairGeom& g, int nb, int splitk, const Y* ypart, const double* x,
+             const double* tp, double* out_tn, double* acc, int mode, double lo, double hi,
+             double c0, double cj, U* u, hipStream_t st) {
+  if (nb <= 0) return;
+  dim3 grid(grid_elems(g.nvc), nb);
+  combine_kernel<Y, U><<<grid, NT, 0, st>>>(g, nb, splitk, ypart, x, tp, out_tn, acc, mode, lo,
+                                            hi, c0, cj, u);
+  GWL_HIP(hipGetLastError());
+}
+template void combine<double, double>(const PairGeom&, int, int, const double*, const double*,
+                                      const double*, double*, double*, int, double, double,
+                                      double, double, double*, hipStream_t);
+template void combine<float, bf16_t>(const PairGeom&, int, int, const float*, const double*,
+                                     const double*, double*, double*, int, double, double,
+                                     double, double, bf16_t*, hipStream_t);
+
+template <typename Y>
+void coupling_finish(const PairGeom& g, int cnt, int splitk, const Y* ypart, double* p_out,
+                     long ldp, hipStream_t st) {
+  if (cnt <= 0) return;
+  dim3 grid(grid_elems(g.nvc), cnt);
+  coupling_finish_kernel<Y><<<grid, NT, 0, st>>>(g, cnt, splitk, ypart, p_out, ldp);
+  GWL_HIP(hipGetLastError());
+}
+template void coupling_finish<double>(const PairGeom&, int, int, const double*, double*, long,
+                                      hipStream_t);
+template void coupling_finish<float>(const PairGeom&, int, int, const float*, double*, long,
+                                     hipStream_t);
+
+void lz_start(const SlotState& s, int nb_slots, const int* slot_list, int cnt, double* q,
+              double* qprev, double* basis, long bstride, long nvc, hipStream_t st) {
+  (void)nb_slots;
+  if (cnt <= 0) return;
+  lz_start_kernel<<<cnt, NT, 0, st>>>(s, slot_list, q, qprev, basis, bstride, nvc);
+  GWL_HIP(hipGetLastError());
+}
+
+void lz_alpha(const SlotState& s, int nb, const double* q, const double* qprev, double* w,
+              long nvc, hipStream_t st) {
+  lz_alpha_kernel<<<nb, NT, 0, st>>>(s, q, qprev, w, nvc);
+  GWL_HIP(hipGetLastError());
+}
+
+void lz_reorth(const SlotState& s, int nb, int kmax, int mode, const double* basis,
+               long bstride, const double* q, const double* qprev, double* w, double* hbuf,
+               long nvc, hipStream_t st) {
+  if (mode == GWL_REORTH_NONE) return;
+  const int nd = (mode == GWL_REORTH_FULL) ? kmax + 1 : 2;
+  const int hld = (mode == GWL_REORTH_FULL) ? s.ld + 1 : 2;
+  for (int pass = 0; pass < 2; ++pass) {
+    lz_dots_kernel<<<dim3(nd, nb), NT, 0, st>>>(s, mode, basis, bstride, q, qprev, w, hbuf,
+                                                hld, nvc);
+    lz_project_kernel<<<dim3(grid_elems(nvc), nb), NT, 0, st>>>(s, mode, basis, bstride, q,
+                                                                qprev, w, hbuf, hld, nvc);
+  }
+  GWL_HIP(hipGetLastError());
+}
+
+void lz_beta(const SlotState& s, int nb, double* q, double* qprev, double* w, double* basis,
+             long bstride, int store_basis, long nvc, hipStream_t st) {
+  lz_beta_kernel<<<nb, NT, 0, st>>>(s, q, qprev, w, basis, bstride, store_basis, nvc);
+  GWL_HIP(hipGetLastError());
+}
+
+}  // namespace gwl

@@ -1,0 +1,372 @@
+"""GPU parity of every step of the path against the FP64 CPU oracle.
+
+Each test calls the HIP library through the C ABI (ctypes binding) and
+compares element by element with the oracle on the same seeded inputs.
+Tolerances:
+  * FP64 kernels (FFT Poisson, coupling vectors, C x, p_g(C) x): 1e-11
+    relative to the largest element; FP64 Sigma vs the oracle's Lanczos
+    Sigma_L: <= 1e-8 relative (max over omega, per QP state).
+  * mixed (BF16 GEMM operands, FP32 accumulation/FFT, FP64 recurrence):
+    <= 1e-3 eV absolute against the oracle.
+"""
+import numpy as np
+import pytest
+
+import gw_inputs as gi
+import oracle
+from oracle import chebyshev as CH
+from oracle import sigma as S
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def box_of(wl):
+    return tuple(n * wl.h for n in wl.grid)
+
+
+def make_ctx(sysm, precision="fp64", interval=None, **kw):
+    import paper_2310_20103_amd as G
+    wl = sysm.wl
+    lo, hi = interval if interval is not None else (0.0, 0.0)
+    return G.Context(sysm.phi, sysm.energies_ev, wl.n_occ, wl.grid, box_of(wl),
+                     precision=precision, poly_degree=wl.poly_degree, poly_lo=lo, poly_hi=hi,
+                     **kw)
+
+
+def relerr(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(b)), 1e-300))
+
+
+class Case:
+    def __init__(self, base, **over):
+        wl = gi.workload(base, **over)
+        self.sys = gi.make_system(wl)
+        self.wl = wl
+        self.pr = oracle.Problem(self.sys.phi, self.sys.energies_ev, wl.n_occ, wl.grid, wl.h)
+        self.lo, self.hi = oracle.default_interval(self.pr)
+
+
+@pytest.fixture(scope="module")
+def small():
+    _say("small case grid24_v8c32")
+    return Case("grid24_v8c32")
+
+
+@pytest.fixture(scope="module")
+def ragged():
+    # grid 12 x 18 x 8 (radices 4*3, 2*3*3, 8), N_v = 5, N_c = 19: every
+    # dimension has a ragged tail against the tiles
+    _say("ragged case grid 12x18x8, 5+19 orbitals")
+    return Case("grid24_v8c32", name="ragged", seed=77, grid=(12, 18, 8), box=6.0,
+                n_occ=5, n_emp=19, n_qp_occ=1, n_qp_emp=1, n_lanczos=24, n_omega=33)
+
+
+@pytest.fixture(scope="module")
+def smooth():
+    _say("smooth stress variant of the small case")
+    return Case("grid24_v8c32", name="smooth", smooth_sigma=1.0)
+
+
+@pytest.fixture(scope="module")
+def ctx_small(small):
+    c = make_ctx(small.sys, interval=(small.lo, small.hi))
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def ctx_ragged(ragged):
+    c = make_ctx(ragged.sys, interval=(ragged.lo, ragged.hi))
+    yield c
+    c.close()
+
+
+# ------------------------------------------------------------------ FFT Poisson
+@pytest.mark.parametrize("which", ["small", "ragged"])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 2e-6)])
+def test_poisson(request, which, precision, tol):
+    case = request.getfixturevalue(which)
+    ctx = request.getfixturevalue("ctx_" + which)
+    wl = case.wl
+    _say("poisson", which, precision)
+    f = gi.random_fields(5, wl.n_r, seed=3)
+    ref = oracle.poisson.poisson(f, wl.grid, wl.h)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    got = ctx.poisson(torch.tensor(f, dtype=dt, device="cuda"), precision).double().cpu().numpy()
+    assert relerr(got, ref) <= tol
+
+
+# ------------------------------------------------------------------ coupling vectors
+@pytest.mark.parametrize("which", ["small", "ragged"])
+def test_coupling(request, which):
+    case = request.getfixturevalue(which)
+    ctx = request.getfixturevalue("ctx_" + which)
+    _say("coupling", which)
+    m = int(case.sys.qp_states[0])
+    ref = case.pr.coupling(m)
+    n = np.arange(case.wl.n_orb)
+    got = ctx.coupling(np.full_like(n, m), n).cpu().numpy()
+    assert relerr(got, ref) <= 1e-11
+
+
+# ------------------------------------------------------------------ C x and p_g(C) x
+@pytest.mark.parametrize("which", ["small", "ragged"])
+def test_apply_c_fp64(request, which):
+    case = request.getfixturevalue(which)
+    ctx = request.getfixturevalue("ctx_" + which)
+    _say("apply_c fp64", which)
+    x = gi.random_pair_vectors(7, case.wl.n_vc, seed=4)
+    ref = x @ case.pr.C.T
+    got = ctx.apply_c(torch.tensor(x, device="cuda")).cpu().numpy()
+    assert relerr(got, ref) <= 1e-11
+
+
+@pytest.mark.parametrize("which", ["small", "ragged"])
+def test_apply_c_mixed(request, which):
+    case = request.getfixturevalue(which)
+    ctx = request.getfixturevalue("ctx_" + which)
+    _say("apply_c mixed", which)
+    x = gi.random_pair_vectors(3, case.wl.n_vc, seed=5)
+    ref = x @ case.pr.C.T
+    got = ctx.apply_c(torch.tensor(x, device="cuda"), "mixed").cpu().numpy()
+    assert relerr(got, ref) <= 1e-3
+    # the coupling part alone to BF16 accuracy
+    dk = ref - case.pr.delta ** 2 * x
+    gk = got - case.pr.delta ** 2 * x
+    assert relerr(gk, dk) <= 2e-2
+
+
+@pytest.mark.parametrize("which", ["small", "ragged"])
+def test_apply_d_fp64(request, which):
+    case = request.getfixturevalue(which)
+    ctx = request.getfixturevalue("ctx_" + which)
+    _say("apply_d fp64", which)
+    x = gi.random_pair_vectors(3, case.wl.n_vc, seed=6)
+    dg = case.pr.dg_matrix(case.lo, case.hi, case.wl.poly_degree)
+    ref = x @ dg.T
+    got = ctx.apply_d(torch.tensor(x, device="cuda")).cpu().numpy()
+    assert relerr(got, ref) <= 1e-11
+
+
+# ------------------------------------------------------------------ Lanczos coefficients
+def test_lanczos_coefficients(small, ctx_small):
+    _say("lanczos coefficients small, 4 pairs x 64 steps")
+    m = int(small.sys.qp_states[0])
+    ns = [0, 3, 9, 39]
+    a, b, n2, ol = ctx_small.lanczos_pairs([m] * 4, ns, [64] * 4)
+    ref = small.pr.lanczos_coeffs(m, 64, small.lo, small.hi, small.wl.poly_degree, n_list=ns)
+    for i, (ra, rb, rn2) in enumerate(ref):
+        assert ol[i] == len(ra)
+        assert abs(n2[i] - rn2) <= 1e-12 * rn2
+        assert relerr(a[i, :len(ra)], ra) <= 1e-9
+        assert relerr(b[i, :len(rb)], rb) <= 1e-9
+
+
+def test_uneven_lengths_with_refill(small):
+    """Lengths 1..64 over 3 slots: slots retire and are refilled mid-run."""
+    _say("uneven lengths, block 3")
+    ctx = make_ctx(small.sys, interval=(small.lo, small.hi), block=3)
+    try:
+        m = int(small.sys.qp_states[1])
+        ns = [1, 7, 20, 33, 2, 11, 38, 5]
+        lens = [1, 5, 64, 17, 3, 40, 9, 26]
+        a, b, n2, ol = ctx.lanczos_pairs([m] * len(ns), ns, lens)
+        for i, n in enumerate(ns):
+            ra, rb, rn2 = small.pr.lanczos_coeffs(m, lens[i], small.lo, small.hi,
+                                                  small.wl.poly_degree, n_list=[n])[0]
+            assert ol[i] == len(ra) == lens[i]
+            assert relerr(a[i, :len(ra)], ra) <= 1e-9
+            if len(rb):
+                assert relerr(b[i, :len(rb)], rb) <= 1e-9
+            assert np.all(a[i, len(ra):] == 0)
+    finally:
+        ctx.close()
+
+
+def test_breakdown_short_fraction():
+    """N_vc = 6 < L = 12: the recurrence must stop at an invariant subspace."""
+    _say("breakdown tiny 2+3")
+    case = Case("grid24_v8c32", name="tiny", seed=5, grid=(8, 8, 8), box=5.0, n_occ=2,
+                n_emp=3, n_lanczos=12, n_omega=21)
+    ctx = make_ctx(case.sys, interval=(case.lo, case.hi))
+    try:
+        m = int(case.sys.qp_states[0])
+        ns = list(range(case.wl.n_orb))
+        a, b, n2, ol = ctx.lanczos_pairs([m] * len(ns), ns, [12] * len(ns))
+        assert np.all(ol <= 6)
+        om = case.sys.omega_ev
+        got = ctx.sigma_c([m], om, case.wl.eta, 12)[0]
+        ref = case.pr.sigma_lanczos(m, om, case.wl.eta, 12, case.lo, case.hi, case.wl.poly_degree)
+        assert relerr(got, ref) <= 1e-9
+        # full length reproduces the L -> N_vc limit
+        sdg = case.pr.sigma_dg(m, om, case.wl.eta, case.lo, case.hi, case.wl.poly_degree)
+        assert relerr(got, sdg) <= 1e-9
+    finally:
+        ctx.close()
+
+
+# ------------------------------------------------------------------ Sigma
+def test_sigma_fp64_small(small, ctx_small):
+    _say("sigma fp64 small L=64")
+    wl = small.wl
+    got = ctx_small.sigma_c(small.sys.qp_states, small.sys.omega_ev, wl.eta, wl.n_lanczos)
+    for i, m in enumerate(small.sys.qp_states):
+        ref = small.pr.sigma_lanczos(int(m), small.sys.omega_ev, wl.eta, wl.n_lanczos,
+                                     small.lo, small.hi, wl.poly_degree)
+        assert relerr(got[i], ref) <= 1e-8
+        assert np.all(np.isfinite(got[i]))
+
+
+def test_sigma_fp64_ragged(ragged, ctx_ragged):
+    _say("sigma fp64 ragged")
+    wl = ragged.wl
+    got = ctx_ragged.sigma_c(ragged.sys.qp_states, ragged.sys.omega_ev, wl.eta, wl.n_lanczos)
+    for i, m in enumerate(ragged.sys.qp_states):
+        ref = ragged.pr.sigma_lanczos(int(m), ragged.sys.omega_ev, wl.eta, wl.n_lanczos,
+                                      ragged.lo, ragged.hi, wl.poly_degree)
+        assert relerr(got[i], ref) <= 1e-8
+
+
+def test_sigma_mixed_small(small, ctx_small):
+    _say("sigma mixed small")
+    wl = small.wl
+    ctx_small.set_precision("mixed")
+    try:
+        got = ctx_small.sigma_c(small.sys.qp_states, small.sys.omega_ev, wl.eta, wl.n_lanczos)
+    finally:
+        ctx_small.set_precision("fp64")
+    for i, m in enumerate(small.sys.qp_states):
+        ref = small.pr.sigma_lanczos(int(m), small.sys.omega_ev, wl.eta, wl.n_lanczos,
+                                     small.lo, small.hi, wl.poly_degree)
+        assert np.max(np.abs(got[i] - ref)) <= 1e-3
+
+
+def test_sigma_mixed_smooth_stress(smooth):
+    """Smooth orbitals give eV-sized Sigma, so the 1 meV bar binds."""
+    _say("sigma mixed smooth")
+    wl = smooth.wl
+    ctx = make_ctx(smooth.sys, precision="mixed", interval=(smooth.lo, smooth.hi))
+    try:
+        got = ctx.sigma_c(smooth.sys.qp_states, smooth.sys.omega_ev, wl.eta, wl.n_lanczos)
+        ctx.set_precision("fp64")
+        got64 = ctx.sigma_c(smooth.sys.qp_states, smooth.sys.omega_ev, wl.eta, wl.n_lanczos)
+    finally:
+        ctx.close()
+    for i, m in enumerate(smooth.sys.qp_states):
+        ref = smooth.pr.sigma_lanczos(int(m), smooth.sys.omega_ev, wl.eta, wl.n_lanczos,
+                                      smooth.lo, smooth.hi, wl.poly_degree)
+        assert np.max(np.abs(ref)) > 0.1          # the stress variant is eV-sized
+        assert relerr(got64[i], ref) <= 1e-8
+        assert np.max(np.abs(got[i] - ref)) <= 1e-3
+
+
+def test_sigma_from_coeffs(small, ctx_small):
+    _say("continued fraction from oracle coefficients")
+    m = int(small.sys.qp_states[0])
+    ns = list(range(small.wl.n_orb))
+    coeffs = small.pr.lanczos_coeffs(m, 20, small.lo, small.hi, small.wl.poly_degree)
+    ld = 20
+    a = np.zeros((len(ns), ld))
+    b = np.zeros((len(ns), ld))
+    lens = np.zeros(len(ns), dtype=np.int32)
+    n2 = np.zeros(len(ns))
+    for i, (ra, rb, rn) in enumerate(coeffs):
+        a[i, :len(ra)] = ra
+        b[i, :len(rb)] = rb
+        lens[i] = len(ra)
+        n2[i] = rn
+    om = small.sys.omega_ev
+    got = ctx_small.sigma_from_coeffs(ns, a, b, n2, lens, om, small.wl.eta)
+    for i, n in enumerate(ns):
+        ref = S.sigma_n_from_tridiag(a[i, :lens[i]], b[i, :max(lens[i] - 1, 0)], n2[i],
+                                     om / oracle.HARTREE_EV, small.pr.eps[n], small.pr.eta(n),
+                                     small.wl.eta / oracle.HARTREE_EV) * oracle.HARTREE_EV
+        assert relerr(got[i], ref) <= 1e-12
+
+
+def test_reorth_modes_close(small):
+    _say("reorth none/local vs full")
+    wl = small.wl
+    ref = small.pr.sigma_lanczos(int(small.sys.qp_states[0]), small.sys.omega_ev, wl.eta,
+                                 wl.n_lanczos, small.lo, small.hi, wl.poly_degree)
+    for mode in ("local", "none"):
+        ctx = make_ctx(small.sys, interval=(small.lo, small.hi), reorth=mode)
+        try:
+            got = ctx.sigma_c(small.sys.qp_states[:1], small.sys.omega_ev, wl.eta, wl.n_lanczos)[0]
+        finally:
+            ctx.close()
+        assert relerr(got, ref) <= 1e-3
+
+
+def test_auto_interval_contains_spectrum(small):
+    _say("auto interval")
+    ctx = make_ctx(small.sys)
+    try:
+        lo, hi = ctx.interval
+    finally:
+        ctx.close()
+    emin, emax = small.pr.spectral_bounds()
+    assert lo <= emin * (1 + 1e-12)
+    assert hi >= emax
+    assert hi <= 1.1 * emax
+
+
+def test_determinism(small, ctx_small):
+    _say("determinism")
+    wl = small.wl
+    a = ctx_small.sigma_c(small.sys.qp_states, small.sys.omega_ev[:50], wl.eta, 16)
+    b = ctx_small.sigma_c(small.sys.qp_states, small.sys.omega_ev[:50], wl.eta, 16)
+    assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------------------ errors and edges
+def test_errors_and_empty(small, ctx_small):
+    import paper_2310_20103_amd as G
+    _say("errors")
+    s = small.sys
+    wl = small.wl
+    with pytest.raises(G.GwlError) as e:
+        G.Context(s.phi, s.energies_ev, 0, wl.grid, wl.box)
+    assert e.value.code == -1
+    bad_e = s.energies_ev.copy()
+    bad_e[wl.n_occ] = -20.0
+    with pytest.raises(G.GwlError) as e:
+        G.Context(s.phi, bad_e, wl.n_occ, wl.grid, wl.box)
+    assert e.value.code == -1
+    with pytest.raises(G.GwlError) as e:
+        G.Context(np.zeros((4, 7 * 8 * 8)), np.array([-5.0, -4.0, 1.0, 2.0]), 2, (7, 8, 8), 5.0)
+    assert e.value.code == -6
+    with pytest.raises(G.GwlError):
+        ctx_small.sigma_c([wl.n_orb], s.omega_ev, wl.eta, 4)
+    with pytest.raises(G.GwlError):
+        ctx_small.sigma_c([0], s.omega_ev, 0.0, 4)
+    with pytest.raises(G.GwlError):
+        ctx_small.sigma_c([0], s.omega_ev, wl.eta, 0)
+    out = ctx_small.sigma_c([], s.omega_ev, wl.eta, 4)
+    assert out.shape == (0, len(s.omega_ev))
+    out = ctx_small.sigma_c([0], [], wl.eta, 4)
+    assert out.shape == (1, 0)
+
+
+# ------------------------------------------------------------------ kernel variants
+@pytest.mark.parametrize("which", ["small", "ragged"])
+def test_mfma_matches_plain_kernels(request, which):
+    """The MFMA GEMMs against the plain FMA tiles on the same inputs."""
+    import paper_2310_20103_amd as G
+    case = request.getfixturevalue(which)
+    ctx = request.getfixturevalue("ctx_" + which)
+    _say("mfma vs plain", which)
+    x = torch.tensor(gi.random_pair_vectors(5, case.wl.n_vc, seed=9), device="cuda")
+    out = {}
+    for kern in (0, 1):
+        ctx.set_option(G.KEY_KERNELS, kern)
+        out[kern] = {p: ctx.apply_c(x, p).cpu().numpy() for p in ("fp64", "mixed")}
+    ctx.set_option(G.KEY_KERNELS, 1)
+    assert relerr(out[1]["fp64"], out[0]["fp64"]) <= 1e-13
+    assert relerr(out[1]["mixed"], out[0]["mixed"]) <= 1e-5
