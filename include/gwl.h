@@ -211,8 +211,19 @@ enum {
   GWL_KEY_PROF_VEC_GEMM2 = 19,
   GWL_KEY_PROF_MS_FFT = 20,     /* query: same for the Poisson solve (all five passes) */
   GWL_KEY_PROF_N_FFT = 21,
-  GWL_KEY_PROF_VEC_FFT = 22
+  GWL_KEY_PROF_VEC_FFT = 22,
+  GWL_KEY_GRAPHS = 23,          /* set/query: 1 (default) = replay a captured HIP graph of the
+                                   p_g(C) product each Lanczos step; 0 = launch eagerly.
+                                   Graphs are not used while GWL_KEY_PROFILE is on. */
+  GWL_KEY_TUNED_BLOCK = 24,     /* query: slots B chosen by the autotuner (block = 0) for the
+                                   current precision, 0 before the first tuned call */
+  GWL_KEY_TUNED_SPLITK = 25     /* query: split chosen with it */
 };
+/* The autotuner runs on the first gwl_sigma_c / gwl_sigma_c_range /
+ * gwl_lanczos_pairs call with block = 0: it times one C-product for
+ * B in {32, 64, 128, 256} and three splits of the second GEMM.  If the
+ * environment variable GWL_TUNE_CACHE names a file, choices are read from and
+ * appended to it (text: "gfx950:N_r:N_v:N_c:precision:kernels B split us"). */
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* gwl_last_error(void);

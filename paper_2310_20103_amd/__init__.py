@@ -7,6 +7,7 @@ of ``include/gwl.h``; this package is its Python binding.
 from .binding import (Context, GwlError, lib, FP64, MIXED_BF16, REORTH, PRECISIONS,  # noqa: F401
                       KEY_PRECISION, KEY_REORTH, KEY_BLOCK, KEY_POLY_LO, KEY_POLY_HI,
                       KEY_POLY_DEGREE, KEY_N_VC, KEY_LAST_MS_TOTAL, KEY_LAST_C_MATVECS,
-                      KEY_GEMM_SPLITK, KEY_KERNELS, KEY_PROFILE, KEY_PROF, LIB_PATH)
+                      KEY_GEMM_SPLITK, KEY_KERNELS, KEY_PROFILE, KEY_PROF, KEY_GRAPHS, KEY_TUNED_BLOCK,
+                      KEY_TUNED_SPLITK, LIB_PATH)
 
 __all__ = ["Context", "GwlError", "lib", "LIB_PATH"]

@@ -15,7 +15,9 @@
 // FP64: v_mfma_f64_16x16x4f64, block tile 128 x 128 x 16, 4 waves of 64 x 64.
 // BF16: v_mfma_f32_32x32x16_bf16 (FP32 accumulation), block tile
 //       256 x 128 x 32, 4 waves of 128 x 64.
-// Tiles are staged through LDS with the next K step prefetched into registers.
+// Tiles are staged through LDS with the next K step prefetched into registers
+// (BF16: two LDS stages, one barrier per K step).  Register budgets are held
+// to two waves per SIMD so that two blocks share a CU.
 // Block ids are remapped so that blocks sharing the large operand tile run on
 // the same XCD (one L2 per XCD).
 #include "common.h"
@@ -35,6 +37,28 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 __device__ inline int xcd_remap(int bid, int total) {
   if (total % 8 != 0) return bid;
   return (bid & 7) * (total >> 3) + (bid >> 3);
+}
+
+// Tile map of the first GEMM (mt x nt tiles, A = pair vectors is the small
+// operand, B = orbitals the large one).  With mt >= 8 each XCD owns a fixed
+// eighth of the M tiles, so its slice of A stays in that XCD's L2 while the
+// orbital tiles stream past once per XCD; with mt < 8 each XCD owns an eighth
+// of the N tiles instead.  Returns false for the padding blocks of the grid.
+__host__ __device__ inline int gemm1_grid(int mt, int nt) {
+  return mt >= 8 ? 8 * ((mt + 7) / 8) * nt : 8 * ((nt + 7) / 8) * mt;
+}
+__device__ inline bool gemm1_tile(int bid, int mt, int nt, int& mi, int& ni) {
+  const int x = bid & 7, loc = bid >> 3;
+  if (mt >= 8) {
+    const int mpx = (mt + 7) / 8;
+    mi = x * mpx + loc % mpx;
+    ni = loc / mpx;
+  } else {
+    const int npx = (nt + 7) / 8;
+    mi = loc % mt;
+    ni = x * npx + loc / mt;
+  }
+  return mi < mt && ni < nt;
 }
 
 // ---------------------------------------------------------------- FP64
@@ -128,15 +152,16 @@ __device__ inline void f64_mainloop(const LA& la, int M, const double* __restric
   }
 }
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 gemm1_f64m_kernel(GemmDims d, int M, int nb, const double* __restrict__ psi_c_rc,
                   const double* __restrict__ psi_v_rv, const double* __restrict__ u,
                   double* __restrict__ rho_part) {
   __shared__ double As[DM][DLD];
   __shared__ double Bs[DN][DLD];
   const int mt = (M + DM - 1) / DM, nt = d.nrp / DN;
-  const int lid = xcd_remap(blockIdx.x, mt * nt);
-  const int m0 = (lid % mt) * DM, n0 = (lid / mt) * DN;
+  int mi, ni;
+  if (!gemm1_tile(blockIdx.x, mt, nt, mi, ni)) return;
+  const int m0 = mi * DM, n0 = ni * DN;
   d4 acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -165,7 +190,7 @@ gemm1_f64m_kernel(GemmDims d, int M, int nb, const double* __restrict__ psi_c_rc
   }
 }
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 gemm2_f64m_kernel(GemmDims d, int M, int splitk, int kchunk, const double* __restrict__ psi_v_t,
                   const double* __restrict__ psi_c_t, const double* __restrict__ vpot,
                   double* __restrict__ ypart) {
@@ -204,59 +229,103 @@ gemm2_f64m_kernel(GemmDims d, int M, int splitk, int kchunk, const double* __res
 
 // ---------------------------------------------------------------- BF16
 constexpr int HM = 256, HN = 128, HK = 32, HLD = HK + 8;  // LDS row: 40 bf16 = 80 B
-constexpr int HWN = HN / 64;  // 32-column blocks per wave (2 waves along N)
+constexpr int HWN = HN / 64;                              // 32-col blocks per wave
+constexpr int HQB = HN * 4 / 256;                         // 16-B B chunks per thread
+
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
 
 __device__ inline bf8 lds_frag(const bf16_t* p) {
   return __builtin_bit_cast(bf8, *reinterpret_cast<const u4*>(p));
 }
+// two floats -> packed bf16 pair, round to nearest even (v_cvt_pk_bf16_f32)
+__device__ inline unsigned pack_bf16(float a, float b) {
+  const bf2 v = {(__bf16)a, (__bf16)b};
+  return __builtin_bit_cast(unsigned, v);
+}
+__device__ inline float lo_bf16(unsigned u) { return __builtin_bit_cast(float, u << 16); }
+__device__ inline float hi_bf16(unsigned u) { return __builtin_bit_cast(float, u & 0xffff0000u); }
 
-struct LoadU16 {  // plain [M][K] bf16 rows; 8 values per chunk
+// A-tile loaders: thread t owns chunks idx = t + 256 q (q < 4) of the
+// 256 x 32 tile, row = idx / 4 = t/4 + 64 q, k offset 8 (t % 4).
+struct LoadU16 {  // plain [M][K] rows
   const bf16_t* a;
   long lda;
-  __device__ u4 load(int m, int k) const {
-    return *reinterpret_cast<const u4*>(a + (long)m * lda + k);
+  __device__ void load4(int m0, int M, int t, int k0, u4 (&ra)[4]) const {
+    const int kc = (t & 3) * 8;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int m = m0 + (t >> 2) + 64 * q;
+      ra[q] = m < M ? *reinterpret_cast<const u4*>(a + (long)m * lda + k0 + kc) : u4{0, 0, 0, 0};
+    }
   }
 };
-struct LoadPsiV16 {  // A[(b,v)][r] = bf16(phi_v(r) V_b(r))
+
+// A[(b,v)][r] = bf16(phi_v(r) V_b(r)).  NVP = padded N_v when it is 64 or 128
+// (the four rows of a thread then share one or two phi_v rows), 0 otherwise.
+template <int NVP>
+struct LoadPsiV16 {
   const bf16_t* psi_v_t;
   const float* vpot;
   long nrp;
   int nvp;
-  __device__ u4 load(int m, int k) const {
-    const int b = m / nvp, vv = m - b * nvp;
-    const u4 pv = *reinterpret_cast<const u4*>(psi_v_t + (long)vv * nrp + k);
-    const f4v v0 = *reinterpret_cast<const f4v*>(vpot + (long)b * nrp + k);
-    const f4v v1 = *reinterpret_cast<const f4v*>(vpot + (long)b * nrp + k + 4);
-    const float vv8[8] = {v0[0], v0[1], v0[2], v0[3], v1[0], v1[1], v1[2], v1[3]};
+  __device__ static u4 scale(u4 pv, const float* vp) {
+    const f4v v0 = *reinterpret_cast<const f4v*>(vp);
+    const f4v v1 = *reinterpret_cast<const f4v*>(vp + 4);
     u4 out;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const unsigned lo = pv[i] & 0xffffu, hi = pv[i] >> 16;
-      const float a0 = bf16_to_f32((bf16_t)lo) * vv8[2 * i];
-      const float a1 = bf16_to_f32((bf16_t)hi) * vv8[2 * i + 1];
-      out[i] = (unsigned)f32_to_bf16(a0) | ((unsigned)f32_to_bf16(a1) << 16);
-    }
+    out[0] = pack_bf16(lo_bf16(pv[0]) * v0[0], hi_bf16(pv[0]) * v0[1]);
+    out[1] = pack_bf16(lo_bf16(pv[1]) * v0[2], hi_bf16(pv[1]) * v0[3]);
+    out[2] = pack_bf16(lo_bf16(pv[2]) * v1[0], hi_bf16(pv[2]) * v1[1]);
+    out[3] = pack_bf16(lo_bf16(pv[3]) * v1[2], hi_bf16(pv[3]) * v1[3]);
     return out;
+  }
+  __device__ void load4(int m0, int M, int t, int k0, u4 (&ra)[4]) const {
+    const int k = k0 + (t & 3) * 8;
+    const int r0 = t >> 2;
+    if constexpr (NVP == 64) {
+      const u4 pv = *reinterpret_cast<const u4*>(psi_v_t + (long)r0 * nrp + k);
+      const int b0 = m0 / 64;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        ra[q] = (m0 + r0 + 64 * q < M) ? scale(pv, vpot + (long)(b0 + q) * nrp + k)
+                                       : u4{0, 0, 0, 0};
+    } else if constexpr (NVP == 128) {
+      const u4 pa = *reinterpret_cast<const u4*>(psi_v_t + (long)r0 * nrp + k);
+      const u4 pb = *reinterpret_cast<const u4*>(psi_v_t + (long)(r0 + 64) * nrp + k);
+      const int b0 = m0 / 128;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const bool ok = m0 + r0 + 64 * q < M;
+        ra[q] = ok ? scale((q & 1) ? pb : pa, vpot + (long)(b0 + (q >> 1)) * nrp + k)
+                   : u4{0, 0, 0, 0};
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = m0 + r0 + 64 * q;
+        if (m < M) {
+          const int b = m / nvp, vv = m - b * nvp;
+          const u4 pv = *reinterpret_cast<const u4*>(psi_v_t + (long)vv * nrp + k);
+          ra[q] = scale(pv, vpot + (long)b * nrp + k);
+        } else {
+          ra[q] = u4{0, 0, 0, 0};
+        }
+      }
+    }
   }
 };
 
-// acc += A[m0.., k] B[n0.., k], k in [kb, ke); B rows beyond nvalid are zero.
-constexpr int HQB = HN * 4 / 256;  // 16-byte B chunks per thread per K step
-
+// acc += A[m0.., k] B[n0.., k], k in [kb, ke), two LDS stages (one barrier
+// per K step); B rows at or beyond nvalid read as zero.
 template <typename LA>
 __device__ inline void bf16_mainloop(const LA& la, int M, const bf16_t* __restrict__ bop, long ldb,
                                      int nvalid, int m0, int n0, int kb, int ke,
-                                     bf16_t (*As)[HLD], bf16_t (*Bs)[HLD], f16v (&acc)[4][HWN]) {
+                                     bf16_t (*As)[HM][HLD], bf16_t (*Bs)[HN][HLD],
+                                     f16v (&acc)[4][HWN]) {
   const int t = threadIdx.x, l = t & 63, w = t >> 6;
   const int wm = w >> 1, wn = w & 1;
   u4 ra[4], rb[HQB];
   auto gload = [&](int k0) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int idx = t + 256 * q;
-      const int row = idx >> 2, kc = (idx & 3) * 8;
-      ra[q] = (m0 + row < M) ? la.load(m0 + row, k0 + kc) : u4{0, 0, 0, 0};
-    }
+    la.load4(m0, M, t, k0, ra);
 #pragma unroll
     for (int q = 0; q < HQB; ++q) {
       const int idx = t + 256 * q;
@@ -266,25 +335,24 @@ __device__ inline void bf16_mainloop(const LA& la, int M, const bf16_t* __restri
                   : u4{0, 0, 0, 0};
     }
   };
-  auto lstore = [&]() {
+  auto lstore = [&](int buf) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int idx = t + 256 * q;
-      const int row = idx >> 2, kc = (idx & 3) * 8;
-      *reinterpret_cast<u4*>(&As[row][kc]) = ra[q];
+      *reinterpret_cast<u4*>(&As[buf][idx >> 2][(idx & 3) * 8]) = ra[q];
     }
 #pragma unroll
     for (int q = 0; q < HQB; ++q) {
       const int idx = t + 256 * q;
-      const int row = idx >> 2, kc = (idx & 3) * 8;
-      *reinterpret_cast<u4*>(&Bs[row][kc]) = rb[q];
+      *reinterpret_cast<u4*>(&Bs[buf][idx >> 2][(idx & 3) * 8]) = rb[q];
     }
   };
   if (kb < ke) {
     gload(kb);
-    lstore();
+    lstore(0);
   }
   __syncthreads();
+  int cur = 0;
   for (int k0 = kb; k0 < ke; k0 += HK) {
     const bool more = k0 + HK < ke;
     if (more) gload(k0 + HK);
@@ -293,44 +361,63 @@ __device__ inline void bf16_mainloop(const LA& la, int M, const bf16_t* __restri
       bf8 a[4];
       const int kk = 16 * ks + 8 * (l >> 5);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = lds_frag(&As[wm * 128 + 32 * i + (l & 31)][kk]);
+      for (int i = 0; i < 4; ++i) a[i] = lds_frag(&As[cur][wm * 128 + 32 * i + (l & 31)][kk]);
 #pragma unroll
       for (int j = 0; j < HWN; ++j) {
-        const bf8 b = lds_frag(&Bs[wn * (HN / 2) + 32 * j + (l & 31)][kk]);
+        const bf8 b = lds_frag(&Bs[cur][wn * (HN / 2) + 32 * j + (l & 31)][kk]);
 #pragma unroll
         for (int i = 0; i < 4; ++i)
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b, acc[i][j], 0, 0, 0);
       }
     }
+    if (more) lstore(cur ^ 1);
     __syncthreads();
-    if (more) {
-      lstore();
-      __syncthreads();
-    }
+    cur ^= 1;
   }
 }
 
-// SEG = 32-row blocks that belong to one pair vector within a wave's 128
-// rows: 4 when N_v (padded) >= 128, 2 when it is 64.
-template <int SEG>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+struct BfSmem {
+  bf16_t As[2][HM][HLD];
+  bf16_t Bs[2][HN][HLD];
+};
+
+// First GEMM.  NVP = padded N_v if 64 or 128: the epilogue weights phi_v(r)
+// of the block's 128 columns are staged once in LDS and shared by both
+// M-waves; NVP = 0 (N_v padded to a multiple of 256): every wave reads its
+// own 128 weights per column from global memory.
+template <int NVP>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 gemm1_bf16_kernel(GemmDims d, int M, int nb, const bf16_t* __restrict__ psi_c_rc,
-                  const float* __restrict__ psi_v_rv, const bf16_t* __restrict__ u,
+                  const bf16_t* __restrict__ psi_v_rv, const bf16_t* __restrict__ u,
                   float* __restrict__ rho_part) {
-  __shared__ bf16_t As[HM][HLD];
-  __shared__ bf16_t Bs[HN][HLD];
+  __shared__ BfSmem sm;
   const int mt = (M + HM - 1) / HM, nt = d.nrp / HN;
-  const int lid = xcd_remap(blockIdx.x, mt * nt);
-  const int m0 = (lid % mt) * HM, n0 = (lid / mt) * HN;
+  int mi, ni;
+  if (!gemm1_tile(blockIdx.x, mt, nt, mi, ni)) return;
+  const int m0 = mi * HM, n0 = ni * HN;
   f16v acc[4][HWN];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < HWN; ++j) acc[i][j] = f16v{};
   LoadU16 la{u, d.ncp};
-  bf16_mainloop(la, M, psi_c_rc, d.ncp, d.nrp, m0, n0, 0, d.ncp, As, Bs, acc);
-  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  bf16_mainloop(la, M, psi_c_rc, d.ncp, d.nrp, m0, n0, 0, d.ncp, sm.As, sm.Bs, acc);
+
+  const int t = threadIdx.x, l = t & 63, w = t >> 6;
   const int wm = w >> 1, wn = w & 1;
+  constexpr int SEG = (NVP == 64) ? 2 : 4;       // 32-row blocks per pair vector segment
+  constexpr int WLD = (NVP > 0 ? NVP : 0) + 8;   // LDS row of staged weights
+  bf16_t* wl = &sm.As[0][0][0];
+  if constexpr (NVP > 0) {
+    // weights phi_v(r), r in [n0, n0 + 128), v in [0, NVP): one copy per block
+    constexpr int CH = NVP / 8;  // 16-byte chunks per row
+    for (int idx = t; idx < HN * CH; idx += 256) {
+      const int rr = idx / CH, cc = (idx - rr * CH) * 8;
+      *reinterpret_cast<u4*>(wl + rr * WLD + cc) =
+          *reinterpret_cast<const u4*>(psi_v_rv + (long)(n0 + rr) * d.nvp + cc);
+    }
+    __syncthreads();
+  }
   const int mw = m0 + wm * 128;
 #pragma unroll
   for (int sg = 0; sg < 4; sg += SEG) {
@@ -340,31 +427,43 @@ gemm1_bf16_kernel(GemmDims d, int M, int nb, const bf16_t* __restrict__ psi_c_rc
       const int vt = vbase / 128;
 #pragma unroll
       for (int j = 0; j < HWN; ++j) {
-        const int r = n0 + wn * (HN / 2) + 32 * j + (l & 31);
-        const float* wr = psi_v_rv + (long)r * d.nvp + vbase + 4 * (l >> 5);
+        const int rl = wn * (HN / 2) + 32 * j + (l & 31);
         float s = 0.f;
 #pragma unroll
         for (int i = 0; i < SEG; ++i) {
 #pragma unroll
           for (int g = 0; g < 4; ++g) {
-            const f4v wv = *reinterpret_cast<const f4v*>(wr + 32 * i + 8 * g);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) s += wv[q] * acc[sg + i][j][4 * g + q];
+            const int v = vbase + 32 * i + 8 * g + 4 * (l >> 5);
+            unsigned w01, w23;
+            if constexpr (NVP > 0) {
+              const unsigned* p = reinterpret_cast<const unsigned*>(wl + rl * WLD + v);
+              w01 = p[0];
+              w23 = p[1];
+            } else {
+              const unsigned* p = reinterpret_cast<const unsigned*>(
+                  psi_v_rv + (long)(n0 + rl) * d.nvp + v);
+              w01 = p[0];
+              w23 = p[1];
+            }
+            s += lo_bf16(w01) * acc[sg + i][j][4 * g + 0];
+            s += hi_bf16(w01) * acc[sg + i][j][4 * g + 1];
+            s += lo_bf16(w23) * acc[sg + i][j][4 * g + 2];
+            s += hi_bf16(w23) * acc[sg + i][j][4 * g + 3];
           }
         }
         s += __shfl_xor(s, 32, 64);
-        if (l < 32) rho_part[((long)vt * nb + b) * d.nrp + r] = s;
+        if (l < 32) rho_part[((long)vt * nb + b) * d.nrp + n0 + rl] = s;
       }
     }
   }
 }
 
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+template <int NVP>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 gemm2_bf16_kernel(GemmDims d, int M, int splitk, int kchunk, const bf16_t* __restrict__ psi_v_t,
                   const bf16_t* __restrict__ psi_c_t, const float* __restrict__ vpot,
                   float* __restrict__ ypart) {
-  __shared__ bf16_t As[HM][HLD];
-  __shared__ bf16_t Bs[HN][HLD];
+  __shared__ BfSmem sm;
   const int mt = (M + HM - 1) / HM, nt = (d.ncp + HN - 1) / HN;
   const int lid = xcd_remap(blockIdx.x, mt * nt * splitk);
   const int s = lid / (mt * nt);
@@ -377,8 +476,8 @@ gemm2_bf16_kernel(GemmDims d, int M, int splitk, int kchunk, const bf16_t* __res
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < HWN; ++j) acc[i][j] = f16v{};
-  LoadPsiV16 la{psi_v_t, vpot, d.nrp, d.nvp};
-  bf16_mainloop(la, M, psi_c_t, d.nrp, d.ncp, m0, n0, kb, ke, As, Bs, acc);
+  LoadPsiV16<NVP> la{psi_v_t, vpot, d.nrp, d.nvp};
+  bf16_mainloop(la, M, psi_c_t, d.nrp, d.ncp, m0, n0, kb, ke, sm.As, sm.Bs, acc);
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wm = w >> 1, wn = w & 1;
   float* out = ypart + (long)s * M * d.ncp;
@@ -404,7 +503,7 @@ void gemm1_f64m(const GemmDims& d, int nb, const double* psi_c_rc, const double*
                 const double* u, double* rho_part, hipStream_t st) {
   if (nb <= 0) return;
   const int M = nb * d.nvp;
-  const int blocks = ceil_div(M, DM) * (d.nrp / DN);
+  const int blocks = gemm1_grid(ceil_div(M, DM), d.nrp / DN);
   gemm1_f64m_kernel<<<blocks, 256, 0, st>>>(d, M, nb, psi_c_rc, psi_v_rv, u, rho_part);
   GWL_HIP(hipGetLastError());
 }
@@ -421,16 +520,22 @@ void gemm2_f64m(const GemmDims& d, int nb, int splitk, const double* psi_v_t,
 
 int gemm1_bf16_vtiles(const GemmDims& d) { return d.nvp >= 128 ? d.nvp / 128 : 1; }
 
-void gemm1_bf16(const GemmDims& d, int nb, const bf16_t* psi_c_rc, const float* psi_v_rv,
+void gemm1_bf16(const GemmDims& d, int nb, const bf16_t* psi_c_rc, const bf16_t* psi_v_rv,
                 const bf16_t* u, float* rho_part, hipStream_t st) {
   if (nb <= 0) return;
   const int M = nb * d.nvp;
-  const int blocks = ceil_div(M, HM) * (d.nrp / HN);
-  if (d.nvp >= 128)
-    gemm1_bf16_kernel<4><<<blocks, 256, 0, st>>>(d, M, nb, psi_c_rc, psi_v_rv, u, rho_part);
+  const int blocks = gemm1_grid(ceil_div(M, HM), d.nrp / HN);
+  if (d.nvp == 64)
+    gemm1_bf16_kernel<64><<<blocks, 256, 0, st>>>(d, M, nb, psi_c_rc, psi_v_rv, u, rho_part);
+  else if (d.nvp == 128)
+    gemm1_bf16_kernel<128><<<blocks, 256, 0, st>>>(d, M, nb, psi_c_rc, psi_v_rv, u, rho_part);
   else
-    gemm1_bf16_kernel<2><<<blocks, 256, 0, st>>>(d, M, nb, psi_c_rc, psi_v_rv, u, rho_part);
+    gemm1_bf16_kernel<0><<<blocks, 256, 0, st>>>(d, M, nb, psi_c_rc, psi_v_rv, u, rho_part);
   GWL_HIP(hipGetLastError());
+}
+
+int gemm2_bf16_blocks(const GemmDims& d, int nb) {
+  return ceil_div(nb * d.nvp, HM) * ceil_div(d.ncp, HN);
 }
 
 void gemm2_bf16(const GemmDims& d, int nb, int splitk, const bf16_t* psi_v_t,
@@ -438,9 +543,18 @@ void gemm2_bf16(const GemmDims& d, int nb, int splitk, const bf16_t* psi_v_t,
   if (nb <= 0) return;
   const int M = nb * d.nvp;
   const int kchunk = (int)round_up(ceil_div(d.nrp, splitk), HK);
-  const int blocks = ceil_div(M, HM) * ceil_div(d.ncp, HN) * splitk;
-  gemm2_bf16_kernel<<<blocks, 256, 0, st>>>(d, M, splitk, kchunk, psi_v_t, psi_c_t, vpot, ypart);
+  const int blocks = gemm2_bf16_blocks(d, nb) * splitk;
+  if (d.nvp == 64)
+    gemm2_bf16_kernel<64><<<blocks, 256, 0, st>>>(d, M, splitk, kchunk, psi_v_t, psi_c_t, vpot, ypart);
+  else if (d.nvp == 128)
+    gemm2_bf16_kernel<128><<<blocks, 256, 0, st>>>(d, M, splitk, kchunk, psi_v_t, psi_c_t, vpot, ypart);
+  else
+    gemm2_bf16_kernel<0><<<blocks, 256, 0, st>>>(d, M, splitk, kchunk, psi_v_t, psi_c_t, vpot, ypart);
   GWL_HIP(hipGetLastError());
+}
+
+int gemm2_f64m_blocks(const GemmDims& d, int nb) {
+  return ceil_div(nb * d.nvp, DM) * ceil_div(d.ncp, DN);
 }
 
 }  // namespace gwl

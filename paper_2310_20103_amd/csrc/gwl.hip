@@ -9,6 +9,8 @@
 // coupling vector is built on the spot.  All coefficients stay on the device
 // until the continued fraction has produced Sigma.
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -151,7 +153,8 @@ struct gwl_ctx {
   DevBuf<double> psi_v_rv64;  // [NRp][NVp]
   DevBuf<bf16_t> psi_t16;     // [NVp + NCp][NRp]
   DevBuf<bf16_t> psi_c_rc16;  // [NRp][NCp]
-  DevBuf<float> psi_v_rv32;   // [NRp][NVp]
+  DevBuf<float> psi_v_rv32;   // [NRp][NVp] (plain BF16 kernel epilogue)
+  DevBuf<bf16_t> psi_v_rv16;  // [NRp][NVp] (MFMA BF16 kernel epilogue)
   DevBuf<double> delta2, sdelta;
 
   // FFT tables
@@ -188,6 +191,20 @@ struct gwl_ctx {
   // statistics of the last call
   double last_ms_total = 0;
   long last_c_matvecs = 0;
+
+  // captured graph of one p_g(C) product over the Lanczos slots (q -> w)
+  int use_graphs = 1;
+  hipGraphExec_t dgraph = nullptr;
+  int dg_nb = -1, dg_prec = -1, dg_S = -1, dg_kern = -1, dg_deg = -1;
+  double dg_lo = 0, dg_hi = 0;
+  long work_gen = 0, dg_gen = -1;
+
+  // autotuned (block, split) per precision
+  struct Tune {
+    int B = 0, S = 0;
+    double us_per_vec = 0;
+  };
+  Tune tuned[2];
 
   // optional per-launch timing with HIP events on the context stream
   int profile = 0;
@@ -262,18 +279,31 @@ struct gwl_ctx {
                     std::max(gemm1_f64m_vtiles(gd), gemm1_bf16_vtiles(gd)));
   }
 
-  int auto_splitk(int nb) const {
+  // Split of the grid sum in the second GEMM: enough blocks to give every
+  // CU several (the kernels run one wave per SIMD), each block keeping a
+  // K range of at least 2048 grid points.
+  int auto_splitk(int nb, int prec) const {
     if (splitk > 0) return splitk;
-    // enough blocks to fill 256 CUs several times over
-    const long tiles = (long)nb * (gd.nvp / 64) * (gd.ncp / 64);
+    if (tuned[prec].B == nb && tuned[prec].S > 0) return tuned[prec].S;
+    return heuristic_splitk(nb, prec);
+  }
+  int heuristic_splitk(int nb, int prec) const {
+    long blocks;
+    if (!fp64_kernel)
+      blocks = (long)nb * (gd.nvp / 64) * ceil_div(gd.ncp, 64);
+    else if (prec == GWL_FP64)
+      blocks = gemm2_f64m_blocks(gd, nb);
+    else
+      blocks = gemm2_bf16_blocks(gd, nb);
     int s = 1;
-    while (tiles * s < 2048 && s < 32 && (long)gd.nrp / (s * 2) >= 1024) s *= 2;
+    while (blocks * s < 1024 && s < 32 && (long)gd.nrp / (s * 2) >= 2048) s *= 2;
     return s;
   }
 
   void ensure_work(int nb, int Lrows, bool need_basis) {
     const long nvpc = (long)gd.nvp * gd.ncp;
     if (nb > cap) {
+      ++work_gen;
       q.ensure((size_t)nb * nvc);
       qprev.ensure((size_t)nb * nvc);
       w.ensure((size_t)nb * nvc);
@@ -345,7 +375,7 @@ struct gwl_ctx {
       int nvt;
       prof_begin();
       if (fp64_kernel) {
-        gemm1_bf16(gd, nb, psi_c_rc16.p, psi_v_rv32.p, uu, rp, st);
+        gemm1_bf16(gd, nb, psi_c_rc16.p, psi_v_rv16.p, uu, rp, st);
         nvt = gemm1_bf16_vtiles(gd);
       } else {
         gemm1_bf16s(gd, nb, psi_c_rc16.p, psi_v_rv32.p, uu, rp, st);
@@ -365,7 +395,6 @@ struct gwl_ctx {
         gemm2_bf16s(gd, nb, S, pv, pc, vp, yp, st);
       prof_end(1, nb);
     }
-    last_c_matvecs += nb;
   }
 
   void cast(int nb, const double* x, int prec) {
@@ -391,7 +420,8 @@ struct gwl_ctx {
 
   // out = C x for nb vectors (x, out device [nb][nvc]); uses u, ypart.
   void apply_c_batch(int nb, const double* x, double* out, int prec) {
-    const int S = auto_splitk(nb);
+    const int S = auto_splitk(nb, prec);
+    last_c_matvecs += nb;
     cast(nb, x, prec);
     k_product(nb, prec, S);
     do_combine(nb, S, prec, x, nullptr, out, nullptr, 0, 0, 0, false);
@@ -401,7 +431,7 @@ struct gwl_ctx {
   // u_ready, else casts.  x is not modified; uses ta, tb.
   void apply_d_batch(int nb, const double* x, double* acc, int prec, bool u_ready) {
     const int g = poly_degree;
-    const int S = auto_splitk(nb);
+    const int S = auto_splitk(nb, prec);
     if (!u_ready) cast(nb, x, prec);
     // t1 = C~ x, acc = c0 x + c1 t1
     k_product(nb, prec, S);
@@ -436,7 +466,7 @@ struct gwl_ctx {
     pair_product(psi_t.p, gd.nrp, (int)nr, s_m.p, s_n.p, cnt, rp, stream);
     poisson_launch<double>(pg64, rp, gd.nrp, 0, 1, vp, gd.nrp, cnt,
                            reinterpret_cast<cplx<double>*>(fftx.p), stream);
-    const int S = auto_splitk(cnt);
+    const int S = auto_splitk(cnt, GWL_FP64);
     const double* pv = psi_t.p;
     const double* pc = psi_t.p + (size_t)gd.nvp * gd.nrp;
     if (fp64_kernel)
@@ -446,6 +476,145 @@ struct gwl_ctx {
     coupling_finish<double>(pair_geom(), cnt, S, yp, dst, ldp, stream);
   }
 
+  // w = p_g(C) q over nb slots; replays a captured graph of the whole product
+  // (g x [first GEMM, five FFT passes, second GEMM, combine] + cast) when the
+  // shapes and buffers are unchanged.
+  void apply_d_step(int nb, int prec) {
+    last_c_matvecs += (long)nb * poly_degree;
+    const int S = auto_splitk(nb, prec);
+    if (!use_graphs || profile) {
+      apply_d_batch(nb, q.p, w.p, prec, false);
+      return;
+    }
+    if (!dgraph || dg_nb != nb || dg_prec != prec || dg_S != S || dg_kern != fp64_kernel ||
+        dg_gen != work_gen || dg_deg != poly_degree || dg_lo != poly_lo || dg_hi != poly_hi) {
+      drop_graph();
+      hipGraph_t g = nullptr;
+      GWL_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+      try {
+        apply_d_batch(nb, q.p, w.p, prec, false);
+      } catch (...) {
+        (void)hipStreamEndCapture(stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      GWL_HIP(hipStreamEndCapture(stream, &g));
+      const hipError_t e = hipGraphInstantiate(&dgraph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) {
+        dgraph = nullptr;
+        throw Error{GWL_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e)};
+      }
+      dg_nb = nb;
+      dg_prec = prec;
+      dg_S = S;
+      dg_kern = fp64_kernel;
+      dg_gen = work_gen;
+      dg_deg = poly_degree;
+      dg_lo = poly_lo;
+      dg_hi = poly_hi;
+    }
+    GWL_HIP(hipGraphLaunch(dgraph, stream));
+  }
+
+  void drop_graph() {
+    if (dgraph) (void)hipGraphExecDestroy(dgraph);
+    dgraph = nullptr;
+  }
+
+  // ---------------------------------------------------------------- autotuner
+  // Pick the number of Lanczos slots B and the split of the second GEMM by
+  // timing one C-product per candidate with HIP events on the context
+  // stream; the time per pair vector decides.  Results are kept per context
+  // and, when GWL_TUNE_CACHE names a file, shared through it (one line per
+  // problem shape: "key B S us_per_vector").
+  std::string tune_key(int prec) const {
+    return "gfx950:" + std::to_string(nr) + ":" + std::to_string(nv) + ":" +
+           std::to_string(nc) + ":" + std::to_string(prec) + ":" + std::to_string(fp64_kernel);
+  }
+
+  bool tune_cache_read(int prec, Tune& t) const {
+    const char* path = std::getenv("GWL_TUNE_CACHE");
+    if (!path || !*path) return false;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    char key[256];
+    int b = 0, sk = 0;
+    double us = 0;
+    bool found = false;
+    const std::string want = tune_key(prec);
+    while (std::fscanf(f, "%255s %d %d %lf", key, &b, &sk, &us) == 4)
+      if (want == key && b > 0 && sk > 0) {
+        t.B = b;
+        t.S = sk;
+        t.us_per_vec = us;
+        found = true;
+      }
+    std::fclose(f);
+    return found;
+  }
+
+  void tune_cache_write(int prec, const Tune& t) const {
+    const char* path = std::getenv("GWL_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d %d %.3f\n", tune_key(prec).c_str(), t.B, t.S, t.us_per_vec);
+    std::fclose(f);
+  }
+
+  Tune autotune(int prec, int bmax) {
+    Tune best = tuned[prec];
+    if (best.B > 0) return best;
+    if (tune_cache_read(prec, best)) {
+      tuned[prec] = best;
+      return best;
+    }
+    const int cands[] = {32, 64, 128, 256};
+    hipEvent_t e0, e1;
+    GWL_HIP(hipEventCreate(&e0));
+    GWL_HIP(hipEventCreate(&e1));
+    best.us_per_vec = 1e300;
+    try {
+      for (int B : cands) {
+        if (B > bmax && B != cands[0]) break;
+        ensure_work(B, 1, false);
+        const int s0 = heuristic_splitk(B, prec);
+        for (int S : {s0 / 2, s0, s0 * 2}) {
+          if (S < 1 || S > 32 || (S > 1 && (long)gd.nrp / S < 1024)) continue;
+          cast(B, q.p, prec);
+          k_product(B, prec, S);  // warm
+          GWL_HIP(hipEventRecord(e0, stream));
+          for (int r = 0; r < 2; ++r) k_product(B, prec, S);
+          GWL_HIP(hipEventRecord(e1, stream));
+          GWL_HIP(hipEventSynchronize(e1));
+          float ms = 0;
+          GWL_HIP(hipEventElapsedTime(&ms, e0, e1));
+          const double us = 1e3 * ms / 2 / B;
+          if (us < best.us_per_vec * 0.97) {
+            best.B = B;
+            best.S = S;
+            best.us_per_vec = us;
+          }
+        }
+      }
+    } catch (...) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (best.B <= 0) {  // nothing timed: fall back to the memory rule and heuristic split
+      best.B = std::max(1, std::min(bmax, 128));
+      best.S = heuristic_splitk(best.B, prec);
+      best.us_per_vec = 0;
+    }
+    tuned[prec] = best;
+    tune_cache_write(prec, best);
+    return best;
+  }
+
   // ---------------------------------------------------------------- scheduler
   // Run Lanczos on p_g(C) (or on C itself when on_c) for P start vectors
   // (m_i, n_i) with lengths len_i.  Coefficients land in coef_a/coef_b
@@ -453,8 +622,14 @@ struct gwl_ctx {
   void run_pairs(int P, const int* m_host, const int* n_host, const int* len_host, int ld,
                  bool on_c = false, const double* start_dev = nullptr) {
     const int prec = precision;
-    int B = block > 0 ? block : auto_block(P, ld);
-    B = std::min(B, P);
+    int B;
+    if (block > 0) {
+      B = block;
+    } else {
+      const int bmem = auto_block(1 << 30, ld);  // memory cap on slots
+      B = std::min(autotune(prec, bmem).B, bmem);
+    }
+    B = std::max(1, std::min(B, P));
     const bool full = (reorth == GWL_REORTH_FULL);
     ensure_work(B, ld, full);
     coef_a.ensure((size_t)P * ld);
@@ -539,9 +714,9 @@ struct gwl_ctx {
       if (!any) break;
       // one Lanczos step for every slot
       if (on_c)
-        apply_c_batch(B, q.p, w.p, prec == GWL_FP64 ? GWL_FP64 : prec);
+        apply_c_batch(B, q.p, w.p, prec);
       else
-        apply_d_batch(B, q.p, w.p, prec, false);
+        apply_d_step(B, prec);
       lz_alpha(ss, B, q.p, qprev.p, w.p, nvc, stream);
       lz_reorth(ss, B, kmax, reorth, full ? basis.p : nullptr, bstride, q.p, qprev.p, w.p,
                 hbuf.p, nvc, stream);
@@ -804,10 +979,16 @@ gwl_status gwl_setup(const void* orbitals, int orb_dtype, int orb_on_device, int
       for (size_t i = 0; i < host.size(); ++i) t16[i] = f32_to_bf16((float)host[i]);
       for (size_t i = 0; i < crc.size(); ++i) c16[i] = f32_to_bf16((float)crc[i]);
       std::vector<float> v32(vrv.size());
-      for (size_t i = 0; i < vrv.size(); ++i) v32[i] = (float)vrv[i];
+      std::vector<bf16_t> v16(vrv.size());
+      for (size_t i = 0; i < vrv.size(); ++i) {
+        v32[i] = (float)vrv[i];
+        v16[i] = f32_to_bf16(v32[i]);
+      }
       c.psi_t16.ensure(t16.size());
       c.psi_c_rc16.ensure(c16.size());
       c.psi_v_rv32.ensure(v32.size());
+      c.psi_v_rv16.ensure(v16.size());
+      GWL_HIP(hipMemcpy(c.psi_v_rv16.p, v16.data(), v16.size() * 2, hipMemcpyHostToDevice));
       GWL_HIP(hipMemcpy(c.psi_t16.p, t16.data(), t16.size() * 2, hipMemcpyHostToDevice));
       GWL_HIP(hipMemcpy(c.psi_c_rc16.p, c16.data(), c16.size() * 2, hipMemcpyHostToDevice));
       GWL_HIP(hipMemcpy(c.psi_v_rv32.p, v32.data(), v32.size() * 4, hipMemcpyHostToDevice));
@@ -859,6 +1040,7 @@ void gwl_destroy(gwl_ctx* ctx) {
   if (!ctx) return;
   (void)hipStreamSynchronize(ctx->stream);
   for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
+  ctx->drop_graph();
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
@@ -891,6 +1073,11 @@ gwl_status gwl_set_option(gwl_ctx* ctx, int key, double value) {
         GWL_CHECK(value == 0 || value == 1, GWL_EINVAL, "profile must be 0 or 1");
         ctx->profile = (int)value;
         break;
+      case GWL_KEY_GRAPHS:
+        GWL_CHECK(value == 0 || value == 1, GWL_EINVAL, "graphs must be 0 or 1");
+        ctx->use_graphs = (int)value;
+        if (!ctx->use_graphs) ctx->drop_graph();
+        break;
       default:
         throw Error{GWL_EINVAL, "unknown or read-only option key"};
     }
@@ -914,6 +1101,9 @@ gwl_status gwl_query(gwl_ctx* ctx, int key, double* out) {
       case GWL_KEY_GEMM_SPLITK: *out = ctx->splitk; break;
       case GWL_KEY_KERNELS: *out = ctx->fp64_kernel; break;
       case GWL_KEY_PROFILE: *out = ctx->profile; break;
+      case GWL_KEY_GRAPHS: *out = ctx->use_graphs; break;
+      case GWL_KEY_TUNED_BLOCK: *out = ctx->tuned[ctx->precision].B; break;
+      case GWL_KEY_TUNED_SPLITK: *out = ctx->tuned[ctx->precision].S; break;
       case GWL_KEY_PROF_MS_GEMM1: *out = ctx->prof_ms[0]; break;
       case GWL_KEY_PROF_N_GEMM1: *out = (double)ctx->prof_n[0]; break;
       case GWL_KEY_PROF_VEC_GEMM1: *out = (double)ctx->prof_vec[0]; break;
@@ -988,6 +1178,7 @@ gwl_status gwl_apply_d(gwl_ctx* ctx, const double* x, double* y, int n_vec, int 
     ctx->ensure_work(chunk, 1, false);
     for (int i0 = 0; i0 < n_vec; i0 += chunk) {
       const int nb = std::min(chunk, n_vec - i0);
+      ctx->last_c_matvecs += (long)nb * ctx->poly_degree;
       ctx->apply_d_batch(nb, x + (size_t)i0 * ctx->nvc, y + (size_t)i0 * ctx->nvc, precision,
                          false);
     }

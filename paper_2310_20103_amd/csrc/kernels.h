@@ -46,11 +46,11 @@ struct GemmDims {
   int nr, nrp, nv, nvp, nc, ncp;
 };
 
-// Padding: N_r to 256; N_c to 64; N_v to 64 when N_v <= 64, else to 128 (the
-// BF16 tile reduces over 128 occupied orbitals of one pair vector at a time).
+// Padding: N_r to 256; N_c to 64; N_v to 64, 128 or a multiple of 256 (the
+// BF16 tile of 256 rows must hold whole pair vectors or lie inside one).
 constexpr int kPadR = 256;
 constexpr int kPadC = 64;
-inline int pad_nv(int nv) { return nv <= 64 ? 64 : (int)round_up(nv, 128); }
+inline int pad_nv(int nv) { return nv <= 64 ? 64 : (nv <= 128 ? 128 : (int)round_up(nv, 256)); }
 
 // FP64 (plain tiled FMA; reference-quality GPU path).
 int gemm1_f64_vtiles(const GemmDims& d);
@@ -75,8 +75,10 @@ void gemm2_f64m(const GemmDims& d, int nb, int splitk, const double* psi_v_t,
 
 // BF16 operands, FP32 accumulation, on MFMA.
 int gemm1_bf16_vtiles(const GemmDims& d);
-void gemm1_bf16(const GemmDims& d, int nb, const bf16_t* psi_c_rc, const float* psi_v_rv,
+void gemm1_bf16(const GemmDims& d, int nb, const bf16_t* psi_c_rc, const bf16_t* psi_v_rv,
                 const bf16_t* u, float* rho_part, hipStream_t st);
+int gemm2_bf16_blocks(const GemmDims& d, int nb);  // blocks per split of the K range
+int gemm2_f64m_blocks(const GemmDims& d, int nb);
 void gemm2_bf16(const GemmDims& d, int nb, int splitk, const bf16_t* psi_v_t,
                 const bf16_t* psi_c_t, const float* vpot, float* ypart, hipStream_t st);
 

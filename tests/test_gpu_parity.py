@@ -199,7 +199,7 @@ def test_breakdown_short_fraction():
         m = int(case.sys.qp_states[0])
         ns = list(range(case.wl.n_orb))
         a, b, n2, ol = ctx.lanczos_pairs([m] * len(ns), ns, [12] * len(ns))
-        assert np.all(ol <= 6)
+        assert np.all(ol <= 6) and np.all(ol >= 1)
         om = case.sys.omega_ev
         got = ctx.sigma_c([m], om, case.wl.eta, 12)[0]
         ref = case.pr.sigma_lanczos(m, om, case.wl.eta, 12, case.lo, case.hi, case.wl.poly_degree)
@@ -370,3 +370,36 @@ def test_mfma_matches_plain_kernels(request, which):
     ctx.set_option(G.KEY_KERNELS, 1)
     assert relerr(out[1]["fp64"], out[0]["fp64"]) <= 1e-13
     assert relerr(out[1]["mixed"], out[0]["mixed"]) <= 1e-5
+
+
+# ------------------------------------------------------------------ graphs and tuner
+def test_graph_replay_matches_eager(small):
+    """Each Lanczos step replays the captured p_g(C) graph with eager vector
+    kernels and host synchronisation in between; every replay feeds a_k, so
+    equal coefficient arrays check every replay against eager launches."""
+    import paper_2310_20103_amd as G
+    _say("graph replay vs eager")
+    m = int(small.sys.qp_states[0])
+    ns = list(range(0, small.wl.n_orb, 2))
+    out = {}
+    for graphs in (0, 1):
+        ctx = make_ctx(small.sys, interval=(small.lo, small.hi), block=7)
+        try:
+            ctx.set_option(G.KEY_GRAPHS, graphs)
+            for p in ("fp64", "mixed"):
+                ctx.set_precision(p)
+                out[(graphs, p)] = ctx.lanczos_pairs([m] * len(ns), ns, [24] * len(ns))
+        finally:
+            ctx.close()
+    for p in ("fp64", "mixed"):
+        for a, b in zip(out[(0, p)], out[(1, p)]):
+            assert np.array_equal(a, b)
+
+
+def test_autotuner_choice(small, ctx_small):
+    import paper_2310_20103_amd as G
+    _say("autotuner")
+    wl = small.wl
+    ctx_small.sigma_c(small.sys.qp_states[:1], small.sys.omega_ev[:4], wl.eta, 2)
+    assert ctx_small.query(G.KEY_TUNED_BLOCK) in (32, 64, 128, 256)
+    assert 1 <= ctx_small.query(G.KEY_TUNED_SPLITK) <= 32
