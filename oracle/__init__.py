@@ -35,5 +35,5 @@ in the module docstrings where they apply.  Parity pins for every function
 are in ``tests/test_oracle_*.py``.
 """
 
-from . import poisson, casida, chebyshev, sigma  # noqa: F401
+from . import poisson, casida, chebyshev, sigma, adjoint  # noqa: F401
 from .sigma import HARTREE_EV, Problem, default_interval  # noqa: F401
