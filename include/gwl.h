@@ -159,6 +159,27 @@ gwl_status gwl_sigma_from_coeffs(gwl_ctx* ctx, const int* n_idx, int n_pairs,
                                  const double* omega_ev, int n_omega,
                                  double eta_ev, double* sigma_out);
 
+/* Vector-Jacobian product of the self-energy (reverse-mode derivative).
+ * For the scalar l = sum_{q,w} Re(conj(G_qw) Sigma_q(w)) with
+ *   grad_sigma  host [n_qp][n_omega][2]: G (re, im), per eV of Sigma,
+ * returns
+ *   grad_energies  host [n_orb]: dl/de_a (per eV of energy),
+ *   grad_orbitals  device float64 [n_orb][nx*ny*nz]: dl/dphi_a(r),
+ *   sigma_out      host [n_qp][n_omega][2] or NULL: the forward Sigma (eV).
+ * The forward is the path of gwl_sigma_c in FP64 with the three-term
+ * recurrence only (no reorthogonalisation, so the Lanczos vectors can be
+ * recomputed exactly from checkpoints every ceil(sqrt(L)) steps instead of
+ * being stored); the derivative is exact for that forward.  Orbitals are free
+ * variables (no orthonormality constraint), occupations and the Chebyshev
+ * interval [lo, hi] are held fixed.  Holds a dense N_vc x N_vc coupling
+ * cotangent and the N_vc pair potentials (GWL_EUNSUPPORTED when too large);
+ * n_lanczos <= 1024.  The paper defines the forward (Eqs. 7-14); the adjoint
+ * is this library's. */
+gwl_status gwl_sigma_c_vjp(gwl_ctx* ctx, const int* qp_states, int n_qp,
+                           const double* omega_ev, int n_omega, double eta_ev, int n_lanczos,
+                           const double* grad_sigma, double* sigma_out,
+                           double* grad_energies, double* grad_orbitals);
+
 /* ---- component entry points (the steps of the path, for parity checks) ---- */
 
 /* Hartree potential V = FFT^-1[kernel_scale 4 pi/|G|^2 FFT[rho]] of n_fields

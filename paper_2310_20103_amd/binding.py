@@ -58,6 +58,7 @@ _SIGS = {
     "gwl_sigma_c_range": (_I, [_P, _P, _I, _I, _I, _P, _I, _D, _I, _P]),
     "gwl_lanczos_pairs": (_I, [_P, _P, _P, _P, _I, _P, _P, _P, _P, _I]),
     "gwl_sigma_from_coeffs": (_I, [_P, _P, _I, _P, _P, _P, _P, _I, _P, _I, _D, _P]),
+    "gwl_sigma_c_vjp": (_I, [_P, _P, _I, _P, _I, _D, _I, _P, _P, _P, _P]),
     "gwl_poisson": (_I, [_P, _P, _P, _I, _I]),
     "gwl_apply_c": (_I, [_P, _P, _P, _I, _I]),
     "gwl_apply_d": (_I, [_P, _P, _P, _I, _I]),
@@ -248,6 +249,25 @@ class Context:
                                        _ptr(om), len(om), float(eta_ev), int(n_lanczos),
                                        _ptr(out)))
         return out[..., 0] + 1j * out[..., 1]
+
+    def sigma_c_vjp(self, qp_states, omega_ev, eta_ev: float, n_lanczos: int, grad_sigma,
+                    device="cuda"):
+        """Reverse-mode derivative of l = sum Re(conj(G) Sigma): returns
+        (Sigma [n_qp, n_omega] complex eV, dl/d energies [n_orb] per eV,
+        dl/d orbitals torch float64 [n_orb, N_r] on the device)."""
+        import torch
+        q = _i32(qp_states)
+        om = _f64(omega_ev)
+        G = np.asarray(grad_sigma, dtype=np.complex128).reshape(len(q), len(om))
+        g2 = np.ascontiguousarray(np.stack([G.real, G.imag], axis=-1))
+        sig = np.zeros((len(q), len(om), 2))
+        ge = np.zeros(self.n_orb)
+        go = torch.empty((self.n_orb, self.n_r), dtype=torch.float64, device=device)
+        _sync_torch()
+        _check(lib().gwl_sigma_c_vjp(self._h, _ptr(q), len(q), _ptr(om), len(om), float(eta_ev),
+                                     int(n_lanczos), _ptr(g2), _ptr(sig), _ptr(ge),
+                                     _dev(go, torch.float64)))
+        return sig[..., 0] + 1j * sig[..., 1], ge, go
 
     def lanczos_pairs(self, m_idx, n_idx, lengths, ld: Optional[int] = None):
         """(alpha [P, ld], beta [P, ld], norm2 [P], out_len [P]) in hartree units."""

@@ -1,0 +1,779 @@
+// Context of the Lanczos GW self-energy library: device buffers, options,
+// the batched Lanczos scheduler and the product drivers.  Shared by the
+// C-ABI entry points (gwl.hip) and the vector-Jacobian product (vjp.hip).
+#pragma once
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace gwl {
+
+
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  // (Re)allocate to at least cnt elements, zero-filled.  Contents are not kept.
+  void ensure(size_t cnt) {
+    if (cnt <= n) return;
+    release();
+    if (cnt == 0) return;
+    hipError_t e = hipMalloc((void**)&p, cnt * sizeof(T));
+    if (e != hipSuccess) {
+      p = nullptr;
+      throw Error{GWL_ENOMEM, "hipMalloc of " + std::to_string(cnt * sizeof(T)) +
+                                  " bytes failed: " + hipGetErrorString(e)};
+    }
+    n = cnt;
+    GWL_HIP(hipMemset(p, 0, cnt * sizeof(T)));
+    GWL_HIP(hipDeviceSynchronize());
+  }
+};
+
+// Chebyshev interpolation coefficients of sqrt on [lo, hi] at the g+1
+// first-kind Chebyshev points: c_j = (2 - [j=0])/(g+1) sum_k sqrt(x_k) cos(j th_k).
+inline std::vector<double> cheb_sqrt(double lo, double hi, int g) {
+  std::vector<double> c(g + 1, 0.0);
+  for (int j = 0; j <= g; ++j) {
+    double s = 0.0;
+    for (int k = 0; k <= g; ++k) {
+      const double th = kPi * (k + 0.5) / (g + 1);
+      const double x = 0.5 * (hi + lo) + 0.5 * (hi - lo) * std::cos(th);
+      s += std::sqrt(x) * std::cos(j * th);
+    }
+    c[j] = 2.0 * s / (g + 1);
+  }
+  c[0] *= 0.5;
+  return c;
+}
+
+// Eigenvalues/vectors of a small symmetric matrix by cyclic Jacobi rotations.
+inline void jacobi_eig(int n, std::vector<double>& a, std::vector<double>& vec) {
+  vec.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) vec[(size_t)i * n + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = i + 1; j < n; ++j) off += a[(size_t)i * n + j] * a[(size_t)i * n + j];
+    if (off < 1e-30) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = a[(size_t)p * n + q];
+        if (std::fabs(apq) < 1e-300) continue;
+        const double app = a[(size_t)p * n + p], aqq = a[(size_t)q * n + q];
+        const double th = 0.5 * (aqq - app) / apq;
+        const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < n; ++k) {
+          const double akp = a[(size_t)k * n + p], akq = a[(size_t)k * n + q];
+          a[(size_t)k * n + p] = c * akp - s * akq;
+          a[(size_t)k * n + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double apk = a[(size_t)p * n + k], aqk = a[(size_t)q * n + k];
+          a[(size_t)p * n + k] = c * apk - s * aqk;
+          a[(size_t)q * n + k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double vkp = vec[(size_t)k * n + p], vkq = vec[(size_t)k * n + q];
+          vec[(size_t)k * n + p] = c * vkp - s * vkq;
+          vec[(size_t)k * n + q] = s * vkp + c * vkq;
+        }
+      }
+  }
+}
+
+inline bool finite_all(const double* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+}  // namespace gwl
+
+using namespace gwl;
+
+
+struct gwl_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+
+  int nx = 0, ny = 0, nz = 0;
+  double lx = 0, ly = 0, lz = 0;
+  long nr = 0;
+  int n_orb = 0, nv = 0, nc = 0;
+  long nvc = 0;
+  GemmDims gd{};
+  double dv = 0;
+
+  int precision = GWL_FP64;
+  int poly_degree = 7;
+  double poly_lo = 0, poly_hi = 0;
+  int reorth = GWL_REORTH_FULL;
+  int block = 0;
+  double kernel_scale = 1.0;
+  int splitk = 0;  // 0 = automatic
+  int fp64_kernel = 1;  // 0 = plain FMA tiles, 1 = MFMA (both precisions)
+  std::vector<double> cheb;
+  std::vector<double> eps_ha;
+
+  // operands
+  DevBuf<double> psi_t;       // [NVp + NCp][NRp]
+  DevBuf<double> psi_c_rc64;  // [NRp][NCp]
+  DevBuf<double> psi_v_rv64;  // [NRp][NVp]
+  DevBuf<bf16_t> psi_t16;     // [NVp + NCp][NRp]
+  DevBuf<bf16_t> psi_c_rc16;  // [NRp][NCp]
+  DevBuf<float> psi_v_rv32;   // [NRp][NVp] (plain BF16 kernel epilogue)
+  DevBuf<bf16_t> psi_v_rv16;  // [NRp][NVp] (MFMA BF16 kernel epilogue)
+  DevBuf<double> delta2, sdelta;
+
+  // FFT tables
+  DevBuf<cplx<double>> tw64[3];
+  DevBuf<cplx<float>> tw32[3];
+  DevBuf<double> g2_64[3];
+  DevBuf<float> g2_32[3];
+  PoissonGeom<double> pg64{};
+  PoissonGeom<float> pg32{};
+
+  // work buffers
+  int cap = 0;      // slot capacity of the buffers below
+  int cap_L = 0;    // basis rows per slot
+  DevBuf<double> q, qprev, w, ta, tb;
+  // Operand buffers are kept per precision: their zero pads (v >= N_v,
+  // c >= N_c, r >= N_r) are written once at allocation and must never hold
+  // the other precision's bytes.
+  DevBuf<double> u64;          // [cap][NVp][NCp]
+  DevBuf<bf16_t> u16;          // [cap][NVp][NCp]
+  DevBuf<unsigned char> rho;   // [nvt][cap][NRp] x 8 (fully written by the first GEMM)
+  DevBuf<double> vpot64;       // [cap][NRp]
+  DevBuf<float> vpot32;        // [cap][NRp]
+  DevBuf<unsigned char> fftx;  // [(cap+1)/2][N_r] x 16
+  DevBuf<unsigned char> ypart; // [S][cap][NVp][NCp] x 8
+  DevBuf<double> basis;        // [cap][cap_L][nvc]
+  DevBuf<double> hbuf;         // [cap][cap_L + 1]
+  DevBuf<int> s_pair, s_k, s_len, s_dead, s_slots, s_m, s_n;
+  DevBuf<double> s_amax, s_bprev;
+  // per-call pair data
+  DevBuf<double> coef_a, coef_b, norm2;
+  DevBuf<int> out_len;
+  DevBuf<double> sig, sig_sum, e_n, eta_n, omega;
+
+  // statistics of the last call
+  double last_ms_total = 0;
+  long last_c_matvecs = 0;
+
+  // captured graph of one p_g(C) product over the Lanczos slots (q -> w)
+  int use_graphs = 1;
+  hipGraphExec_t dgraph = nullptr;
+  int dg_nb = -1, dg_prec = -1, dg_S = -1, dg_kern = -1, dg_deg = -1;
+  double dg_lo = 0, dg_hi = 0;
+  long work_gen = 0, dg_gen = -1;
+
+  // autotuned (block, split) per precision
+  struct Tune {
+    int B = 0, S = 0;
+    double us_per_vec = 0;
+  };
+  Tune tuned[2];
+
+  // optional per-launch timing with HIP events on the context stream
+  int profile = 0;
+  std::vector<hipEvent_t> ev_pool;
+  struct ProfRec {
+    int kind, e0, e1, nvec;
+  };
+  std::vector<ProfRec> prof_recs;
+  double prof_ms[3] = {0, 0, 0};
+  long prof_n[3] = {0, 0, 0}, prof_vec[3] = {0, 0, 0};
+
+  void prof_reset() {
+    prof_recs.clear();
+    for (int i = 0; i < 3; ++i) prof_ms[i] = 0, prof_n[i] = 0, prof_vec[i] = 0;
+  }
+  int prof_event() {
+    const int idx = (int)prof_recs.size() * 2;
+    while ((int)ev_pool.size() <= idx) {
+      hipEvent_t e;
+      GWL_HIP(hipEventCreate(&e));
+      ev_pool.push_back(e);
+    }
+    return idx;
+  }
+  int prof_open = -1;
+  void prof_begin() {
+    if (!profile) return;
+    const int e = prof_event();
+    GWL_HIP(hipEventRecord(ev_pool[e], stream));
+    prof_open = e;
+  }
+  void prof_end(int kind, int nvec) {
+    if (!profile) return;
+    const int e0 = prof_open;
+    prof_open = -1;
+    const int e1 = (int)prof_recs.size() * 2 + 1;
+    while ((int)ev_pool.size() <= e1) {
+      hipEvent_t e;
+      GWL_HIP(hipEventCreate(&e));
+      ev_pool.push_back(e);
+    }
+    GWL_HIP(hipEventRecord(ev_pool[e1], stream));
+    prof_recs.push_back({kind, e0, e1, nvec});
+  }
+  // Accumulate recorded intervals; the stream must be idle.
+  void prof_flush() {
+    for (const auto& r : prof_recs) {
+      float ms = 0.f;
+      GWL_HIP(hipEventElapsedTime(&ms, ev_pool[r.e0], ev_pool[r.e1]));
+      prof_ms[r.kind] += ms;
+      prof_n[r.kind] += 1;
+      prof_vec[r.kind] += r.nvec;
+    }
+    prof_recs.clear();
+  }
+
+  PairGeom pair_geom() const {
+    PairGeom g;
+    g.nv = nv;
+    g.nc = nc;
+    g.nvp = gd.nvp;
+    g.ncp = gd.ncp;
+    g.nvc = nvc;
+    g.delta2 = delta2.p;
+    g.sdelta = sdelta.p;
+    g.dv = dv;
+    return g;
+  }
+
+  int nvt_max() const {
+    return std::max(std::max(gemm1_f64_vtiles(gd), gemm1_bf16s_vtiles(gd)),
+                    std::max(gemm1_f64m_vtiles(gd), gemm1_bf16_vtiles(gd)));
+  }
+
+  // Split of the grid sum in the second GEMM: enough blocks to give every
+  // CU several (the kernels run one wave per SIMD), each block keeping a
+  // K range of at least 2048 grid points.
+  int auto_splitk(int nb, int prec) const {
+    if (splitk > 0) return splitk;
+    if (tuned[prec].B == nb && tuned[prec].S > 0) return tuned[prec].S;
+    return heuristic_splitk(nb, prec);
+  }
+  int heuristic_splitk(int nb, int prec) const {
+    long blocks;
+    if (!fp64_kernel)
+      blocks = (long)nb * (gd.nvp / 64) * ceil_div(gd.ncp, 64);
+    else if (prec == GWL_FP64)
+      blocks = gemm2_f64m_blocks(gd, nb);
+    else
+      blocks = gemm2_bf16_blocks(gd, nb);
+    int s = 1;
+    while (blocks * s < 1024 && s < 32 && (long)gd.nrp / (s * 2) >= 2048) s *= 2;
+    return s;
+  }
+
+  void ensure_work(int nb, int Lrows, bool need_basis) {
+    const long nvpc = (long)gd.nvp * gd.ncp;
+    if (nb > cap) {
+      ++work_gen;
+      q.ensure((size_t)nb * nvc);
+      qprev.ensure((size_t)nb * nvc);
+      w.ensure((size_t)nb * nvc);
+      ta.ensure((size_t)nb * nvc);
+      tb.ensure((size_t)nb * nvc);
+      u64.ensure((size_t)nb * nvpc);
+      u16.ensure((size_t)alloc_rows_u(nb, gd.nvp) * gd.ncp);
+      rho.ensure((size_t)nvt_max() * nb * gd.nrp * 8);
+      vpot64.ensure((size_t)nb * gd.nrp);
+      vpot32.ensure((size_t)alloc_rows_v(nb, gd.nvp) * gd.nrp);
+      fftx.ensure((size_t)((nb + 1) / 2) * nr * 16);
+      ypart.ensure((size_t)32 * nb * nvpc * 8);
+      s_pair.ensure(nb);
+      s_k.ensure(nb);
+      s_len.ensure(nb);
+      s_dead.ensure(nb);
+      s_slots.ensure(nb);
+      s_m.ensure(nb);
+      s_n.ensure(nb);
+      s_amax.ensure(nb);
+      s_bprev.ensure(nb);
+      cap = nb;
+    }
+    if (Lrows + 1 > cap_L || nb * (size_t)(Lrows + 1) > hbuf.n) {
+      hbuf.ensure((size_t)nb * (Lrows + 2));
+      cap_L = std::max(cap_L, Lrows + 1);
+    }
+    if (need_basis) basis.ensure((size_t)nb * Lrows * nvc);
+  }
+
+  int orb_row(int n) const { return n < nv ? n : gd.nvp + (n - nv); }
+
+  // ---------------------------------------------------------------- products
+  // ypart <- second GEMM of K applied to u (u already cast for nb vectors).
+  void k_product(int nb, int prec, int S) {
+    hipStream_t st = stream;
+    if (prec == GWL_FP64) {
+      const double* uu = u64.p;
+      double* rp = reinterpret_cast<double*>(rho.p);
+      double* vp = vpot64.p;
+      double* yp = reinterpret_cast<double*>(ypart.p);
+      int nvt;
+      prof_begin();
+      if (fp64_kernel) {
+        gemm1_f64m(gd, nb, psi_c_rc64.p, psi_v_rv64.p, uu, rp, st);
+        nvt = gemm1_f64m_vtiles(gd);
+      } else {
+        gemm1_f64(gd, nb, psi_c_rc64.p, psi_v_rv64.p, uu, rp, st);
+        nvt = gemm1_f64_vtiles(gd);
+      }
+      prof_end(0, nb);
+      prof_begin();
+      poisson_launch<double>(pg64, rp, gd.nrp, (long)nb * gd.nrp, nvt, vp, gd.nrp, nb,
+                             reinterpret_cast<cplx<double>*>(fftx.p), st);
+      prof_end(2, nb);
+      const double* pv = psi_t.p;
+      const double* pc = psi_t.p + (size_t)gd.nvp * gd.nrp;
+      prof_begin();
+      if (fp64_kernel)
+        gemm2_f64m(gd, nb, S, pv, pc, vp, yp, st);
+      else
+        gemm2_f64(gd, nb, S, pv, pc, vp, yp, st);
+      prof_end(1, nb);
+    } else {
+      const bf16_t* uu = u16.p;
+      float* rp = reinterpret_cast<float*>(rho.p);
+      float* vp = vpot32.p;
+      float* yp = reinterpret_cast<float*>(ypart.p);
+      int nvt;
+      prof_begin();
+      if (fp64_kernel) {
+        gemm1_bf16(gd, nb, psi_c_rc16.p, psi_v_rv16.p, uu, rp, st);
+        nvt = gemm1_bf16_vtiles(gd);
+      } else {
+        gemm1_bf16s(gd, nb, psi_c_rc16.p, psi_v_rv32.p, uu, rp, st);
+        nvt = gemm1_bf16s_vtiles(gd);
+      }
+      prof_end(0, nb);
+      prof_begin();
+      poisson_launch<float>(pg32, rp, gd.nrp, (long)nb * gd.nrp, nvt, vp, gd.nrp, nb,
+                            reinterpret_cast<cplx<float>*>(fftx.p), st);
+      prof_end(2, nb);
+      const bf16_t* pv = psi_t16.p;
+      const bf16_t* pc = psi_t16.p + (size_t)gd.nvp * gd.nrp;
+      prof_begin();
+      if (fp64_kernel)
+        gemm2_bf16(gd, nb, S, pv, pc, vp, yp, st);
+      else
+        gemm2_bf16s(gd, nb, S, pv, pc, vp, yp, st);
+      prof_end(1, nb);
+    }
+  }
+
+  void cast(int nb, const double* x, int prec) {
+    PairGeom g = pair_geom();
+    if (prec == GWL_FP64)
+      cast_u<double>(g, nb, x, nvc, u64.p, stream);
+    else
+      cast_u<bf16_t>(g, nb, x, nvc, u16.p, stream);
+  }
+
+  void do_combine(int nb, int S, int prec, const double* x, const double* tp, double* out,
+                  double* acc, int mode, double c0, double cj, bool write_u) {
+    PairGeom g = pair_geom();
+    if (prec == GWL_FP64)
+      combine<double, double>(g, nb, S, reinterpret_cast<const double*>(ypart.p), x, tp, out,
+                              acc, mode, poly_lo, poly_hi, c0, cj,
+                              write_u ? u64.p : nullptr, stream);
+    else
+      combine<float, bf16_t>(g, nb, S, reinterpret_cast<const float*>(ypart.p), x, tp, out,
+                             acc, mode, poly_lo, poly_hi, c0, cj,
+                             write_u ? u16.p : nullptr, stream);
+  }
+
+  // out = C x for nb vectors (x, out device [nb][nvc]); uses u, ypart.
+  void apply_c_batch(int nb, const double* x, double* out, int prec) {
+    const int S = auto_splitk(nb, prec);
+    last_c_matvecs += nb;
+    cast(nb, x, prec);
+    k_product(nb, prec, S);
+    do_combine(nb, S, prec, x, nullptr, out, nullptr, 0, 0, 0, false);
+  }
+
+  // acc = p_g(C) x.  Expects u = cast(Delta^1/2 x) already in place when
+  // u_ready, else casts.  x is not modified; uses ta, tb.
+  void apply_d_batch(int nb, const double* x, double* acc, int prec, bool u_ready) {
+    const int g = poly_degree;
+    const int S = auto_splitk(nb, prec);
+    if (!u_ready) cast(nb, x, prec);
+    // t1 = C~ x, acc = c0 x + c1 t1
+    k_product(nb, prec, S);
+    double* t_prev = const_cast<double*>(x);
+    double* t_cur = ta.p;
+    do_combine(nb, S, prec, x, nullptr, t_cur, acc, 1, cheb[0], cheb[1], g >= 2);
+    double* spare = tb.p;
+    for (int j = 2; j <= g; ++j) {
+      k_product(nb, prec, S);
+      // t_j = 2 C~ t_{j-1} - t_{j-2}; written over t_{j-2} unless that is x
+      double* out = (t_prev == x) ? spare : t_prev;
+      do_combine(nb, S, prec, t_cur, t_prev, out, acc, 2, 0.0, cheb[j], j < g);
+      t_prev = t_cur;
+      t_cur = out;
+    }
+  }
+
+  // Coupling vectors of cnt (m, n) pairs into rows dst (device [cnt][ldp]).
+  void coupling_batch(int cnt, const int* m_host, const int* n_host, double* dst, long ldp) {
+    ensure_work(cnt, 1, false);
+    std::vector<int> mr(cnt), nrw(cnt);
+    for (int i = 0; i < cnt; ++i) {
+      mr[i] = orb_row(m_host[i]);
+      nrw[i] = orb_row(n_host[i]);
+    }
+    GWL_HIP(hipStreamSynchronize(stream));
+    GWL_HIP(hipMemcpy(s_m.p, mr.data(), cnt * sizeof(int), hipMemcpyHostToDevice));
+    GWL_HIP(hipMemcpy(s_n.p, nrw.data(), cnt * sizeof(int), hipMemcpyHostToDevice));
+    double* rp = reinterpret_cast<double*>(rho.p);
+    double* vp = vpot64.p;
+    double* yp = reinterpret_cast<double*>(ypart.p);
+    pair_product(psi_t.p, gd.nrp, (int)nr, s_m.p, s_n.p, cnt, rp, stream);
+    poisson_launch<double>(pg64, rp, gd.nrp, 0, 1, vp, gd.nrp, cnt,
+                           reinterpret_cast<cplx<double>*>(fftx.p), stream);
+    const int S = auto_splitk(cnt, GWL_FP64);
+    const double* pv = psi_t.p;
+    const double* pc = psi_t.p + (size_t)gd.nvp * gd.nrp;
+    if (fp64_kernel)
+      gemm2_f64m(gd, cnt, S, pv, pc, vp, yp, stream);
+    else
+      gemm2_f64(gd, cnt, S, pv, pc, vp, yp, stream);
+    coupling_finish<double>(pair_geom(), cnt, S, yp, dst, ldp, stream);
+  }
+
+  // w = p_g(C) q over nb slots; replays a captured graph of the whole product
+  // (g x [first GEMM, five FFT passes, second GEMM, combine] + cast) when the
+  // shapes and buffers are unchanged.
+  void apply_d_step(int nb, int prec) {
+    last_c_matvecs += (long)nb * poly_degree;
+    const int S = auto_splitk(nb, prec);
+    if (!use_graphs || profile) {
+      apply_d_batch(nb, q.p, w.p, prec, false);
+      return;
+    }
+    if (!dgraph || dg_nb != nb || dg_prec != prec || dg_S != S || dg_kern != fp64_kernel ||
+        dg_gen != work_gen || dg_deg != poly_degree || dg_lo != poly_lo || dg_hi != poly_hi) {
+      drop_graph();
+      hipGraph_t g = nullptr;
+      GWL_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+      try {
+        apply_d_batch(nb, q.p, w.p, prec, false);
+      } catch (...) {
+        (void)hipStreamEndCapture(stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      GWL_HIP(hipStreamEndCapture(stream, &g));
+      const hipError_t e = hipGraphInstantiate(&dgraph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) {
+        dgraph = nullptr;
+        throw Error{GWL_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e)};
+      }
+      dg_nb = nb;
+      dg_prec = prec;
+      dg_S = S;
+      dg_kern = fp64_kernel;
+      dg_gen = work_gen;
+      dg_deg = poly_degree;
+      dg_lo = poly_lo;
+      dg_hi = poly_hi;
+    }
+    GWL_HIP(hipGraphLaunch(dgraph, stream));
+  }
+
+  void drop_graph() {
+    if (dgraph) (void)hipGraphExecDestroy(dgraph);
+    dgraph = nullptr;
+  }
+
+  // ---------------------------------------------------------------- autotuner
+  // Pick the number of Lanczos slots B and the split of the second GEMM by
+  // timing one C-product per candidate with HIP events on the context
+  // stream; the time per pair vector decides.  Results are kept per context
+  // and, when GWL_TUNE_CACHE names a file, shared through it (one line per
+  // problem shape: "key B S us_per_vector").
+  std::string tune_key(int prec) const {
+    return "gfx950:" + std::to_string(nr) + ":" + std::to_string(nv) + ":" +
+           std::to_string(nc) + ":" + std::to_string(prec) + ":" + std::to_string(fp64_kernel);
+  }
+
+  bool tune_cache_read(int prec, Tune& t) const {
+    const char* path = std::getenv("GWL_TUNE_CACHE");
+    if (!path || !*path) return false;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    char key[256];
+    int b = 0, sk = 0;
+    double us = 0;
+    bool found = false;
+    const std::string want = tune_key(prec);
+    while (std::fscanf(f, "%255s %d %d %lf", key, &b, &sk, &us) == 4)
+      if (want == key && b > 0 && sk > 0) {
+        t.B = b;
+        t.S = sk;
+        t.us_per_vec = us;
+        found = true;
+      }
+    std::fclose(f);
+    return found;
+  }
+
+  void tune_cache_write(int prec, const Tune& t) const {
+    const char* path = std::getenv("GWL_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d %d %.3f\n", tune_key(prec).c_str(), t.B, t.S, t.us_per_vec);
+    std::fclose(f);
+  }
+
+  Tune autotune(int prec, int bmax) {
+    Tune best = tuned[prec];
+    if (best.B > 0) return best;
+    if (tune_cache_read(prec, best)) {
+      tuned[prec] = best;
+      return best;
+    }
+    const int cands[] = {32, 64, 128, 256};
+    hipEvent_t e0, e1;
+    GWL_HIP(hipEventCreate(&e0));
+    GWL_HIP(hipEventCreate(&e1));
+    best.us_per_vec = 1e300;
+    try {
+      for (int B : cands) {
+        if (B > bmax && B != cands[0]) break;
+        ensure_work(B, 1, false);
+        const int s0 = heuristic_splitk(B, prec);
+        for (int S : {s0 / 2, s0, s0 * 2}) {
+          if (S < 1 || S > 32 || (S > 1 && (long)gd.nrp / S < 1024)) continue;
+          cast(B, q.p, prec);
+          k_product(B, prec, S);  // warm
+          GWL_HIP(hipEventRecord(e0, stream));
+          for (int r = 0; r < 2; ++r) k_product(B, prec, S);
+          GWL_HIP(hipEventRecord(e1, stream));
+          GWL_HIP(hipEventSynchronize(e1));
+          float ms = 0;
+          GWL_HIP(hipEventElapsedTime(&ms, e0, e1));
+          const double us = 1e3 * ms / 2 / B;
+          if (us < best.us_per_vec * 0.97) {
+            best.B = B;
+            best.S = S;
+            best.us_per_vec = us;
+          }
+        }
+      }
+    } catch (...) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (best.B <= 0) {  // nothing timed: fall back to the memory rule and heuristic split
+      best.B = std::max(1, std::min(bmax, 128));
+      best.S = heuristic_splitk(best.B, prec);
+      best.us_per_vec = 0;
+    }
+    tuned[prec] = best;
+    tune_cache_write(prec, best);
+    return best;
+  }
+
+  // ---------------------------------------------------------------- scheduler
+  // Run Lanczos on p_g(C) (or on C itself when on_c) for P start vectors
+  // (m_i, n_i) with lengths len_i.  Coefficients land in coef_a/coef_b
+  // ([P][ld]), norm2 [P], out_len [P] on the device.
+  void run_pairs(int P, const int* m_host, const int* n_host, const int* len_host, int ld,
+                 bool on_c = false, const double* start_dev = nullptr) {
+    const int prec = precision;
+    int B;
+    if (block > 0) {
+      B = block;
+    } else {
+      const int bmem = auto_block(1 << 30, ld);  // memory cap on slots
+      B = std::min(autotune(prec, bmem).B, bmem);
+    }
+    B = std::max(1, std::min(B, P));
+    const bool full = (reorth == GWL_REORTH_FULL);
+    ensure_work(B, ld, full);
+    coef_a.ensure((size_t)P * ld);
+    coef_b.ensure((size_t)P * ld);
+    norm2.ensure(P);
+    out_len.ensure(P);
+    GWL_HIP(hipMemsetAsync(coef_a.p, 0, sizeof(double) * (size_t)P * ld, stream));
+    GWL_HIP(hipMemsetAsync(coef_b.p, 0, sizeof(double) * (size_t)P * ld, stream));
+    SlotState ss;
+    ss.pair = s_pair.p;
+    ss.k = s_k.p;
+    ss.len = s_len.p;
+    ss.dead = s_dead.p;
+    ss.amax = s_amax.p;
+    ss.bprev = s_bprev.p;
+    ss.coef_a = coef_a.p;
+    ss.coef_b = coef_b.p;
+    ss.out_len = out_len.p;
+    ss.norm2 = norm2.p;
+    ss.ld = ld;
+    const long bstride = (long)ld * nvc;
+    std::vector<int> hp(B, -1), hk(B, 0), hl(B, 0);
+    GWL_HIP(hipMemcpyAsync(s_pair.p, hp.data(), B * sizeof(int), hipMemcpyHostToDevice, stream));
+    GWL_HIP(hipStreamSynchronize(stream));
+    int next = 0;
+    std::vector<int> slots, ms, ns;
+    while (true) {
+      // refill
+      slots.clear();
+      ms.clear();
+      ns.clear();
+      for (int b = 0; b < B && next < P; ++b) {
+        if (hp[b] < 0 || hk[b] >= hl[b]) {
+          hp[b] = next;
+          hk[b] = 0;
+          hl[b] = len_host[next];
+          slots.push_back(b);
+          ms.push_back(m_host[next]);
+          ns.push_back(n_host[next]);
+          ++next;
+        }
+      }
+      if (!slots.empty()) {
+        const int cnt = (int)slots.size();
+        GWL_HIP(hipStreamSynchronize(stream));
+        prof_flush();
+        // mark slots that are done as empty
+        for (int b = 0; b < B; ++b)
+          if (hp[b] >= 0 && hk[b] >= hl[b]) hp[b] = -1;
+        GWL_HIP(hipMemcpy(s_pair.p, hp.data(), B * sizeof(int), hipMemcpyHostToDevice));
+        GWL_HIP(hipMemcpy(s_len.p, hl.data(), B * sizeof(int), hipMemcpyHostToDevice));
+        GWL_HIP(hipMemcpy(s_slots.p, slots.data(), cnt * sizeof(int), hipMemcpyHostToDevice));
+        if (start_dev) {
+          for (int i = 0; i < cnt; ++i)
+            GWL_HIP(hipMemcpyAsync(q.p + (size_t)slots[i] * nvc,
+                                   start_dev + (size_t)hp[slots[i]] * nvc, nvc * sizeof(double),
+                                   hipMemcpyDeviceToDevice, stream));
+        } else {
+          // coupling vectors straight into q rows (contiguous run of slots
+          // when all refill at once; otherwise one row at a time via w)
+          bool contiguous = true;
+          for (int i = 0; i < cnt; ++i) contiguous &= (slots[i] == slots[0] + i);
+          if (contiguous) {
+            coupling_batch(cnt, ms.data(), ns.data(), q.p + (size_t)slots[0] * nvc, nvc);
+          } else {
+            coupling_batch(cnt, ms.data(), ns.data(), w.p, nvc);
+            for (int i = 0; i < cnt; ++i)
+              GWL_HIP(hipMemcpyAsync(q.p + (size_t)slots[i] * nvc, w.p + (size_t)i * nvc,
+                                     nvc * sizeof(double), hipMemcpyDeviceToDevice, stream));
+          }
+        }
+        lz_start(ss, B, s_slots.p, cnt, q.p, qprev.p, full ? basis.p : nullptr, bstride, nvc,
+                 stream);
+      }
+      bool any = false;
+      int kmax = 0;
+      for (int b = 0; b < B; ++b)
+        if (hp[b] >= 0 && hk[b] < hl[b]) {
+          any = true;
+          kmax = std::max(kmax, hk[b]);
+        }
+      if (!any) break;
+      // one Lanczos step for every slot
+      if (on_c)
+        apply_c_batch(B, q.p, w.p, prec);
+      else
+        apply_d_step(B, prec);
+      lz_alpha(ss, B, q.p, qprev.p, w.p, nvc, stream);
+      lz_reorth(ss, B, kmax, reorth, full ? basis.p : nullptr, bstride, q.p, qprev.p, w.p,
+                hbuf.p, nvc, stream);
+      lz_beta(ss, B, q.p, qprev.p, w.p, full ? basis.p : nullptr, bstride, full ? 1 : 0, nvc,
+              stream);
+      for (int b = 0; b < B; ++b)
+        if (hp[b] >= 0 && hk[b] < hl[b]) ++hk[b];
+      // bound the number of outstanding timing events
+      if (profile && prof_recs.size() > 4096) {
+        GWL_HIP(hipStreamSynchronize(stream));
+        prof_flush();
+      }
+    }
+    GWL_HIP(hipStreamSynchronize(stream));
+    prof_flush();
+  }
+
+  int auto_block(int P, int L) const {
+    // memory per slot: basis (FULL) + work vectors; keep the basis under 64 GB
+    const double per_slot = (reorth == GWL_REORTH_FULL ? (double)L * nvc * 8 : 0.0) +
+                            8.0 * nvc * 8 + 4.0 * gd.nrp * 8;
+    int B = (int)std::min<double>(256.0, 64e9 / std::max(per_slot, 1.0));
+    if (nvc <= 4096) B = 256;
+    B = std::max(1, std::min(B, P));
+    return B;
+  }
+
+  // Upper end of the spectrum of C: Lanczos on C from a fixed pseudo-random
+  // start, largest Ritz value plus its residual bound, 1% margin.
+  double estimate_hi() {
+    const int steps = (int)std::min<long>(40, nvc);
+    std::vector<double> x0(nvc);
+    uint64_t st = 0x9E3779B97F4A7C15ull;
+    for (long i = 0; i < nvc; ++i) {
+      st ^= st << 13;
+      st ^= st >> 7;
+      st ^= st << 17;
+      x0[i] = (double)(st >> 11) / 9007199254740992.0 - 0.5;
+    }
+    DevBuf<double> start;
+    start.ensure(nvc);
+    GWL_HIP(hipMemcpy(start.p, x0.data(), nvc * sizeof(double), hipMemcpyHostToDevice));
+    const int saved_reorth = reorth, saved_block = block, saved_prec = precision;
+    reorth = GWL_REORTH_FULL;
+    block = 1;
+    precision = GWL_FP64;
+    int m0 = 0, n0 = 0, len = steps;
+    run_pairs(1, &m0, &n0, &len, steps, true, start.p);
+    reorth = saved_reorth;
+    block = saved_block;
+    precision = saved_prec;
+    std::vector<double> a(steps), b(steps);
+    int L = 0;
+    GWL_HIP(hipMemcpy(a.data(), coef_a.p, steps * sizeof(double), hipMemcpyDeviceToHost));
+    GWL_HIP(hipMemcpy(b.data(), coef_b.p, steps * sizeof(double), hipMemcpyDeviceToHost));
+    GWL_HIP(hipMemcpy(&L, out_len.p, sizeof(int), hipMemcpyDeviceToHost));
+    GWL_CHECK(L >= 1 && finite_all(a.data(), L), GWL_ENUMERIC, "spectrum estimate failed");
+    std::vector<double> t((size_t)L * L, 0.0), vec;
+    for (int i = 0; i < L; ++i) {
+      t[(size_t)i * L + i] = a[i];
+      if (i + 1 < L) t[(size_t)i * L + i + 1] = t[(size_t)(i + 1) * L + i] = b[i];
+    }
+    jacobi_eig(L, t, vec);
+    int imax = 0;
+    for (int i = 1; i < L; ++i)
+      if (t[(size_t)i * L + i] > t[(size_t)imax * L + imax]) imax = i;
+    const double theta = t[(size_t)imax * L + imax];
+    const double resid = (L < steps) ? 0.0 : std::fabs(b[L - 1] * vec[(size_t)(L - 1) * L + imax]);
+    return (theta + resid) * 1.01;
+  }
+};

@@ -16,7 +16,8 @@
 // BF16: v_mfma_f32_32x32x16_bf16 (FP32 accumulation), block tile
 //       256 x 128 x 32, 4 waves of 128 x 64.
 // Tiles are staged through LDS with the next K step prefetched into registers
-// (BF16: two LDS stages, one barrier per K step).  Register budgets are held
+// (BF16: two XOR-swizzled LDS stages, one barrier per K step, the loads of
+// the next step in flight during the current step's MFMAs).  Register budgets are held
 // to two waves per SIMD so that two blocks share a CU.
 // Block ids are remapped so that blocks sharing the large operand tile run on
 // the same XCD (one L2 per XCD).
@@ -228,9 +229,10 @@ gemm2_f64m_kernel(GemmDims d, int M, int splitk, int kchunk, const double* __res
 }
 
 // ---------------------------------------------------------------- BF16
-constexpr int HM = 256, HN = 128, HK = 32, HLD = HK + 8;  // LDS row: 40 bf16 = 80 B
-constexpr int HWN = HN / 64;                              // 32-col blocks per wave
-constexpr int HQB = HN * 4 / 256;                         // 16-B B chunks per thread
+constexpr int HM = 256, HN = 128, HK = 32, HLD = HK;  // LDS row: 32 bf16 = 64 B, swizzled
+constexpr int HWN = HN / 64;                          // 32-col blocks per wave
+constexpr int HQB = HN * 4 / 256;                     // 16-B B chunks per thread
+constexpr int G1_TILES = 4;                           // N tiles walked by one first-GEMM block
 
 typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
 
@@ -245,219 +247,233 @@ __device__ inline unsigned pack_bf16(float a, float b) {
 __device__ inline float lo_bf16(unsigned u) { return __builtin_bit_cast(float, u << 16); }
 __device__ inline float hi_bf16(unsigned u) { return __builtin_bit_cast(float, u & 0xffff0000u); }
 
-// A-tile loaders: thread t owns chunks idx = t + 256 q (q < 4) of the
-// 256 x 32 tile, row = idx / 4 = t/4 + 64 q, k offset 8 (t % 4).
+// LDS layout of a 32-wide K slab: rows of 64 bytes (four 16-byte chunks),
+// chunk c of row r stored at position c ^ ((r >> 2) & 3).  Both the 16-byte
+// staging writes (four threads per row) and the fragment reads (32 rows, one
+// chunk) then touch distinct banks.
+__device__ inline int swz(int row, int chunk) { return (chunk ^ ((row >> 2) & 3)) * 8; }
+
+// A-tile loaders.  Thread t owns chunks idx = t + 256 q (q < 4) of the
+// 256 x 32 tile: row t/4 + 64 q, K offset 8 (t % 4).  load() only issues the
+// global loads into registers; finish() turns them into the bf16 chunks
+// stored to LDS, after the current step's MFMAs.  Rows up to the 256-row
+// tile boundary are always allocated, so no load is guarded.
 struct LoadU16 {  // plain [M][K] rows
   const bf16_t* a;
   long lda;
-  __device__ void load4(int m0, int M, int t, int k0, u4 (&ra)[4]) const {
-    const int kc = (t & 3) * 8;
+  struct Raw {
+    u4 c[4];
+  };
+  __device__ void load(int m0, int t, int k0, Raw& r) const {
+    const bf16_t* p = a + (long)(m0 + (t >> 2)) * lda + k0 + (t & 3) * 8;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int m = m0 + (t >> 2) + 64 * q;
-      ra[q] = m < M ? *reinterpret_cast<const u4*>(a + (long)m * lda + k0 + kc) : u4{0, 0, 0, 0};
-    }
+    for (int q = 0; q < 4; ++q) r.c[q] = *reinterpret_cast<const u4*>(p + (long)64 * q * lda);
   }
+  __device__ u4 finish(const Raw& r, int q) const { return r.c[q]; }
 };
 
-// A[(b,v)][r] = bf16(phi_v(r) V_b(r)).  NVP = padded N_v when it is 64 or 128
-// (the four rows of a thread then share one or two phi_v rows), 0 otherwise.
+__device__ inline u4 scale8(u4 pv, f4v v0, f4v v1) {
+  u4 out;
+  out[0] = pack_bf16(lo_bf16(pv[0]) * v0[0], hi_bf16(pv[0]) * v0[1]);
+  out[1] = pack_bf16(lo_bf16(pv[1]) * v0[2], hi_bf16(pv[1]) * v0[3]);
+  out[2] = pack_bf16(lo_bf16(pv[2]) * v1[0], hi_bf16(pv[2]) * v1[1]);
+  out[3] = pack_bf16(lo_bf16(pv[3]) * v1[2], hi_bf16(pv[3]) * v1[3]);
+  return out;
+}
+
+// A[(b,v)][r] = bf16(phi_v(r) V_b(r)).  NVP = padded N_v when it is 64 or
+// 128 (a thread's four rows then share one or two phi_v rows and use four or
+// two potentials), 0 otherwise.
 template <int NVP>
 struct LoadPsiV16 {
   const bf16_t* psi_v_t;
   const float* vpot;
   long nrp;
   int nvp;
-  __device__ static u4 scale(u4 pv, const float* vp) {
-    const f4v v0 = *reinterpret_cast<const f4v*>(vp);
-    const f4v v1 = *reinterpret_cast<const f4v*>(vp + 4);
-    u4 out;
-    out[0] = pack_bf16(lo_bf16(pv[0]) * v0[0], hi_bf16(pv[0]) * v0[1]);
-    out[1] = pack_bf16(lo_bf16(pv[1]) * v0[2], hi_bf16(pv[1]) * v0[3]);
-    out[2] = pack_bf16(lo_bf16(pv[2]) * v1[0], hi_bf16(pv[2]) * v1[1]);
-    out[3] = pack_bf16(lo_bf16(pv[3]) * v1[2], hi_bf16(pv[3]) * v1[3]);
-    return out;
-  }
-  __device__ void load4(int m0, int M, int t, int k0, u4 (&ra)[4]) const {
+  static constexpr int NPV = NVP == 64 ? 1 : (NVP == 128 ? 2 : 4);
+  static constexpr int NB = NVP == 128 ? 2 : 4;
+  struct Raw {
+    u4 pv[NPV];
+    f4v v[NB][2];
+  };
+  __device__ void load(int m0, int t, int k0, Raw& r) const {
     const int k = k0 + (t & 3) * 8;
     const int r0 = t >> 2;
     if constexpr (NVP == 64) {
-      const u4 pv = *reinterpret_cast<const u4*>(psi_v_t + (long)r0 * nrp + k);
-      const int b0 = m0 / 64;
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        ra[q] = (m0 + r0 + 64 * q < M) ? scale(pv, vpot + (long)(b0 + q) * nrp + k)
-                                       : u4{0, 0, 0, 0};
-    } else if constexpr (NVP == 128) {
-      const u4 pa = *reinterpret_cast<const u4*>(psi_v_t + (long)r0 * nrp + k);
-      const u4 pb = *reinterpret_cast<const u4*>(psi_v_t + (long)(r0 + 64) * nrp + k);
-      const int b0 = m0 / 128;
+      r.pv[0] = *reinterpret_cast<const u4*>(psi_v_t + (long)r0 * nrp + k);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const bool ok = m0 + r0 + 64 * q < M;
-        ra[q] = ok ? scale((q & 1) ? pb : pa, vpot + (long)(b0 + (q >> 1)) * nrp + k)
-                   : u4{0, 0, 0, 0};
+        const float* vp = vpot + (long)(m0 / 64 + q) * nrp + k;
+        r.v[q][0] = *reinterpret_cast<const f4v*>(vp);
+        r.v[q][1] = *reinterpret_cast<const f4v*>(vp + 4);
+      }
+    } else if constexpr (NVP == 128) {
+      r.pv[0] = *reinterpret_cast<const u4*>(psi_v_t + (long)r0 * nrp + k);
+      r.pv[1] = *reinterpret_cast<const u4*>(psi_v_t + (long)(r0 + 64) * nrp + k);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const float* vp = vpot + (long)(m0 / 128 + h) * nrp + k;
+        r.v[h][0] = *reinterpret_cast<const f4v*>(vp);
+        r.v[h][1] = *reinterpret_cast<const f4v*>(vp + 4);
       }
     } else {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int m = m0 + r0 + 64 * q;
-        if (m < M) {
-          const int b = m / nvp, vv = m - b * nvp;
-          const u4 pv = *reinterpret_cast<const u4*>(psi_v_t + (long)vv * nrp + k);
-          ra[q] = scale(pv, vpot + (long)b * nrp + k);
-        } else {
-          ra[q] = u4{0, 0, 0, 0};
-        }
+        const int b = m / nvp, vv = m - b * nvp;
+        r.pv[q] = *reinterpret_cast<const u4*>(psi_v_t + (long)vv * nrp + k);
+        const float* vp = vpot + (long)b * nrp + k;
+        r.v[q][0] = *reinterpret_cast<const f4v*>(vp);
+        r.v[q][1] = *reinterpret_cast<const f4v*>(vp + 4);
       }
     }
+  }
+  __device__ u4 finish(const Raw& r, int q) const {
+    if constexpr (NVP == 64) return scale8(r.pv[0], r.v[q][0], r.v[q][1]);
+    else if constexpr (NVP == 128) return scale8(r.pv[q & 1], r.v[q >> 1][0], r.v[q >> 1][1]);
+    else return scale8(r.pv[q], r.v[q][0], r.v[q][1]);
   }
 };
 
-// acc += A[m0.., k] B[n0.., k], k in [kb, ke), two LDS stages (one barrier
-// per K step); B rows at or beyond nvalid read as zero.
+union BfSmem {
+  struct {
+    bf16_t As[2][HM][HLD];
+    bf16_t Bs[2][HN][HLD];
+  };
+};
+
+// One block tile in registers: global loads of one K step of A (raw) and B.
 template <typename LA>
-__device__ inline void bf16_mainloop(const LA& la, int M, const bf16_t* __restrict__ bop, long ldb,
-                                     int nvalid, int m0, int n0, int kb, int ke,
-                                     bf16_t (*As)[HM][HLD], bf16_t (*Bs)[HN][HLD],
-                                     f16v (&acc)[4][HWN]) {
-  const int t = threadIdx.x, l = t & 63, w = t >> 6;
-  const int wm = w >> 1, wn = w & 1;
-  u4 ra[4], rb[HQB];
-  auto gload = [&](int k0) {
-    la.load4(m0, M, t, k0, ra);
+struct BfStage {
+  typename LA::Raw a;
+  u4 b[HQB];
+};
+
+template <typename LA>
+__device__ inline void bf_gload(const LA& la, const bf16_t* __restrict__ bop, long ldb, int m0,
+                                int n0, int k0, BfStage<LA>& x) {
+  const int t = threadIdx.x;
+  la.load(m0, t, k0, x.a);
+  const bf16_t* p = bop + (long)(n0 + (t >> 2)) * ldb + k0 + (t & 3) * 8;
 #pragma unroll
-    for (int q = 0; q < HQB; ++q) {
-      const int idx = t + 256 * q;
-      const int row = idx >> 2, kc = (idx & 3) * 8;
-      rb[q] = (n0 + row < nvalid)
-                  ? *reinterpret_cast<const u4*>(bop + (long)(n0 + row) * ldb + k0 + kc)
-                  : u4{0, 0, 0, 0};
-    }
-  };
-  auto lstore = [&](int buf) {
+  for (int q = 0; q < HQB; ++q) x.b[q] = *reinterpret_cast<const u4*>(p + (long)64 * q * ldb);
+}
+
+template <typename LA>
+__device__ inline void bf_lstore(const LA& la, BfSmem& sm, int buf, const BfStage<LA>& x) {
+  const int t = threadIdx.x;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int idx = t + 256 * q;
-      *reinterpret_cast<u4*>(&As[buf][idx >> 2][(idx & 3) * 8]) = ra[q];
-    }
-#pragma unroll
-    for (int q = 0; q < HQB; ++q) {
-      const int idx = t + 256 * q;
-      *reinterpret_cast<u4*>(&Bs[buf][idx >> 2][(idx & 3) * 8]) = rb[q];
-    }
-  };
-  if (kb < ke) {
-    gload(kb);
-    lstore(0);
+  for (int q = 0; q < 4; ++q) {
+    const int row = (t >> 2) + 64 * q;
+    *reinterpret_cast<u4*>(&sm.As[buf][row][swz(row, t & 3)]) = la.finish(x.a, q);
   }
-  __syncthreads();
-  int cur = 0;
-  for (int k0 = kb; k0 < ke; k0 += HK) {
-    const bool more = k0 + HK < ke;
-    if (more) gload(k0 + HK);
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-      bf8 a[4];
-      const int kk = 16 * ks + 8 * (l >> 5);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = lds_frag(&As[cur][wm * 128 + 32 * i + (l & 31)][kk]);
-#pragma unroll
-      for (int j = 0; j < HWN; ++j) {
-        const bf8 b = lds_frag(&Bs[cur][wn * (HN / 2) + 32 * j + (l & 31)][kk]);
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b, acc[i][j], 0, 0, 0);
-      }
-    }
-    if (more) lstore(cur ^ 1);
-    __syncthreads();
-    cur ^= 1;
+  for (int q = 0; q < HQB; ++q) {
+    const int row = (t >> 2) + 64 * q;
+    *reinterpret_cast<u4*>(&sm.Bs[buf][row][swz(row, t & 3)]) = x.b[q];
   }
 }
 
-struct BfSmem {
-  bf16_t As[2][HM][HLD];
-  bf16_t Bs[2][HN][HLD];
-};
+__device__ inline void bf_compute(BfSmem& sm, int buf, f16v (&acc)[4][HWN]) {
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = w >> 1, wn = w & 1;
+#pragma unroll
+  for (int ks = 0; ks < 2; ++ks) {
+    const int ch = 2 * ks + (l >> 5);
+    bf8 a[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = wm * 128 + 32 * i + (l & 31);
+      a[i] = lds_frag(&sm.As[buf][row][swz(row, ch)]);
+    }
+#pragma unroll
+    for (int j = 0; j < HWN; ++j) {
+      const int row = wn * (HN / 2) + 32 * j + (l & 31);
+      const bf8 b = lds_frag(&sm.Bs[buf][row][swz(row, ch)]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b, acc[i][j], 0, 0, 0);
+    }
+  }
+}
 
-// First GEMM.  NVP = padded N_v if 64 or 128: the epilogue weights phi_v(r)
-// of the block's 128 columns are staged once in LDS and shared by both
-// M-waves; NVP = 0 (N_v padded to a multiple of 256): every wave reads its
-// own 128 weights per column from global memory.
-template <int NVP>
+// First GEMM.  A block owns one M tile and walks up to G1_TILES consecutive N
+// tiles; the first K step of the next tile is loaded while the last step of
+// the current one computes and its epilogue runs.  SEG = 32-row blocks that
+// belong to one pair vector within a wave's 128 rows (4 when N_v padded >=
+// 128, 2 when 64).  Epilogue weights phi_v(r) (BF16) are read from L2.
+template <int SEG>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 gemm1_bf16_kernel(GemmDims d, int M, int nb, const bf16_t* __restrict__ psi_c_rc,
                   const bf16_t* __restrict__ psi_v_rv, const bf16_t* __restrict__ u,
                   float* __restrict__ rho_part) {
   __shared__ BfSmem sm;
   const int mt = (M + HM - 1) / HM, nt = d.nrp / HN;
-  int mi, ni;
-  if (!gemm1_tile(blockIdx.x, mt, nt, mi, ni)) return;
-  const int m0 = mi * HM, n0 = ni * HN;
-  f16v acc[4][HWN];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < HWN; ++j) acc[i][j] = f16v{};
-  LoadU16 la{u, d.ncp};
-  bf16_mainloop(la, M, psi_c_rc, d.ncp, d.nrp, m0, n0, 0, d.ncp, sm.As, sm.Bs, acc);
-
+  const int ng = (nt + G1_TILES - 1) / G1_TILES;
+  int mi, gi;
+  if (!gemm1_tile(blockIdx.x, mt, ng, mi, gi)) return;
+  const int m0 = mi * HM;
+  const int nt0 = gi * G1_TILES, nt1 = min(nt, nt0 + G1_TILES);
   const int t = threadIdx.x, l = t & 63, w = t >> 6;
   const int wm = w >> 1, wn = w & 1;
-  constexpr int SEG = (NVP == 64) ? 2 : 4;       // 32-row blocks per pair vector segment
-  constexpr int WLD = (NVP > 0 ? NVP : 0) + 8;   // LDS row of staged weights
-  bf16_t* wl = &sm.As[0][0][0];
-  if constexpr (NVP > 0) {
-    // weights phi_v(r), r in [n0, n0 + 128), v in [0, NVP): one copy per block
-    constexpr int CH = NVP / 8;  // 16-byte chunks per row
-    for (int idx = t; idx < HN * CH; idx += 256) {
-      const int rr = idx / CH, cc = (idx - rr * CH) * 8;
-      *reinterpret_cast<u4*>(wl + rr * WLD + cc) =
-          *reinterpret_cast<const u4*>(psi_v_rv + (long)(n0 + rr) * d.nvp + cc);
-    }
+  const int nsteps = d.ncp / HK;
+  LoadU16 la{u, d.ncp};
+  BfStage<LoadU16> x;
+  bf_gload(la, psi_c_rc, d.ncp, m0, nt0 * HN, 0, x);
+  for (int ti = nt0; ti < nt1; ++ti) {
+    const int n0 = ti * HN;
+    f16v acc[4][HWN];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < HWN; ++j) acc[i][j] = f16v{};
+    bf_lstore(la, sm, 0, x);
     __syncthreads();
-  }
-  const int mw = m0 + wm * 128;
+    for (int i = 0; i < nsteps; ++i) {
+      const int cur = i & 1;
+      const bool more = i + 1 < nsteps;
+      if (more)
+        bf_gload(la, psi_c_rc, d.ncp, m0, n0, (i + 1) * HK, x);
+      else if (ti + 1 < nt1)
+        bf_gload(la, psi_c_rc, d.ncp, m0, n0 + HN, 0, x);
+      bf_compute(sm, cur, acc);
+      if (more) bf_lstore(la, sm, cur ^ 1, x);
+      __syncthreads();
+    }
+    // epilogue: rho_b(r) = sum_v phi_v(r) C1[(b,v), r] over each segment
+    const int mw = m0 + wm * 128;
 #pragma unroll
-  for (int sg = 0; sg < 4; sg += SEG) {
-    const int ms = mw + 32 * sg;
-    if (ms < M) {
-      const int b = ms / d.nvp, vbase = ms - b * d.nvp;
-      const int vt = vbase / 128;
+    for (int sg = 0; sg < 4; sg += SEG) {
+      const int ms = mw + 32 * sg;
+      if (ms < M) {
+        const int b = ms / d.nvp, vbase = ms - b * d.nvp;
+        const int vt = vbase / 128;
 #pragma unroll
-      for (int j = 0; j < HWN; ++j) {
-        const int rl = wn * (HN / 2) + 32 * j + (l & 31);
-        float s = 0.f;
+        for (int j = 0; j < HWN; ++j) {
+          const int r = n0 + wn * (HN / 2) + 32 * j + (l & 31);
+          const bf16_t* wr = psi_v_rv + (long)r * d.nvp + vbase + 4 * (l >> 5);
+          float s = 0.f;
 #pragma unroll
-        for (int i = 0; i < SEG; ++i) {
+          for (int i = 0; i < SEG; ++i) {
 #pragma unroll
-          for (int g = 0; g < 4; ++g) {
-            const int v = vbase + 32 * i + 8 * g + 4 * (l >> 5);
-            unsigned w01, w23;
-            if constexpr (NVP > 0) {
-              const unsigned* p = reinterpret_cast<const unsigned*>(wl + rl * WLD + v);
-              w01 = p[0];
-              w23 = p[1];
-            } else {
-              const unsigned* p = reinterpret_cast<const unsigned*>(
-                  psi_v_rv + (long)(n0 + rl) * d.nvp + v);
-              w01 = p[0];
-              w23 = p[1];
+            for (int g = 0; g < 4; ++g) {
+              const uint2 wv = *reinterpret_cast<const uint2*>(wr + 32 * i + 8 * g);
+              s += lo_bf16(wv.x) * acc[sg + i][j][4 * g + 0];
+              s += hi_bf16(wv.x) * acc[sg + i][j][4 * g + 1];
+              s += lo_bf16(wv.y) * acc[sg + i][j][4 * g + 2];
+              s += hi_bf16(wv.y) * acc[sg + i][j][4 * g + 3];
             }
-            s += lo_bf16(w01) * acc[sg + i][j][4 * g + 0];
-            s += hi_bf16(w01) * acc[sg + i][j][4 * g + 1];
-            s += lo_bf16(w23) * acc[sg + i][j][4 * g + 2];
-            s += hi_bf16(w23) * acc[sg + i][j][4 * g + 3];
           }
+          s += __shfl_xor(s, 32, 64);
+          if (l < 32) rho_part[((long)vt * nb + b) * d.nrp + r] = s;
         }
-        s += __shfl_xor(s, 32, 64);
-        if (l < 32) rho_part[((long)vt * nb + b) * d.nrp + n0 + rl] = s;
       }
     }
   }
 }
 
+// Second GEMM over one split of the grid sum; one LDS stage prefetched, the
+// A operand scaled by the potential after the current step's MFMAs.
 template <int NVP>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 gemm2_bf16_kernel(GemmDims d, int M, int splitk, int kchunk, const bf16_t* __restrict__ psi_v_t,
@@ -471,13 +487,27 @@ gemm2_bf16_kernel(GemmDims d, int M, int splitk, int kchunk, const bf16_t* __res
   const int m0 = (rem % mt) * HM, n0 = (rem / mt) * HN;
   const int kb = s * kchunk;
   const int ke = min(d.nrp, kb + kchunk);
+  const int nsteps = ke > kb ? (ke - kb) / HK : 0;
   f16v acc[4][HWN];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < HWN; ++j) acc[i][j] = f16v{};
   LoadPsiV16<NVP> la{psi_v_t, vpot, d.nrp, d.nvp};
-  bf16_mainloop(la, M, psi_c_t, d.nrp, d.ncp, m0, n0, kb, ke, sm.As, sm.Bs, acc);
+  BfStage<LoadPsiV16<NVP>> x;
+  if (nsteps > 0) {
+    bf_gload(la, psi_c_t, d.nrp, m0, n0, kb, x);
+    bf_lstore(la, sm, 0, x);
+  }
+  __syncthreads();
+  for (int i = 0; i < nsteps; ++i) {
+    const int cur = i & 1;
+    const bool more = i + 1 < nsteps;
+    if (more) bf_gload(la, psi_c_t, d.nrp, m0, n0, kb + (i + 1) * HK, x);
+    bf_compute(sm, cur, acc);
+    if (more) bf_lstore(la, sm, cur ^ 1, x);
+    __syncthreads();
+  }
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wm = w >> 1, wn = w & 1;
   float* out = ypart + (long)s * M * d.ncp;
@@ -524,13 +554,11 @@ void gemm1_bf16(const GemmDims& d, int nb, const bf16_t* psi_c_rc, const bf16_t*
                 const bf16_t* u, float* rho_part, hipStream_t st) {
   if (nb <= 0) return;
   const int M = nb * d.nvp;
-  const int blocks = gemm1_grid(ceil_div(M, HM), d.nrp / HN);
+  const int blocks = gemm1_grid(ceil_div(M, HM), ceil_div(d.nrp / HN, G1_TILES));
   if (d.nvp == 64)
-    gemm1_bf16_kernel<64><<<blocks, 256, 0, st>>>(d, M, nb, psi_c_rc, psi_v_rv, u, rho_part);
-  else if (d.nvp == 128)
-    gemm1_bf16_kernel<128><<<blocks, 256, 0, st>>>(d, M, nb, psi_c_rc, psi_v_rv, u, rho_part);
+    gemm1_bf16_kernel<2><<<blocks, 256, 0, st>>>(d, M, nb, psi_c_rc, psi_v_rv, u, rho_part);
   else
-    gemm1_bf16_kernel<0><<<blocks, 256, 0, st>>>(d, M, nb, psi_c_rc, psi_v_rv, u, rho_part);
+    gemm1_bf16_kernel<4><<<blocks, 256, 0, st>>>(d, M, nb, psi_c_rc, psi_v_rv, u, rho_part);
   GWL_HIP(hipGetLastError());
 }
 

@@ -51,6 +51,13 @@ struct GemmDims {
 constexpr int kPadR = 256;
 constexpr int kPadC = 64;
 inline int pad_nv(int nv) { return nv <= 64 ? 64 : (nv <= 128 ? 128 : (int)round_up(nv, 256)); }
+// The BF16 tiles read whole 256-row A tiles and 128-row B tiles without
+// bounds checks: pair-vector operand rows are allocated to a multiple of 256,
+// potentials to the pair vectors those rows touch, orbital rows of the
+// second GEMM's B operand to a multiple of 128.
+inline long alloc_rows_u(long nb, int nvp) { return round_up(nb * nvp, 256); }
+inline long alloc_rows_v(long nb, int nvp) { return alloc_rows_u(nb, nvp) / nvp + 1; }
+inline long alloc_rows_c(int ncp) { return round_up(ncp, 128); }
 
 // FP64 (plain tiled FMA; reference-quality GPU path).
 int gemm1_f64_vtiles(const GemmDims& d);
@@ -103,11 +110,12 @@ void cast_u(const PairGeom& g, int nb, const double* x, long ldx, U* u, hipStrea
 // cx = Delta^2 x + 2 dV Delta^1/2 y.  mode 0: out = cx.  mode 1 (first
 // Chebyshev step): tn = (2 cx - (hi+lo) x)/(hi-lo); acc = c0 x + c1 tn.
 // mode 2: tn = 2 (2 cx - (hi+lo) x)/(hi-lo) - tp; acc += cj tn.
-// If u != null also writes u = cast(Delta^1/2 tn) (mode 1, 2) for the next product.
+// If u != null also writes u = cast(Delta^1/2 tn) (mode 1, 2) for the next product;
+// if kx_out != null also writes the coupling part K Delta^1/2 x = dV y.
 template <typename Y, typename U>
 void combine(const PairGeom& g, int nb, int splitk, const Y* ypart, const double* x,
              const double* tp, double* out_tn, double* acc, int mode, double lo, double hi,
-             double c0, double cj, U* u, hipStream_t st);
+             double c0, double cj, U* u, hipStream_t st, double* kx_out = nullptr);
 
 // Coupling finish: P_i = dV Delta^1/2 sum_s ypart[s][i]; writes P (compact)
 // to p_out[i] (ld ldp).
@@ -154,5 +162,38 @@ void cfrac_sigma(int npairs, const double* coef_a, const double* coef_b, const i
 // out[q][w] = sum_{p in [q*per, (q+1)*per)} sig[p][w], fixed order.
 void sum_groups(const double* sig, int ngroups, int per, int nomega, double* out,
                 hipStream_t st);
+
+// ---------------------------------------------------------------- adjoint
+void adj_cfrac(int npairs, const double* ca, const double* cb, const int* lens,
+               const double* norm2, int ld, const double* e_n, const double* eta_n,
+               const int* qidx, const double* omega_ha, int nomega, double delta_ha,
+               const double* G, void* tscr, double* abar, double* bbar, double* nbar,
+               double* ebar, double* sig, hipStream_t st);
+void adj_lanczos_step(int k, int nb, const int* pair_of_slot, const int* lens, int ld,
+                      const double* ca, const double* cb, const double* abar, const double* bbar,
+                      const double* q_next, const double* q_cur, const double* q_prev,
+                      const double* w_cur, const double* qb_next, double* qb_cur, double* qb_prev,
+                      double* wbar, double* pend, long nvc, hipStream_t st);
+void adj_start(int nb, const int* pair_of_slot, const double* norm2, const double* nbar,
+               const double* P, const double* qb0, const double* sdelta, double* dbar,
+               double* kbar, long nvc, hipStream_t st);
+void adj_combine(const PairGeom& g, int nb, int splitk, const double* ypart, const double* sj,
+                 const double* sj1, const double* seed, double cprev, double sigma, double lo,
+                 double hi, double* out, double* ks, double* u, hipStream_t st);
+void adj_dbar_uv(const PairGeom& g, int nb, const double* s, const double* ks, const double* t,
+                 const double* kt, double alpha, double kappa, double* dbar, double* U,
+                 double* V, hipStream_t st);
+void adj_scale_copy(double* dst, const double* src, double c, long n, hipStream_t st);
+void adj_axpy(double* dst, const double* src, double a, long n, hipStream_t st);
+void adj_sum_rows(double* dst, const double* src, int nrows, long n, hipStream_t st);
+void adj_symmetrize(double* S, const double* A, long n, hipStream_t st);
+void adj_pair_density(const double* psi_t, long ld, int nv, int nc, int nvp, long q0, int cnt,
+                      double* rho, hipStream_t st);
+void adj_orb_grad_vc(const double* psi_t, const double* W, long ld, int nr, int nv, int nc,
+                     int nvp, double dv, double* grad, hipStream_t st);
+void adj_orb_grad_nm(const double* psi_t, const double* Vk, long ld, int nr, const int* mrow,
+                     const int* nrow, int npairs, double dv, double* grad, hipStream_t st);
+void adj_gather_orbitals(const double* src, long ld, int nr, int nv, int nvp, int norb,
+                         double* dst, hipStream_t st);
 
 }  // namespace gwl

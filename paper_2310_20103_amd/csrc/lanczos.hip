@@ -67,7 +67,8 @@ template <typename Y, typename U>
 __global__ void combine_kernel(PairGeom g, int nb, int splitk, const Y* __restrict__ ypart,
                                const double* __restrict__ x, const double* __restrict__ tp,
                                double* __restrict__ out, double* __restrict__ acc, int mode,
-                               double lo, double hi, double c0, double cj, U* __restrict__ u) {
+                               double lo, double hi, double c0, double cj, U* __restrict__ u,
+                               double* __restrict__ kx_out) {
   const int b = blockIdx.y;
   const long stride_s = (long)nb * g.nvp * g.ncp;
   const Y* yb = ypart + (long)b * g.nvp * g.ncp;
@@ -82,6 +83,7 @@ __global__ void combine_kernel(PairGeom g, int nb, int splitk, const Y* __restri
     const double sd = g.sdelta[i];
     const double cx = g.delta2[i] * xi + 2.0 * g.dv * sd * y;
     const long o = (long)b * g.nvc + i;
+    if (kx_out) kx_out[o] = g.dv * y;  // K Delta^1/2 x
     if (mode == 0) {
       out[o] = cx;
       continue;
@@ -296,19 +298,19 @@ template void cast_u<bf16_t>(const PairGeom&, int, const double*, long, bf16_t*,
 template <typename Y, typename U>
 void combine(const PairGeom& g, int nb, int splitk, const Y* ypart, const double* x,
              const double* tp, double* out_tn, double* acc, int mode, double lo, double hi,
-             double c0, double cj, U* u, hipStream_t st) {
+             double c0, double cj, U* u, hipStream_t st, double* kx_out) {
   if (nb <= 0) return;
   dim3 grid(grid_elems(g.nvc), nb);
   combine_kernel<Y, U><<<grid, NT, 0, st>>>(g, nb, splitk, ypart, x, tp, out_tn, acc, mode, lo,
-                                            hi, c0, cj, u);
+                                            hi, c0, cj, u, kx_out);
   GWL_HIP(hipGetLastError());
 }
 template void combine<double, double>(const PairGeom&, int, int, const double*, const double*,
                                       const double*, double*, double*, int, double, double,
-                                      double, double, double*, hipStream_t);
+                                      double, double, double*, hipStream_t, double*);
 template void combine<float, bf16_t>(const PairGeom&, int, int, const float*, const double*,
                                      const double*, double*, double*, int, double, double,
-                                     double, double, bf16_t*, hipStream_t);
+                                     double, double, bf16_t*, hipStream_t, double*);
 
 template <typename Y>
 void coupling_finish(const PairGeom& g, int cnt, int splitk, const Y* ypart, double* p_out,
