@@ -41,6 +41,30 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel, workload, block):
+    """HBM bytes per launch of `kernel` from the counter summary committed in
+    profiles/ (FETCH_SIZE and WRITE_SIZE passes scaled by a plain-copy
+    calibration).  None when there is no summary, when it was taken at another
+    block size, or when the kernel source has changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for ln in f:
+            if ":" in ln and not ln.startswith(" "):
+                k, v = ln.split(":", 1)
+                kv[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_2310_20103_amd", "csrc", kv.get("source", "?"))
+    if not os.path.exists(src) or int(kv.get("block", -1)) != block:
+        return None
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != kv.get("source_sha256"):
+            return None
+    return float(kv["hbm_bytes_per_launch"])
+
+
 def cpu_baseline(wl, phi, eps, m, n, steps, lo, hi):
     """The FP64 oracle (matrix-free route) on a bounded sample: one start
     vector, `steps` Lanczos steps, extrapolated to spectra/s."""
@@ -78,6 +102,8 @@ def main():
     ap.add_argument("--fp64-window", type=int, default=2, help="Lanczos steps of the FP64 window")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -89,6 +115,14 @@ def main():
     import paper_2310_20103_amd as G
 
     assert torch.cuda.is_available(), "needs a GPU"
+    if args.calibrate_copy:
+        # one elementwise kernel that reads 256 MiB and writes 256 MiB
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+        log("calibration copy of 256 MiB done")
     wl = gi.workload(args.workload)
     t = time.perf_counter()
     phi = gi.make_orbitals(wl)
@@ -145,9 +179,12 @@ def main():
     ms, cnt, vec = prof[dom]
     flop_launch = 2.0 * wl.n_r * wl.n_occ * wl.n_emp * (vec / max(cnt, 1))
     achieved = flop_launch / (ms / max(cnt, 1) / 1e3) / 1e12 if cnt else 0.0
+    traffic = measured_traffic(f"{dom}_bf16", wl.name, B)
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4),
-                "traffic": None, "kernel": f"{dom}_bf16", "launches": int(cnt),
+                "traffic": traffic, "traffic_unit": "bytes per launch",
+                "algorithmic_flop_per_launch": flop_launch,
+                "kernel": f"{dom}_bf16", "launches": int(cnt),
                 "avg_launch_ms": round(ms / max(cnt, 1), 4)}
     kernel_ms = {k: round(v[0], 2) for k, v in prof.items()}
 

@@ -238,7 +238,10 @@ enum {
                                    Graphs are not used while GWL_KEY_PROFILE is on. */
   GWL_KEY_TUNED_BLOCK = 24,     /* query: slots B chosen by the autotuner (block = 0) for the
                                    current precision, 0 before the first tuned call */
-  GWL_KEY_TUNED_SPLITK = 25     /* query: split chosen with it */
+  GWL_KEY_TUNED_SPLITK = 25,    /* query: split chosen with it */
+  GWL_KEY_BF16_TILE = 26        /* set/query: block tile width of the second BF16 GEMM, 256
+                                   (default: one wave per SIMD, accumulators in AGPRs) or
+                                   128 (two waves per SIMD) */
 };
 /* The autotuner runs on the first gwl_sigma_c / gwl_sigma_c_range /
  * gwl_lanczos_pairs call with block = 0: it times one C-product for

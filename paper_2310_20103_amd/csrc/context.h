@@ -133,6 +133,7 @@ struct gwl_ctx {
   double kernel_scale = 1.0;
   int splitk = 0;  // 0 = automatic
   int fp64_kernel = 1;  // 0 = plain FMA tiles, 1 = MFMA (both precisions)
+  int bf16_tile = 256;  // block tile width of the second BF16 MFMA GEMM
   std::vector<double> cheb;
   std::vector<double> eps_ha;
 
@@ -142,8 +143,8 @@ struct gwl_ctx {
   DevBuf<double> psi_v_rv64;  // [NRp][NVp]
   DevBuf<bf16_t> psi_t16;     // [NVp + NCp][NRp]
   DevBuf<bf16_t> psi_c_rc16;  // [NRp][NCp]
-  DevBuf<float> psi_v_rv32;   // [NRp][NVp] (plain BF16 kernel epilogue)
-  DevBuf<bf16_t> psi_v_rv16;  // [NRp][NVp] (MFMA BF16 kernel epilogue)
+  DevBuf<float> psi_v_rv32;   // [NRp][NVp] (BF16 kernel epilogues)
+  DevBuf<bf16_t> psi_v_rv16;  // [NRp][NVp] (MFMA BF16 epilogue, N_vp <= 128)
   DevBuf<double> delta2, sdelta;
 
   // FFT tables
@@ -283,7 +284,7 @@ struct gwl_ctx {
     else if (prec == GWL_FP64)
       blocks = gemm2_f64m_blocks(gd, nb);
     else
-      blocks = gemm2_bf16_blocks(gd, nb);
+      blocks = gemm2_bf16_blocks(gd, nb, bf16_tile);
     int s = 1;
     while (blocks * s < 1024 && s < 32 && (long)gd.nrp / (s * 2) >= 2048) s *= 2;
     return s;
@@ -364,7 +365,7 @@ struct gwl_ctx {
       int nvt;
       prof_begin();
       if (fp64_kernel) {
-        gemm1_bf16(gd, nb, psi_c_rc16.p, psi_v_rv16.p, uu, rp, st);
+        gemm1_bf16(gd, nb, psi_c_rc16.p, psi_v_rv32.p, psi_v_rv16.p, uu, rp, st);
         nvt = gemm1_bf16_vtiles(gd);
       } else {
         gemm1_bf16s(gd, nb, psi_c_rc16.p, psi_v_rv32.p, uu, rp, st);
@@ -379,7 +380,7 @@ struct gwl_ctx {
       const bf16_t* pc = psi_t16.p + (size_t)gd.nvp * gd.nrp;
       prof_begin();
       if (fp64_kernel)
-        gemm2_bf16(gd, nb, S, pv, pc, vp, yp, st);
+        gemm2_bf16(gd, nb, bf16_tile, S, pv, pc, vp, yp, st);
       else
         gemm2_bf16s(gd, nb, S, pv, pc, vp, yp, st);
       prof_end(1, nb);
@@ -519,7 +520,8 @@ struct gwl_ctx {
   // problem shape: "key B S us_per_vector").
   std::string tune_key(int prec) const {
     return "gfx950:" + std::to_string(nr) + ":" + std::to_string(nv) + ":" +
-           std::to_string(nc) + ":" + std::to_string(prec) + ":" + std::to_string(fp64_kernel);
+           std::to_string(nc) + ":" + std::to_string(prec) + ":" + std::to_string(fp64_kernel) + ":" +
+           std::to_string(bf16_tile);
   }
 
   bool tune_cache_read(int prec, Tune& t) const {

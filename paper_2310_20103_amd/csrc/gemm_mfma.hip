@@ -229,10 +229,19 @@ gemm2_f64m_kernel(GemmDims d, int M, int splitk, int kchunk, const double* __res
 }
 
 // ---------------------------------------------------------------- BF16
-constexpr int HM = 256, HN = 128, HK = 32, HLD = HK;  // LDS row: 32 bf16 = 64 B, swizzled
-constexpr int HWN = HN / 64;                          // 32-col blocks per wave
-constexpr int HQB = HN * 4 / 256;                     // 16-B B chunks per thread
-constexpr int G1_TILES = 4;                           // N tiles walked by one first-GEMM block
+// Block tile HM x BN (BN = 128 or 256), four waves in a 2 x 2 grid, each
+// wave 128 x BN/2 of 32 x 32 MFMA blocks.  BN = 256 gives each wave 256 FP32
+// accumulators (held in AGPRs, one wave per SIMD) and halves the LDS and L1
+// traffic per flop; BN = 128 runs two waves per SIMD.  The first GEMM uses
+// BN = 128 (its per-tile row-dot epilogue needs a second wave per SIMD to
+// hide it); the second GEMM takes either, 256 by default.
+constexpr int HM = 256, HK = 32, HLD = HK;  // LDS row: 32 bf16 = 64 B, swizzled
+constexpr int G1_TILES = 4;                 // N tiles walked by one first-GEMM block
+template <int BN>
+struct BfCfg {
+  static constexpr int WN = BN / 64;       // 32-col blocks per wave
+  static constexpr int QB = BN * 4 / 256;  // 16-B B chunks per thread and K step
+};
 
 typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
 
@@ -335,32 +344,33 @@ struct LoadPsiV16 {
   }
 };
 
-union BfSmem {
-  struct {
-    bf16_t As[2][HM][HLD];
-    bf16_t Bs[2][HN][HLD];
-  };
+template <int BN>
+struct BfSmem {
+  bf16_t As[2][HM][HLD];
+  bf16_t Bs[2][BN][HLD];
 };
 
 // One block tile in registers: global loads of one K step of A (raw) and B.
-template <typename LA>
+template <typename LA, int BN>
 struct BfStage {
   typename LA::Raw a;
-  u4 b[HQB];
+  u4 b[BfCfg<BN>::QB];
 };
 
-template <typename LA>
+template <typename LA, int BN>
 __device__ inline void bf_gload(const LA& la, const bf16_t* __restrict__ bop, long ldb, int m0,
-                                int n0, int k0, BfStage<LA>& x) {
+                                int n0, int k0, BfStage<LA, BN>& x) {
   const int t = threadIdx.x;
   la.load(m0, t, k0, x.a);
   const bf16_t* p = bop + (long)(n0 + (t >> 2)) * ldb + k0 + (t & 3) * 8;
 #pragma unroll
-  for (int q = 0; q < HQB; ++q) x.b[q] = *reinterpret_cast<const u4*>(p + (long)64 * q * ldb);
+  for (int q = 0; q < BfCfg<BN>::QB; ++q)
+    x.b[q] = *reinterpret_cast<const u4*>(p + (long)64 * q * ldb);
 }
 
-template <typename LA>
-__device__ inline void bf_lstore(const LA& la, BfSmem& sm, int buf, const BfStage<LA>& x) {
+template <typename LA, int BN>
+__device__ inline void bf_lstore(const LA& la, BfSmem<BN>& sm, int buf,
+                                 const BfStage<LA, BN>& x) {
   const int t = threadIdx.x;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -368,13 +378,16 @@ __device__ inline void bf_lstore(const LA& la, BfSmem& sm, int buf, const BfStag
     *reinterpret_cast<u4*>(&sm.As[buf][row][swz(row, t & 3)]) = la.finish(x.a, q);
   }
 #pragma unroll
-  for (int q = 0; q < HQB; ++q) {
+  for (int q = 0; q < BfCfg<BN>::QB; ++q) {
     const int row = (t >> 2) + 64 * q;
     *reinterpret_cast<u4*>(&sm.Bs[buf][row][swz(row, t & 3)]) = x.b[q];
   }
 }
 
-__device__ inline void bf_compute(BfSmem& sm, int buf, f16v (&acc)[4][HWN]) {
+// ZERO: the first 16-wide K slice starts the accumulators from zero (the MFMA
+// reads an inline 0 for C) instead of from acc.
+template <int BN, bool ZERO = false>
+__device__ inline void bf_compute(BfSmem<BN>& sm, int buf, f16v (&acc)[4][BfCfg<BN>::WN]) {
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wm = w >> 1, wn = w & 1;
 #pragma unroll
@@ -387,12 +400,13 @@ __device__ inline void bf_compute(BfSmem& sm, int buf, f16v (&acc)[4][HWN]) {
       a[i] = lds_frag(&sm.As[buf][row][swz(row, ch)]);
     }
 #pragma unroll
-    for (int j = 0; j < HWN; ++j) {
-      const int row = wn * (HN / 2) + 32 * j + (l & 31);
+    for (int j = 0; j < BfCfg<BN>::WN; ++j) {
+      const int row = wn * (BN / 2) + 32 * j + (l & 31);
       const bf8 b = lds_frag(&sm.Bs[buf][row][swz(row, ch)]);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+            a[i], b, (ZERO && ks == 0) ? f16v{} : acc[i][j], 0, 0, 0);
     }
   }
 }
@@ -401,14 +415,57 @@ __device__ inline void bf_compute(BfSmem& sm, int buf, f16v (&acc)[4][HWN]) {
 // tiles; the first K step of the next tile is loaded while the last step of
 // the current one computes and its epilogue runs.  SEG = 32-row blocks that
 // belong to one pair vector within a wave's 128 rows (4 when N_v padded >=
-// 128, 2 when 64).  Epilogue weights phi_v(r) (BF16) are read from L2.
-template <int SEG>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
-gemm1_bf16_kernel(GemmDims d, int M, int nb, const bf16_t* __restrict__ psi_c_rc,
-                  const bf16_t* __restrict__ psi_v_rv, const bf16_t* __restrict__ u,
-                  float* __restrict__ rho_part) {
-  __shared__ BfSmem sm;
-  const int mt = (M + HM - 1) / HM, nt = d.nrp / HN;
+// 128, 2 when 64).
+//
+// Epilogue weights phi_v(r): with N_v padded to NVW = 64 or 128 every wave of
+// the block uses the same v window, so the tile's BF16 weights [BN][NVW] are
+// copied global -> LDS by the direct-to-LDS loads while the K loop runs
+// (16-byte chunks XOR-swizzled by row, so the epilogue's 8-byte reads of 32
+// rows hit distinct bank groups).  NVW = 0 (larger N_v) reads FP32 weights
+// from L2 instead.
+template <int BN, int NVW>
+struct G1Smem {
+  BfSmem<BN> st;
+  bf16_t wt[NVW > 0 ? BN : 1][NVW > 0 ? NVW : 1];
+};
+
+template <int NVW>
+__device__ inline int wswz(int row, int chunk) {
+  return (chunk ^ (row & (NVW / 8 - 1))) * 8;
+}
+
+// Issue the copies of the weights of rows [n0, n0 + BN), v in [0, NVW): each
+// wave moves 1 KB segments, lane l's 16 bytes landing at segment + 16 l.
+template <int BN, int NVW>
+__device__ inline void g1_weights_dma(G1Smem<BN, NVW>& sm, const bf16_t* __restrict__ w16,
+                                      int nvp, int n0) {
+  constexpr int CPR = NVW / 8;               // 16-byte chunks per row
+  constexpr int RPS = 64 / CPR;              // rows per 1 KB segment
+  constexpr int SEGS = BN / RPS;             // segments per tile
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  // segment q * 4 + w holds rows (q * 4 + w) * RPS + l / CPR; the swizzled
+  // chunk (l % CPR) ^ (row % CPR) does not depend on q
+  const int rl0 = w * RPS + l / CPR;
+  const int c = (l % CPR) ^ (rl0 & (CPR - 1));
+  const bf16_t* src = w16 + (long)(n0 + rl0) * nvp + 8 * c;
+  bf16_t* dst = &sm.wt[0][0] + w * 512;
+  for (int q = 0; q < SEGS / 4; ++q) {
+    __builtin_amdgcn_global_load_lds(src, dst, 16, 0, 0);
+    src += (long)4 * RPS * nvp;
+    dst += 4 * 512;
+  }
+}
+
+template <int BN, int SEG, int NVW>
+__device__ inline void gemm1_bf16_body(const GemmDims& d, int M, int nb,
+                                       const bf16_t* __restrict__ psi_c_rc,
+                                       const float* __restrict__ psi_v_rv,
+                                       const bf16_t* __restrict__ psi_v_rv16,
+                                       const bf16_t* __restrict__ u,
+                                       float* __restrict__ rho_part) {
+  constexpr int WN = BfCfg<BN>::WN;
+  __shared__ G1Smem<BN, NVW> sm;
+  const int mt = (M + HM - 1) / HM, nt = d.nrp / BN;
   const int ng = (nt + G1_TILES - 1) / G1_TILES;
   int mi, gi;
   if (!gemm1_tile(blockIdx.x, mt, ng, mi, gi)) return;
@@ -418,26 +475,42 @@ gemm1_bf16_kernel(GemmDims d, int M, int nb, const bf16_t* __restrict__ psi_c_rc
   const int wm = w >> 1, wn = w & 1;
   const int nsteps = d.ncp / HK;
   LoadU16 la{u, d.ncp};
-  BfStage<LoadU16> x;
-  bf_gload(la, psi_c_rc, d.ncp, m0, nt0 * HN, 0, x);
+  BfStage<LoadU16, BN> x;
+  bf_gload(la, psi_c_rc, d.ncp, m0, nt0 * BN, 0, x);
   for (int ti = nt0; ti < nt1; ++ti) {
-    const int n0 = ti * HN;
-    f16v acc[4][HWN];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < HWN; ++j) acc[i][j] = f16v{};
-    bf_lstore(la, sm, 0, x);
+    const int n0 = ti * BN;
+    f16v acc[4][WN];
+    bf_lstore(la, sm.st, 0, x);
+    __syncthreads();  // also: the previous epilogue has finished reading sm.wt
+    if constexpr (NVW > 0) g1_weights_dma<BN, NVW>(sm, psi_v_rv16, d.nvp, n0);
+    // K step 0 (nsteps >= 2: N_c is padded to a multiple of 64)
+    bf_gload(la, psi_c_rc, d.ncp, m0, n0, HK, x);
+    bf_compute<BN, true>(sm.st, 0, acc);
+    bf_lstore(la, sm.st, 1, x);
     __syncthreads();
-    for (int i = 0; i < nsteps; ++i) {
+    for (int i = 1; i < nsteps; ++i) {
       const int cur = i & 1;
       const bool more = i + 1 < nsteps;
       if (more)
         bf_gload(la, psi_c_rc, d.ncp, m0, n0, (i + 1) * HK, x);
       else if (ti + 1 < nt1)
-        bf_gload(la, psi_c_rc, d.ncp, m0, n0 + HN, 0, x);
-      bf_compute(sm, cur, acc);
-      if (more) bf_lstore(la, sm, cur ^ 1, x);
+        bf_gload(la, psi_c_rc, d.ncp, m0, n0 + BN, 0, x);
+      bf_compute(sm.st, cur, acc);
+      if (more) bf_lstore(la, sm.st, cur ^ 1, x);
+      __syncthreads();
+    }
+    if constexpr (NVW > 0) {
+      // The weight copies were issued before every load still in flight
+      // except the next tile's first K step (4 + QB loads); loads complete in
+      // issue order, so waiting down to that many leaves the copies done.
+      if (ti + 1 < nt1) {
+        if constexpr (BN == 128)
+          asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
+        else
+          asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
+      } else {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      }
       __syncthreads();
     }
     // epilogue: rho_b(r) = sum_v phi_v(r) C1[(b,v), r] over each segment
@@ -449,19 +522,34 @@ gemm1_bf16_kernel(GemmDims d, int M, int nb, const bf16_t* __restrict__ psi_c_rc
         const int b = ms / d.nvp, vbase = ms - b * d.nvp;
         const int vt = vbase / 128;
 #pragma unroll
-        for (int j = 0; j < HWN; ++j) {
-          const int r = n0 + wn * (HN / 2) + 32 * j + (l & 31);
-          const bf16_t* wr = psi_v_rv + (long)r * d.nvp + vbase + 4 * (l >> 5);
+        for (int j = 0; j < WN; ++j) {
+          const int rl = wn * (BN / 2) + 32 * j + (l & 31);
+          const int r = n0 + rl;
           float s = 0.f;
+          if constexpr (NVW > 0) {
 #pragma unroll
-          for (int i = 0; i < SEG; ++i) {
+            for (int i = 0; i < SEG; ++i) {
 #pragma unroll
-            for (int g = 0; g < 4; ++g) {
-              const uint2 wv = *reinterpret_cast<const uint2*>(wr + 32 * i + 8 * g);
-              s += lo_bf16(wv.x) * acc[sg + i][j][4 * g + 0];
-              s += hi_bf16(wv.x) * acc[sg + i][j][4 * g + 1];
-              s += lo_bf16(wv.y) * acc[sg + i][j][4 * g + 2];
-              s += hi_bf16(wv.y) * acc[sg + i][j][4 * g + 3];
+              for (int g = 0; g < 4; ++g) {
+                const int ch = (vbase + 32 * i + 8 * g) >> 3;
+                const uint2 wv =
+                    *reinterpret_cast<const uint2*>(&sm.wt[rl][wswz<NVW>(rl, ch) + 4 * (l >> 5)]);
+                s += lo_bf16(wv.x) * acc[sg + i][j][4 * g + 0];
+                s += hi_bf16(wv.x) * acc[sg + i][j][4 * g + 1];
+                s += lo_bf16(wv.y) * acc[sg + i][j][4 * g + 2];
+                s += hi_bf16(wv.y) * acc[sg + i][j][4 * g + 3];
+              }
+            }
+          } else {
+            const float* wr = psi_v_rv + (long)r * d.nvp + vbase + 4 * (l >> 5);
+#pragma unroll
+            for (int i = 0; i < SEG; ++i) {
+#pragma unroll
+              for (int g = 0; g < 4; ++g) {
+                const f4v wv = *reinterpret_cast<const f4v*>(wr + 32 * i + 8 * g);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) s += wv[e] * acc[sg + i][j][4 * g + e];
+              }
             }
           }
           s += __shfl_xor(s, 32, 64);
@@ -472,48 +560,65 @@ gemm1_bf16_kernel(GemmDims d, int M, int nb, const bf16_t* __restrict__ psi_c_rc
   }
 }
 
-// Second GEMM over one split of the grid sum; one LDS stage prefetched, the
-// A operand scaled by the potential after the current step's MFMAs.
-template <int NVP>
+template <int SEG, int NVW>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
-gemm2_bf16_kernel(GemmDims d, int M, int splitk, int kchunk, const bf16_t* __restrict__ psi_v_t,
-                  const bf16_t* __restrict__ psi_c_t, const float* __restrict__ vpot,
-                  float* __restrict__ ypart) {
-  __shared__ BfSmem sm;
-  const int mt = (M + HM - 1) / HM, nt = (d.ncp + HN - 1) / HN;
+gemm1_bf16_n128_kernel(GemmDims d, int M, int nb, const bf16_t* __restrict__ psi_c_rc,
+                       const float* __restrict__ psi_v_rv, const bf16_t* __restrict__ psi_v_rv16,
+                       const bf16_t* __restrict__ u, float* __restrict__ rho_part) {
+  gemm1_bf16_body<128, SEG, NVW>(d, M, nb, psi_c_rc, psi_v_rv, psi_v_rv16, u, rho_part);
+}
+
+// Second GEMM over one split of the grid sum: global loads two K steps ahead,
+// the A operand of the next step scaled by the potential and stored after the
+// current step's MFMAs.
+template <int BN, int NVP>
+__device__ inline void gemm2_bf16_body(const GemmDims& d, int M, int splitk, int kchunk,
+                                       const bf16_t* __restrict__ psi_v_t,
+                                       const bf16_t* __restrict__ psi_c_t,
+                                       const float* __restrict__ vpot,
+                                       float* __restrict__ ypart) {
+  constexpr int WN = BfCfg<BN>::WN;
+  __shared__ BfSmem<BN> sm;
+  const int mt = (M + HM - 1) / HM, nt = (d.ncp + BN - 1) / BN;
   const int lid = xcd_remap(blockIdx.x, mt * nt * splitk);
   const int s = lid / (mt * nt);
   const int rem = lid - s * mt * nt;
-  const int m0 = (rem % mt) * HM, n0 = (rem / mt) * HN;
+  const int m0 = (rem % mt) * HM, n0 = (rem / mt) * BN;
   const int kb = s * kchunk;
   const int ke = min(d.nrp, kb + kchunk);
-  const int nsteps = ke > kb ? (ke - kb) / HK : 0;
-  f16v acc[4][HWN];
+  const int nsteps = ke > kb ? (ke - kb) / HK : 0;  // even: kchunk and N_rp are multiples of 2 HK
+  f16v acc[4][WN];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < HWN; ++j) acc[i][j] = f16v{};
+    for (int j = 0; j < WN; ++j) acc[i][j] = f16v{};
   LoadPsiV16<NVP> la{psi_v_t, vpot, d.nrp, d.nvp};
-  BfStage<LoadPsiV16<NVP>> x;
+  // Two register stages: the loads of step i + 2 are in flight while step i
+  // computes and step i + 1 is scaled into the other LDS buffer.  The last
+  // steps reload the final slab instead of branching.
+  BfStage<LoadPsiV16<NVP>, BN> x0, x1;
   if (nsteps > 0) {
-    bf_gload(la, psi_c_t, d.nrp, m0, n0, kb, x);
-    bf_lstore(la, sm, 0, x);
+    bf_gload(la, psi_c_t, d.nrp, m0, n0, kb, x0);
+    bf_gload(la, psi_c_t, d.nrp, m0, n0, kb + HK, x1);
+    bf_lstore(la, sm, 0, x0);
   }
   __syncthreads();
-  for (int i = 0; i < nsteps; ++i) {
-    const int cur = i & 1;
-    const bool more = i + 1 < nsteps;
-    if (more) bf_gload(la, psi_c_t, d.nrp, m0, n0, kb + (i + 1) * HK, x);
-    bf_compute(sm, cur, acc);
-    if (more) bf_lstore(la, sm, cur ^ 1, x);
+  for (int i = 0; i < nsteps; i += 2) {
+    bf_gload(la, psi_c_t, d.nrp, m0, n0, kb + min(i + 2, nsteps - 1) * HK, x0);
+    bf_compute(sm, 0, acc);
+    bf_lstore(la, sm, 1, x1);
+    __syncthreads();
+    bf_gload(la, psi_c_t, d.nrp, m0, n0, kb + min(i + 3, nsteps - 1) * HK, x1);
+    bf_compute(sm, 1, acc);
+    bf_lstore(la, sm, 0, x0);
     __syncthreads();
   }
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wm = w >> 1, wn = w & 1;
   float* out = ypart + (long)s * M * d.ncp;
 #pragma unroll
-  for (int j = 0; j < HWN; ++j) {
-    const int n = n0 + wn * (HN / 2) + 32 * j + (l & 31);
+  for (int j = 0; j < WN; ++j) {
+    const int n = n0 + wn * (BN / 2) + 32 * j + (l & 31);
     if (n >= d.ncp) continue;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -523,6 +628,21 @@ gemm2_bf16_kernel(GemmDims d, int M, int splitk, int kchunk, const bf16_t* __res
         if (m < M) out[(long)m * d.ncp + n] = acc[i][j][q];
       }
   }
+}
+
+template <int NVP>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+gemm2_bf16_n128_kernel(GemmDims d, int M, int splitk, int kchunk,
+                       const bf16_t* __restrict__ psi_v_t, const bf16_t* __restrict__ psi_c_t,
+                       const float* __restrict__ vpot, float* __restrict__ ypart) {
+  gemm2_bf16_body<128, NVP>(d, M, splitk, kchunk, psi_v_t, psi_c_t, vpot, ypart);
+}
+template <int NVP>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+gemm2_bf16_n256_kernel(GemmDims d, int M, int splitk, int kchunk,
+                       const bf16_t* __restrict__ psi_v_t, const bf16_t* __restrict__ psi_c_t,
+                       const float* __restrict__ vpot, float* __restrict__ ypart) {
+  gemm2_bf16_body<256, NVP>(d, M, splitk, kchunk, psi_v_t, psi_c_t, vpot, ypart);
 }
 
 }  // namespace
@@ -550,34 +670,44 @@ void gemm2_f64m(const GemmDims& d, int nb, int splitk, const double* psi_v_t,
 
 int gemm1_bf16_vtiles(const GemmDims& d) { return d.nvp >= 128 ? d.nvp / 128 : 1; }
 
-void gemm1_bf16(const GemmDims& d, int nb, const bf16_t* psi_c_rc, const bf16_t* psi_v_rv,
-                const bf16_t* u, float* rho_part, hipStream_t st) {
+void gemm1_bf16(const GemmDims& d, int nb, const bf16_t* psi_c_rc, const float* psi_v_rv,
+                const bf16_t* psi_v_rv16, const bf16_t* u, float* rho_part, hipStream_t st) {
   if (nb <= 0) return;
   const int M = nb * d.nvp;
-  const int blocks = gemm1_grid(ceil_div(M, HM), ceil_div(d.nrp / HN, G1_TILES));
-  if (d.nvp == 64)
-    gemm1_bf16_kernel<2><<<blocks, 256, 0, st>>>(d, M, nb, psi_c_rc, psi_v_rv, u, rho_part);
-  else
-    gemm1_bf16_kernel<4><<<blocks, 256, 0, st>>>(d, M, nb, psi_c_rc, psi_v_rv, u, rho_part);
+  const int blocks = gemm1_grid(ceil_div(M, HM), ceil_div(d.nrp / 128, G1_TILES));
+#define GWL_G1(SEGV, NVWV)                                                                   \
+  gemm1_bf16_n128_kernel<SEGV, NVWV><<<blocks, 256, 0, st>>>(d, M, nb, psi_c_rc, psi_v_rv, \
+                                                             psi_v_rv16, u, rho_part)
+  if (d.nvp == 64) GWL_G1(2, 64);
+  else if (d.nvp == 128) GWL_G1(4, 128);
+  else GWL_G1(4, 0);
+#undef GWL_G1
   GWL_HIP(hipGetLastError());
 }
 
-int gemm2_bf16_blocks(const GemmDims& d, int nb) {
-  return ceil_div(nb * d.nvp, HM) * ceil_div(d.ncp, HN);
+int gemm2_bf16_blocks(const GemmDims& d, int nb, int bn) {
+  return ceil_div(nb * d.nvp, HM) * ceil_div(d.ncp, bn);
 }
 
-void gemm2_bf16(const GemmDims& d, int nb, int splitk, const bf16_t* psi_v_t,
+void gemm2_bf16(const GemmDims& d, int nb, int bn, int splitk, const bf16_t* psi_v_t,
                 const bf16_t* psi_c_t, const float* vpot, float* ypart, hipStream_t st) {
   if (nb <= 0) return;
   const int M = nb * d.nvp;
-  const int kchunk = (int)round_up(ceil_div(d.nrp, splitk), HK);
-  const int blocks = gemm2_bf16_blocks(d, nb) * splitk;
-  if (d.nvp == 64)
-    gemm2_bf16_kernel<64><<<blocks, 256, 0, st>>>(d, M, splitk, kchunk, psi_v_t, psi_c_t, vpot, ypart);
-  else if (d.nvp == 128)
-    gemm2_bf16_kernel<128><<<blocks, 256, 0, st>>>(d, M, splitk, kchunk, psi_v_t, psi_c_t, vpot, ypart);
-  else
-    gemm2_bf16_kernel<0><<<blocks, 256, 0, st>>>(d, M, splitk, kchunk, psi_v_t, psi_c_t, vpot, ypart);
+  const int kchunk = (int)round_up(ceil_div(d.nrp, splitk), 2 * HK);
+  const int blocks = gemm2_bf16_blocks(d, nb, bn) * splitk;
+#define GWL_G2(BNV, NVPV)                                                                   \
+  gemm2_bf16_n##BNV##_kernel<NVPV><<<blocks, 256, 0, st>>>(d, M, splitk, kchunk, psi_v_t, \
+                                                            psi_c_t, vpot, ypart)
+  if (bn == 256) {
+    if (d.nvp == 64) GWL_G2(256, 64);
+    else if (d.nvp == 128) GWL_G2(256, 128);
+    else GWL_G2(256, 0);
+  } else {
+    if (d.nvp == 64) GWL_G2(128, 64);
+    else if (d.nvp == 128) GWL_G2(128, 128);
+    else GWL_G2(128, 0);
+  }
+#undef GWL_G2
   GWL_HIP(hipGetLastError());
 }
 

@@ -310,6 +310,14 @@ gwl_status gwl_set_option(gwl_ctx* ctx, int key, double value) {
         GWL_CHECK(value == 0 || value == 1, GWL_EINVAL, "kernels must be 0 or 1");
         ctx->fp64_kernel = (int)value;
         break;
+      case GWL_KEY_BF16_TILE:
+        GWL_CHECK(value == 128 || value == 256, GWL_EINVAL, "BF16 tile must be 128 or 256");
+        if (ctx->bf16_tile != (int)value) {
+          ctx->bf16_tile = (int)value;
+          ctx->tuned[GWL_MIXED_BF16] = gwl_ctx::Tune{};
+          ctx->drop_graph();
+        }
+        break;
       case GWL_KEY_PROFILE:
         GWL_CHECK(value == 0 || value == 1, GWL_EINVAL, "profile must be 0 or 1");
         ctx->profile = (int)value;
@@ -341,6 +349,7 @@ gwl_status gwl_query(gwl_ctx* ctx, int key, double* out) {
       case GWL_KEY_LAST_C_MATVECS: *out = (double)ctx->last_c_matvecs; break;
       case GWL_KEY_GEMM_SPLITK: *out = ctx->splitk; break;
       case GWL_KEY_KERNELS: *out = ctx->fp64_kernel; break;
+      case GWL_KEY_BF16_TILE: *out = ctx->bf16_tile; break;
       case GWL_KEY_PROFILE: *out = ctx->profile; break;
       case GWL_KEY_GRAPHS: *out = ctx->use_graphs; break;
       case GWL_KEY_TUNED_BLOCK: *out = ctx->tuned[ctx->precision].B; break;

@@ -54,10 +54,10 @@ inline int pad_nv(int nv) { return nv <= 64 ? 64 : (nv <= 128 ? 128 : (int)round
 // The BF16 tiles read whole 256-row A tiles and 128-row B tiles without
 // bounds checks: pair-vector operand rows are allocated to a multiple of 256,
 // potentials to the pair vectors those rows touch, orbital rows of the
-// second GEMM's B operand to a multiple of 128.
+// second GEMM's B operand to a multiple of 256.
 inline long alloc_rows_u(long nb, int nvp) { return round_up(nb * nvp, 256); }
 inline long alloc_rows_v(long nb, int nvp) { return alloc_rows_u(nb, nvp) / nvp + 1; }
-inline long alloc_rows_c(int ncp) { return round_up(ncp, 128); }
+inline long alloc_rows_c(int ncp) { return round_up(ncp, 256); }
 
 // FP64 (plain tiled FMA; reference-quality GPU path).
 int gemm1_f64_vtiles(const GemmDims& d);
@@ -82,11 +82,14 @@ void gemm2_f64m(const GemmDims& d, int nb, int splitk, const double* psi_v_t,
 
 // BF16 operands, FP32 accumulation, on MFMA.
 int gemm1_bf16_vtiles(const GemmDims& d);
-void gemm1_bf16(const GemmDims& d, int nb, const bf16_t* psi_c_rc, const bf16_t* psi_v_rv,
-                const bf16_t* u, float* rho_part, hipStream_t st);
-int gemm2_bf16_blocks(const GemmDims& d, int nb);  // blocks per split of the K range
+// psi_v_rv: FP32 [N_rp][N_vp] epilogue weights; psi_v_rv16: the same in BF16
+// (used when N_vp is 64 or 128)
+void gemm1_bf16(const GemmDims& d, int nb, const bf16_t* psi_c_rc, const float* psi_v_rv,
+                const bf16_t* psi_v_rv16, const bf16_t* u, float* rho_part, hipStream_t st);
+// bn = block tile width of the second GEMM (128 or 256)
+int gemm2_bf16_blocks(const GemmDims& d, int nb, int bn);  // blocks per split of the K range
 int gemm2_f64m_blocks(const GemmDims& d, int nb);
-void gemm2_bf16(const GemmDims& d, int nb, int splitk, const bf16_t* psi_v_t,
+void gemm2_bf16(const GemmDims& d, int nb, int bn, int splitk, const bf16_t* psi_v_t,
                 const bf16_t* psi_c_t, const float* vpot, float* ypart, hipStream_t st);
 
 // ---------------------------------------------------------------- pair-space ops

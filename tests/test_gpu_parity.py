@@ -367,9 +367,16 @@ def test_mfma_matches_plain_kernels(request, which):
     for kern in (0, 1):
         ctx.set_option(G.KEY_KERNELS, kern)
         out[kern] = {p: ctx.apply_c(x, p).cpu().numpy() for p in ("fp64", "mixed")}
-    ctx.set_option(G.KEY_KERNELS, 1)
     assert relerr(out[1]["fp64"], out[0]["fp64"]) <= 1e-13
     assert relerr(out[1]["mixed"], out[0]["mixed"]) <= 1e-5
+    # both block tiles of the second BF16 GEMM (256 is the default)
+    try:
+        ctx.set_option(G.KEY_BF16_TILE, 128)
+        assert ctx.query(G.KEY_BF16_TILE) == 128
+        m128 = ctx.apply_c(x, "mixed").cpu().numpy()
+    finally:
+        ctx.set_option(G.KEY_BF16_TILE, 256)
+    assert relerr(m128, out[0]["mixed"]) <= 1e-5
 
 
 # ------------------------------------------------------------------ graphs and tuner
