@@ -4,9 +4,9 @@
 Workload (grid64_v128c512): 64^3 grid in a 24 bohr box, 128 occupied + 512
 empty seeded orthonormal real orbitals (pair dimension 65,536), Lanczos on
 p_7(C) with L = 200 steps, 2,000 frequencies in [-20, 20] eV, broadening
-0.05 eV, full reorthogonalisation.  Arithmetic: GEMM operands BF16 with FP32
-accumulation, FP32 FFT, FP64 Lanczos recurrence / Chebyshev combination /
-continued fraction.
+0.05 eV, full reorthogonalisation.  Arithmetic: first GEMM on FP16 operands,
+second GEMM on BF16 operands, FP32 accumulation, FP32 FFT, FP64 Lanczos
+recurrence / Chebyshev combination / continued fraction.
 
 One step = one block of B start vectors (m, n) of one quasiparticle state m
 through the whole path: coupling vectors P_nm, L Lanczos steps on p_g(C)
@@ -18,6 +18,16 @@ Also reported: the plain FP64 GPU path on a steady-state window (B vectors,
 a few Lanczos steps) extrapolated to spectra/s, the mixed-vs-FP64 error on a
 sample, the roofline fraction of the dominant kernel (HIP events on the
 library's stream), and the FP64 CPU oracle on a bounded sample.
+
+Two further measurements print their own line:
+  --mode uneven   batched start vectors with uneven Lanczos lengths
+                  (grid64_v128c512_pairs1024: drawn (m, n) pairs, lengths
+                  U[50, 300]); vector-steps/s for B in {32, 64, 128, 256}, with
+                  and without graph replay, on the first --pairs pairs.
+  --mode adjoint  forward Sigma_c and its vector-Jacobian product in FP64 on
+                  grid48_v64c256 (48^3 grid, 64 + 256 orbitals, L = 120,
+                  32 frequencies) for one quasiparticle state; the ratio of
+                  the two times.
 """
 from __future__ import annotations
 
@@ -32,7 +42,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_BF16_TFLOPS = 2500.0   # MI355X dense BF16 MFMA
+PEAK_16BIT_TFLOPS = 2500.0  # MI355X dense FP16 / BF16 MFMA
 PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 matrix
 METRIC = "Sigma_c spectra/s & matvec TFLOP/s, mixed vs FP64 on 1 GPU at 1e-3 eV"
 
@@ -92,9 +102,97 @@ def cpu_baseline(wl, phi, eps, m, n, steps, lo, hi):
     }
 
 
+def run_uneven(args):
+    import torch
+    import gw_inputs as gi
+    import paper_2310_20103_amd as G
+    wl = gi.workload("grid64_v128c512_pairs1024")
+    sysm = gi.make_system(wl)
+    ex = sysm.extras
+    P = min(args.pairs, wl.n_pairs)
+    m, n, lens = ex["m_idx"][:P], ex["n_idx"][:P], ex["lengths"][:P]
+    box = tuple(k * wl.h for k in wl.grid)
+    ctx = G.Context(sysm.phi, sysm.energies_ev, wl.n_occ, wl.grid, box, precision="mixed",
+                    poly_degree=wl.poly_degree, reorth="full")
+    runs = []
+    for B, graphs in ((32, 1), (64, 1), (128, 1), (256, 1), (128, 0)):
+        ctx.set_block(B)
+        ctx.set_option(G.KEY_GRAPHS, graphs)
+        ctx.lanczos_pairs(m[:B], n[:B], [1] * min(B, P))
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ctx.lanczos_pairs(m, n, lens)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        vs = float(np.sum(lens))
+        runs.append({"block": B, "graphs": bool(graphs), "seconds": round(dt, 3),
+                     "vector_steps_per_s": round(vs / dt, 2),
+                     "partial_spectra_per_s": round(P / wl.n_orb / dt, 6),
+                     "matvec_tflops": round(4.0 * wl.n_r * wl.n_occ * wl.n_emp
+                                            * ctx.query(G.KEY_LAST_C_MATVECS) / dt / 1e12, 1)})
+        log(f"uneven B={B} graphs={graphs}: {dt:.1f}s")
+    ctx.close()
+    best = max(runs, key=lambda r: r["vector_steps_per_s"])
+    print(json.dumps({
+        "metric": "Lanczos vector-steps/s, uneven lengths, mixed precision", "unit": "vector-steps/s",
+        "value": best["vector_steps_per_s"], "n_gpus": 1, "higher_is_better": True,
+        "dtype": "f16/bf16", "data": "synthetic",
+        "config": {"workload": wl.name, "pairs": int(P), "lengths": "U[50, 300]",
+                   "vector_steps": int(np.sum(lens)), "poly_degree": wl.poly_degree,
+                   "reorth": "full"},
+        "runs": runs}), flush=True)
+
+
+def run_adjoint(args):
+    import torch
+    import gw_inputs as gi
+    import paper_2310_20103_amd as G
+    wl = gi.workload("grid48_v64c256")
+    phi = gi.make_orbitals(wl)
+    eps = gi.make_energies(wl)
+    qp = gi.frontier_states(eps, wl.n_occ, wl.n_qp_occ, wl.n_qp_emp)
+    omega = gi.omega_grid(wl)
+    box = tuple(k * wl.h for k in wl.grid)
+    m = [int(qp[0])]
+    rng = np.random.default_rng([wl.seed, 9])
+    cot = rng.standard_normal((1, wl.n_omega)) + 1j * rng.standard_normal((1, wl.n_omega))
+    ctx = G.Context(phi, eps, wl.n_occ, wl.grid, box, precision="fp64",
+                    poly_degree=wl.poly_degree, reorth="none", block=args.block)
+    ctx.lanczos_pairs([m[0]] * 2, [0, 1], [1, 1])
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    sig = ctx.sigma_c(m, omega, wl.eta, wl.n_lanczos)
+    t_fwd = time.perf_counter() - t
+    log(f"adjoint: forward {t_fwd:.1f}s")
+    t = time.perf_counter()
+    sig2, ge, go = ctx.sigma_c_vjp(m, omega, wl.eta, wl.n_lanczos, cot)
+    torch.cuda.synchronize()
+    t_vjp = time.perf_counter() - t
+    log(f"adjoint: vjp {t_vjp:.1f}s")
+    same = float(np.max(np.abs(sig2 - sig)) / max(np.max(np.abs(sig)), 1e-300))
+    ctx.set_reorth("full")
+    t = time.perf_counter()
+    ctx.sigma_c(m, omega, wl.eta, wl.n_lanczos)
+    t_full = time.perf_counter() - t
+    ctx.close()
+    print(json.dumps({
+        "metric": "Sigma_c vector-Jacobian product time / forward time, FP64", "unit": "ratio",
+        "value": round(t_vjp / t_fwd, 3), "n_gpus": 1, "higher_is_better": False,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": wl.name, "qp_states": 1, "start_vectors": wl.n_orb,
+                   "n_lanczos": wl.n_lanczos, "n_omega": wl.n_omega, "block": args.block},
+        "forward_s": round(t_fwd, 3), "vjp_s_incl_forward": round(t_vjp, 3),
+        "forward_full_reorth_s": round(t_full, 3),
+        "vjp_sigma_vs_forward_rel": same,
+        "grad_norms": {"energies": float(np.linalg.norm(ge)),
+                       "orbitals": float(torch.linalg.norm(go).item())}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--mode", choices=("headline", "uneven", "adjoint"), default="headline")
+    ap.add_argument("--pairs", type=int, default=256, help="uneven mode: pairs measured")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--block", type=int, default=128)
@@ -109,6 +207,12 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.mode == "uneven":
+        return run_uneven(args)
+    if args.mode == "adjoint":
+        if args.block == 128:
+            args.block = 64
+        return run_adjoint(args)
 
     import torch
     import gw_inputs as gi
@@ -179,12 +283,13 @@ def main():
     ms, cnt, vec = prof[dom]
     flop_launch = 2.0 * wl.n_r * wl.n_occ * wl.n_emp * (vec / max(cnt, 1))
     achieved = flop_launch / (ms / max(cnt, 1) / 1e3) / 1e12 if cnt else 0.0
-    traffic = measured_traffic(f"{dom}_bf16", wl.name, B)
-    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4),
+    kname = {"gemm1": "gemm1_f16", "gemm2": "gemm2_bf16"}[dom]
+    traffic = measured_traffic(kname, wl.name, B)
+    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_16BIT_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_16BIT_TFLOPS, 4),
                 "traffic": traffic, "traffic_unit": "bytes per launch",
                 "algorithmic_flop_per_launch": flop_launch,
-                "kernel": f"{dom}_bf16", "launches": int(cnt),
+                "kernel": kname, "launches": int(cnt),
                 "avg_launch_ms": round(ms / max(cnt, 1), 4)}
     kernel_ms = {k: round(v[0], 2) for k, v in prof.items()}
 
@@ -215,7 +320,7 @@ def main():
         "metric": METRIC, "value": round(value, 6), "unit": "spectra/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(elapsed / max(args.steps, 1) * 1e3, 2),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f16/bf16",
         "data": "synthetic",
         "config": {"workload": wl.name, "grid": list(wl.grid), "box_bohr": wl.box,
                    "n_occ": wl.n_occ, "n_emp": wl.n_emp, "pair_dim": wl.n_vc,

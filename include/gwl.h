@@ -68,7 +68,11 @@ typedef enum {
  * FP64 in every mode. */
 typedef enum {
   GWL_FP64 = 0,       /* GEMMs and FFT in FP64 */
-  GWL_MIXED_BF16 = 1  /* GEMM operands BF16 with FP32 accumulation, FFT FP32 */
+  GWL_MIXED_BF16 = 1  /* mixed: first GEMM on FP16 operands (pair vectors and orbitals
+                         scaled by powers of two into FP16's range), second GEMM on
+                         BF16 operands, both with FP32 accumulation; FFT FP32;
+                         recurrence, Chebyshev combination and continued fraction
+                         FP64 */
 } gwl_precision;
 
 /* Reorthogonalisation of the Lanczos vectors (the paper does not prescribe
@@ -239,9 +243,20 @@ enum {
   GWL_KEY_TUNED_BLOCK = 24,     /* query: slots B chosen by the autotuner (block = 0) for the
                                    current precision, 0 before the first tuned call */
   GWL_KEY_TUNED_SPLITK = 25,    /* query: split chosen with it */
-  GWL_KEY_BF16_TILE = 26        /* set/query: block tile width of the second BF16 GEMM, 256
+  GWL_KEY_BF16_TILE = 26,       /* set/query: block tile width of the second BF16 GEMM, 256
                                    (default: one wave per SIMD, accumulators in AGPRs) or
                                    128 (two waves per SIMD) */
+  GWL_KEY_TDA = 27              /* set/query: 0 (default) = the full method above; 1 =
+                                   Tamm-Dancoff approximation (B = 0 in the Casida matrix,
+                                   the variant the paper's closing discussion names): the
+                                   Lanczos operator is A = Delta + K (no square root, no
+                                   polynomial; the interval is unused), start vectors are
+                                   k_nm = (nm|vc) (gwl_coupling returns these), and
+                                   Sigma(w, n) = -eta_n R_A(-eta_n z_n).  Applies to
+                                   gwl_sigma_c, gwl_sigma_c_range, gwl_lanczos_pairs,
+                                   gwl_sigma_from_coeffs and gwl_coupling; gwl_apply_c and
+                                   gwl_apply_d keep their meaning; gwl_sigma_c_vjp returns
+                                   GWL_EUNSUPPORTED while it is set. */
 };
 /* The autotuner runs on the first gwl_sigma_c / gwl_sigma_c_range /
  * gwl_lanczos_pairs call with block = 0: it times one C-product for

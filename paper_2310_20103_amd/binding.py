@@ -23,7 +23,7 @@ REORTH = {"none": 0, "local": 1, "full": 2}
 KEY_PRECISION, KEY_REORTH, KEY_BLOCK, KEY_POLY_LO, KEY_POLY_HI, KEY_POLY_DEGREE = 1, 2, 3, 4, 5, 6
 KEY_N_VC, KEY_LAST_MS_TOTAL, KEY_LAST_C_MATVECS, KEY_GEMM_SPLITK, KEY_KERNELS = 7, 9, 10, 11, 12
 KEY_PROFILE = 13
-KEY_GRAPHS, KEY_TUNED_BLOCK, KEY_TUNED_SPLITK, KEY_BF16_TILE = 23, 24, 25, 26
+KEY_GRAPHS, KEY_TUNED_BLOCK, KEY_TUNED_SPLITK, KEY_BF16_TILE, KEY_TDA = 23, 24, 25, 26, 27
 KEY_PROF = {"gemm1": (14, 15, 16), "gemm2": (17, 18, 19), "fft": (20, 21, 22)}
 PRECISIONS = {"fp64": FP64, "mixed": MIXED_BF16, "bf16": MIXED_BF16}
 
@@ -223,6 +223,10 @@ class Context:
 
     def set_block(self, b: int):
         self.set_option(KEY_BLOCK, b)
+
+    def set_tda(self, on: bool):
+        """Tamm-Dancoff approximation on (Lanczos on A = Delta + K) or off."""
+        self.set_option(KEY_TDA, 1 if on else 0)
 
     def profile_totals(self):
         """{kernel: (event ms, launches, pair vectors)} of the last call when

@@ -1,6 +1,8 @@
 // Continued fraction (Haydock, Eq. 14) and assembly of Sigma(w, n) (Eq. 12):
 //   R(zeta) = ||P||^2 / (zeta - a_0 - b_1^2 / (zeta - a_1 - ...)),
 //   Sigma(w, n) = [R(-eta_n z_n) - R(0)] / z_n,  z_n = w - e_n - i eta_n delta.
+// Tamm-Dancoff (B = 0 in the Casida matrix, Lanczos on A from (nm|vc)):
+//   Sigma(w, n) = -eta_n R_A(-eta_n z_n).
 // FP64 complex.  One thread per (pair, frequency); the pair's coefficients are
 // staged in LDS.  Both evaluation points are off the spectrum (Im = +delta, or
 // 0 below the positive spectrum of D), so the backward recurrence never
@@ -17,7 +19,7 @@ __global__ void __launch_bounds__(256)
 cfrac_kernel(const double* __restrict__ ca, const double* __restrict__ cb,
              const int* __restrict__ lens, const double* __restrict__ norm2, int ld,
              const double* __restrict__ e_n, const double* __restrict__ eta_n,
-             const double* __restrict__ omega, int nomega, double delta,
+             const double* __restrict__ omega, int nomega, double delta, int tda,
              double* __restrict__ sig) {
   __shared__ double sa[CF_MAXL];
   __shared__ double sb2[CF_MAXL];
@@ -59,11 +61,16 @@ cfrac_kernel(const double* __restrict__ ca, const double* __restrict__ cb,
       // R(zeta) = n2 / t
       const double d = 1.0 / (tr * tr + ti * ti);
       const double rr = n2 * tr * d, ri = -n2 * ti * d;
-      // (R - r0) / z
-      const double nr = rr - r0, ni = ri;
-      const double dz = 1.0 / (zr * zr + zi * zi);
-      sr = (nr * zr + ni * zi) * dz;
-      si = (ni * zr - nr * zi) * dz;
+      if (tda) {
+        sr = -eta * rr;
+        si = -eta * ri;
+      } else {
+        // (R - r0) / z
+        const double nr = rr - r0, ni = ri;
+        const double dz = 1.0 / (zr * zr + zi * zi);
+        sr = (nr * zr + ni * zi) * dz;
+        si = (ni * zr - nr * zi) * dz;
+      }
     }
     sig[((long)p * nomega + w) * 2] = sr * kHartreeEv;
     sig[((long)p * nomega + w) * 2 + 1] = si * kHartreeEv;
@@ -84,13 +91,13 @@ __global__ void sum_groups_kernel(const double* __restrict__ sig, int per, int n
 
 void cfrac_sigma(int npairs, const double* coef_a, const double* coef_b, const int* lens,
                  const double* norm2, int ld, const double* e_n, const double* eta_n,
-                 const double* omega_ha, int nomega, double delta_ha, double* sig,
+                 const double* omega_ha, int nomega, double delta_ha, int tda, double* sig,
                  hipStream_t st) {
   if (npairs <= 0 || nomega <= 0) return;
   GWL_CHECK(ld <= CF_MAXL, GWL_EINVAL, "Lanczos length exceeds 4000");
   dim3 grid(ceil_div(nomega, 256), npairs);
   cfrac_kernel<<<grid, 256, 0, st>>>(coef_a, coef_b, lens, norm2, ld, e_n, eta_n, omega_ha,
-                                     nomega, delta_ha, sig);
+                                     nomega, delta_ha, tda, sig);
   GWL_HIP(hipGetLastError());
 }
 

@@ -54,6 +54,25 @@ __host__ __device__ inline float bf16_to_f32(bf16_t h) {
   return f;
 }
 
+// raw IEEE binary16 bits (a distinct type so that overloads can tell it from
+// bfloat16); conversions round to nearest even
+struct f16_t {
+  uint16_t bits;
+};
+
+__host__ __device__ inline f16_t f32_to_f16(float f) {
+  const _Float16 h = (_Float16)f;
+  f16_t r;
+  __builtin_memcpy(&r.bits, &h, 2);
+  return r;
+}
+
+__host__ __device__ inline float f16_to_f32(f16_t v) {
+  _Float16 h;
+  __builtin_memcpy(&h, &v.bits, 2);
+  return (float)h;
+}
+
 template <typename T>
 struct cplx {
   T x, y;

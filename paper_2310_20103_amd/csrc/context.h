@@ -134,6 +134,19 @@ struct gwl_ctx {
   int splitk = 0;  // 0 = automatic
   int fp64_kernel = 1;  // 0 = plain FMA tiles, 1 = MFMA (both precisions)
   int bf16_tile = 256;  // block tile width of the second BF16 MFMA GEMM
+  int tda = 0;          // 1: Tamm-Dancoff (Lanczos on A = Delta + K from (nm|vc))
+  // FP16 first GEMM of the mixed path: the orbital operands carry orb16_scale
+  // and the pair-vector operand u_scale (powers of two chosen from bounds so
+  // that no element exceeds 2^14); the combine undoes both
+  double orb16_scale = 1.0, u_scale = 1.0, sd_max = 1.0;
+  // u_scale for vectors of 2-norm <= norm: |u_i| <= max(Delta^1/2, 1) * norm,
+  // and the Chebyshev iterates stay within the same bound
+  void set_u_bound(double norm) {
+    const double bound = std::max(sd_max, 1.0) * std::max(norm, 1e-300);
+    int e = (int)std::floor(std::log2(16384.0 / bound));
+    e = std::max(-60, std::min(60, e));
+    u_scale = std::ldexp(1.0, e);
+  }
   std::vector<double> cheb;
   std::vector<double> eps_ha;
 
@@ -142,10 +155,10 @@ struct gwl_ctx {
   DevBuf<double> psi_c_rc64;  // [NRp][NCp]
   DevBuf<double> psi_v_rv64;  // [NRp][NVp]
   DevBuf<bf16_t> psi_t16;     // [NVp + NCp][NRp]
-  DevBuf<bf16_t> psi_c_rc16;  // [NRp][NCp]
-  DevBuf<float> psi_v_rv32;   // [NRp][NVp] (BF16 kernel epilogues)
-  DevBuf<bf16_t> psi_v_rv16;  // [NRp][NVp] (MFMA BF16 epilogue, N_vp <= 128)
-  DevBuf<double> delta2, sdelta;
+  DevBuf<f16_t> psi_c_rc16;   // [NRp][NCp] FP16, scaled by orb16_scale
+  DevBuf<float> psi_v_rv32;   // [NRp][NVp] FP32, scaled (other mixed epilogues)
+  DevBuf<f16_t> psi_v_rv16;   // [NRp][NVp] FP16, scaled (MFMA epilogue, N_vp <= 128)
+  DevBuf<double> delta1, delta2, sdelta;
 
   // FFT tables
   DevBuf<cplx<double>> tw64[3];
@@ -163,7 +176,7 @@ struct gwl_ctx {
   // c >= N_c, r >= N_r) are written once at allocation and must never hold
   // the other precision's bytes.
   DevBuf<double> u64;          // [cap][NVp][NCp]
-  DevBuf<bf16_t> u16;          // [cap][NVp][NCp]
+  DevBuf<f16_t> u16;           // [cap][NVp][NCp] FP16, scaled by u_scale
   DevBuf<unsigned char> rho;   // [nvt][cap][NRp] x 8 (fully written by the first GEMM)
   DevBuf<double> vpot64;       // [cap][NRp]
   DevBuf<float> vpot32;        // [cap][NRp]
@@ -171,7 +184,9 @@ struct gwl_ctx {
   DevBuf<unsigned char> ypart; // [S][cap][NVp][NCp] x 8
   DevBuf<double> basis;        // [cap][cap_L][nvc]
   DevBuf<double> hbuf;         // [cap][cap_L + 1]
-  DevBuf<int> s_pair, s_k, s_len, s_dead, s_slots, s_m, s_n;
+  DevBuf<int> s_pair, s_k, s_len, s_dead, s_slots, s_m, s_n, s_act;
+  // while set, GEMM operand rows map to these slots (see PairGeom::rows)
+  const int* cur_rows = nullptr;
   DevBuf<double> s_amax, s_bprev;
   // per-call pair data
   DevBuf<double> coef_a, coef_b, norm2;
@@ -186,7 +201,7 @@ struct gwl_ctx {
   int use_graphs = 1;
   hipGraphExec_t dgraph = nullptr;
   int dg_nb = -1, dg_prec = -1, dg_S = -1, dg_kern = -1, dg_deg = -1;
-  double dg_lo = 0, dg_hi = 0;
+  double dg_lo = 0, dg_hi = 0, dg_uscale = 0;
   long work_gen = 0, dg_gen = -1;
 
   // autotuned (block, split) per precision
@@ -251,8 +266,12 @@ struct gwl_ctx {
     prof_recs.clear();
   }
 
-  PairGeom pair_geom() const {
+  // a_op: geometry of the Tamm-Dancoff product / coupling vectors
+  PairGeom pair_geom(bool a_op = false) const {
     PairGeom g;
+    g.rows = cur_rows;
+    g.tda = a_op ? 1 : 0;
+    g.delta = delta1.p;
     g.nv = nv;
     g.nc = nc;
     g.nvp = gd.nvp;
@@ -265,8 +284,8 @@ struct gwl_ctx {
   }
 
   int nvt_max() const {
-    return std::max(std::max(gemm1_f64_vtiles(gd), gemm1_bf16s_vtiles(gd)),
-                    std::max(gemm1_f64m_vtiles(gd), gemm1_bf16_vtiles(gd)));
+    return std::max(std::max(gemm1_f64_vtiles(gd), gemm1_f16s_vtiles(gd)),
+                    std::max(gemm1_f64m_vtiles(gd), gemm1_f16_vtiles(gd)));
   }
 
   // Split of the grid sum in the second GEMM: enough blocks to give every
@@ -311,6 +330,7 @@ struct gwl_ctx {
       s_len.ensure(nb);
       s_dead.ensure(nb);
       s_slots.ensure(nb);
+      s_act.ensure(nb);
       s_m.ensure(nb);
       s_n.ensure(nb);
       s_amax.ensure(nb);
@@ -358,18 +378,18 @@ struct gwl_ctx {
         gemm2_f64(gd, nb, S, pv, pc, vp, yp, st);
       prof_end(1, nb);
     } else {
-      const bf16_t* uu = u16.p;
+      const f16_t* uu = u16.p;
       float* rp = reinterpret_cast<float*>(rho.p);
       float* vp = vpot32.p;
       float* yp = reinterpret_cast<float*>(ypart.p);
       int nvt;
       prof_begin();
       if (fp64_kernel) {
-        gemm1_bf16(gd, nb, psi_c_rc16.p, psi_v_rv32.p, psi_v_rv16.p, uu, rp, st);
-        nvt = gemm1_bf16_vtiles(gd);
+        gemm1_f16(gd, nb, psi_c_rc16.p, psi_v_rv32.p, psi_v_rv16.p, uu, rp, st);
+        nvt = gemm1_f16_vtiles(gd);
       } else {
-        gemm1_bf16s(gd, nb, psi_c_rc16.p, psi_v_rv32.p, uu, rp, st);
-        nvt = gemm1_bf16s_vtiles(gd);
+        gemm1_f16s(gd, nb, psi_c_rc16.p, psi_v_rv32.p, uu, rp, st);
+        nvt = gemm1_f16s_vtiles(gd);
       }
       prof_end(0, nb);
       prof_begin();
@@ -387,25 +407,39 @@ struct gwl_ctx {
     }
   }
 
-  void cast(int nb, const double* x, int prec) {
-    PairGeom g = pair_geom();
-    if (prec == GWL_FP64)
+  void cast(int nb, const double* x, int prec, bool a_op = false) {
+    PairGeom g = pair_geom(a_op);
+    if (prec == GWL_FP64) {
       cast_u<double>(g, nb, x, nvc, u64.p, stream);
-    else
-      cast_u<bf16_t>(g, nb, x, nvc, u16.p, stream);
+    } else {
+      g.uscale = u_scale;
+      cast_u<f16_t>(g, nb, x, nvc, u16.p, stream);
+    }
   }
 
   void do_combine(int nb, int S, int prec, const double* x, const double* tp, double* out,
                   double* acc, int mode, double c0, double cj, bool write_u) {
-    PairGeom g = pair_geom();
+    PairGeom g = pair_geom(mode == 3);
     if (prec == GWL_FP64)
       combine<double, double>(g, nb, S, reinterpret_cast<const double*>(ypart.p), x, tp, out,
                               acc, mode, poly_lo, poly_hi, c0, cj,
                               write_u ? u64.p : nullptr, stream);
-    else
-      combine<float, bf16_t>(g, nb, S, reinterpret_cast<const float*>(ypart.p), x, tp, out,
-                             acc, mode, poly_lo, poly_hi, c0, cj,
-                             write_u ? u16.p : nullptr, stream);
+    else {
+      g.uscale = u_scale;
+      g.yscale = 1.0 / (u_scale * orb16_scale * orb16_scale);
+      combine<float, f16_t>(g, nb, S, reinterpret_cast<const float*>(ypart.p), x, tp, out,
+                            acc, mode, poly_lo, poly_hi, c0, cj,
+                            write_u ? u16.p : nullptr, stream);
+    }
+  }
+
+  // out = A x = Delta x + K x (Tamm-Dancoff) for nb vectors; uses u, ypart.
+  void apply_a_batch(int nb, const double* x, double* out, int prec) {
+    const int S = auto_splitk(nb, prec);
+    last_c_matvecs += nb;
+    cast(nb, x, prec, true);
+    k_product(nb, prec, S);
+    do_combine(nb, S, prec, x, nullptr, out, nullptr, 3, 0, 0, false);
   }
 
   // out = C x for nb vectors (x, out device [nb][nvc]); uses u, ypart.
@@ -463,7 +497,7 @@ struct gwl_ctx {
       gemm2_f64m(gd, cnt, S, pv, pc, vp, yp, stream);
     else
       gemm2_f64(gd, cnt, S, pv, pc, vp, yp, stream);
-    coupling_finish<double>(pair_geom(), cnt, S, yp, dst, ldp, stream);
+    coupling_finish<double>(pair_geom(tda != 0), cnt, S, yp, dst, ldp, stream);
   }
 
   // w = p_g(C) q over nb slots; replays a captured graph of the whole product
@@ -472,12 +506,17 @@ struct gwl_ctx {
   void apply_d_step(int nb, int prec) {
     last_c_matvecs += (long)nb * poly_degree;
     const int S = auto_splitk(nb, prec);
+    if (cur_rows) {  // a subset of the slots: launched eagerly
+      apply_d_batch(nb, q.p, w.p, prec, false);
+      return;
+    }
     if (!use_graphs || profile) {
       apply_d_batch(nb, q.p, w.p, prec, false);
       return;
     }
     if (!dgraph || dg_nb != nb || dg_prec != prec || dg_S != S || dg_kern != fp64_kernel ||
-        dg_gen != work_gen || dg_deg != poly_degree || dg_lo != poly_lo || dg_hi != poly_hi) {
+        dg_gen != work_gen || dg_deg != poly_degree || dg_lo != poly_lo || dg_hi != poly_hi ||
+        dg_uscale != u_scale) {
       drop_graph();
       hipGraph_t g = nullptr;
       GWL_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
@@ -503,6 +542,7 @@ struct gwl_ctx {
       dg_deg = poly_degree;
       dg_lo = poly_lo;
       dg_hi = poly_hi;
+      dg_uscale = u_scale;
     }
     GWL_HIP(hipGraphLaunch(dgraph, stream));
   }
@@ -613,6 +653,7 @@ struct gwl_ctx {
   void run_pairs(int P, const int* m_host, const int* n_host, const int* len_host, int ld,
                  bool on_c = false, const double* start_dev = nullptr) {
     const int prec = precision;
+    set_u_bound(1.0);  // Lanczos vectors have unit norm
     int B;
     if (block > 0) {
       B = block;
@@ -645,8 +686,14 @@ struct gwl_ctx {
     std::vector<int> hp(B, -1), hk(B, 0), hl(B, 0);
     GWL_HIP(hipMemcpyAsync(s_pair.p, hp.data(), B * sizeof(int), hipMemcpyHostToDevice, stream));
     GWL_HIP(hipStreamSynchronize(stream));
+    // longest runs first, so that the slots still busy when the queue
+    // runs dry hold the shortest ones
+    std::vector<int> order(P);
+    for (int i = 0; i < P; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return len_host[a] > len_host[b]; });
     int next = 0;
-    std::vector<int> slots, ms, ns;
+    std::vector<int> slots, ms, ns, act, act_dev;
     while (true) {
       // refill
       slots.clear();
@@ -654,12 +701,13 @@ struct gwl_ctx {
       ns.clear();
       for (int b = 0; b < B && next < P; ++b) {
         if (hp[b] < 0 || hk[b] >= hl[b]) {
-          hp[b] = next;
+          const int pi = order[next];
+          hp[b] = pi;
           hk[b] = 0;
-          hl[b] = len_host[next];
+          hl[b] = len_host[pi];
           slots.push_back(b);
-          ms.push_back(m_host[next]);
-          ns.push_back(n_host[next]);
+          ms.push_back(m_host[pi]);
+          ns.push_back(n_host[pi]);
           ++next;
         }
       }
@@ -695,19 +743,35 @@ struct gwl_ctx {
         lz_start(ss, B, s_slots.p, cnt, q.p, qprev.p, full ? basis.p : nullptr, bstride, nvc,
                  stream);
       }
-      bool any = false;
       int kmax = 0;
+      act.clear();
       for (int b = 0; b < B; ++b)
         if (hp[b] >= 0 && hk[b] < hl[b]) {
-          any = true;
+          act.push_back(b);
           kmax = std::max(kmax, hk[b]);
         }
-      if (!any) break;
-      // one Lanczos step for every slot
-      if (on_c)
-        apply_c_batch(B, q.p, w.p, prec);
-      else
-        apply_d_step(B, prec);
+      if (act.empty()) break;
+      // one Lanczos step for every slot; once slots fall idle (queue empty)
+      // the product runs over the busy ones only
+      const int nact = (int)act.size();
+      if (nact < B && act != act_dev) {
+        GWL_HIP(hipStreamSynchronize(stream));
+        GWL_HIP(hipMemcpy(s_act.p, act.data(), nact * sizeof(int), hipMemcpyHostToDevice));
+        act_dev = act;
+      }
+      if (nact < B) cur_rows = s_act.p;
+      try {
+        if (on_c)
+          apply_c_batch(nact, q.p, w.p, prec);
+        else if (tda)
+          apply_a_batch(nact, q.p, w.p, prec);
+        else
+          apply_d_step(nact, prec);
+      } catch (...) {
+        cur_rows = nullptr;
+        throw;
+      }
+      cur_rows = nullptr;
       lz_alpha(ss, B, q.p, qprev.p, w.p, nvc, stream);
       lz_reorth(ss, B, kmax, reorth, full ? basis.p : nullptr, bstride, q.p, qprev.p, w.p,
                 hbuf.p, nvc, stream);
@@ -751,14 +815,17 @@ struct gwl_ctx {
     start.ensure(nvc);
     GWL_HIP(hipMemcpy(start.p, x0.data(), nvc * sizeof(double), hipMemcpyHostToDevice));
     const int saved_reorth = reorth, saved_block = block, saved_prec = precision;
+    const int saved_tda = tda;
     reorth = GWL_REORTH_FULL;
     block = 1;
     precision = GWL_FP64;
+    tda = 0;
     int m0 = 0, n0 = 0, len = steps;
     run_pairs(1, &m0, &n0, &len, steps, true, start.p);
     reorth = saved_reorth;
     block = saved_block;
     precision = saved_prec;
+    tda = saved_tda;
     std::vector<double> a(steps), b(steps);
     int L = 0;
     GWL_HIP(hipMemcpy(a.data(), coef_a.p, steps * sizeof(double), hipMemcpyDeviceToHost));

@@ -13,12 +13,14 @@
 // into LDS, so the per-vector operand never exists in HBM either.
 //
 // FP64: v_mfma_f64_16x16x4f64, block tile 128 x 128 x 16, 4 waves of 64 x 64.
-// BF16: v_mfma_f32_32x32x16_bf16 (FP32 accumulation), block tile
-//       256 x 128 x 32, 4 waves of 128 x 64.
+// Mixed path: the first GEMM on FP16 operands (v_mfma_f32_32x32x16_f16; the
+// pair vector is scaled by a power of two into FP16's range), the second on
+// BF16 operands (v_mfma_f32_32x32x16_bf16, whose range holds phi_v V without
+// scaling), both with FP32 accumulation; block tiles 256 x 128 x 32 (4 waves
+// of 128 x 64) and, for the second GEMM, 256 x 256 x 32.
 // Tiles are staged through LDS with the next K step prefetched into registers
-// (BF16: two XOR-swizzled LDS stages, one barrier per K step, the loads of
-// the next step in flight during the current step's MFMAs).  Register budgets are held
-// to two waves per SIMD so that two blocks share a CU.
+// (two XOR-swizzled LDS stages, one barrier per K step, the loads of the next
+// step in flight during the current step's MFMAs).
 // Block ids are remapped so that blocks sharing the large operand tile run on
 // the same XCD (one L2 per XCD).
 #include "common.h"
@@ -30,6 +32,7 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f16v __attribute__((ext_vector_type(16)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 
@@ -245,8 +248,24 @@ struct BfCfg {
 
 typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
 
-__device__ inline bf8 lds_frag(const bf16_t* p) {
-  return __builtin_bit_cast(bf8, *reinterpret_cast<const u4*>(p));
+// 16-bit operand element types of the MFMA kernels: bit patterns in LDS,
+// fragments of eight for v_mfma_f32_32x32x16_{bf16,f16}
+struct OpBf16 {
+  typedef bf8 frag;
+  __device__ static f16v mfma(frag a, frag b, f16v c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+struct OpF16 {
+  typedef h8 frag;
+  __device__ static f16v mfma(frag a, frag b, f16v c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+template <typename OP>
+__device__ inline typename OP::frag lds_frag(const bf16_t* p) {
+  return __builtin_bit_cast(typename OP::frag, *reinterpret_cast<const u4*>(p));
 }
 // two floats -> packed bf16 pair, round to nearest even (v_cvt_pk_bf16_f32)
 __device__ inline unsigned pack_bf16(float a, float b) {
@@ -255,6 +274,12 @@ __device__ inline unsigned pack_bf16(float a, float b) {
 }
 __device__ inline float lo_bf16(unsigned u) { return __builtin_bit_cast(float, u << 16); }
 __device__ inline float hi_bf16(unsigned u) { return __builtin_bit_cast(float, u & 0xffff0000u); }
+__device__ inline float lo_f16(unsigned u) {
+  return (float)__builtin_bit_cast(_Float16, (unsigned short)(u & 0xffffu));
+}
+__device__ inline float hi_f16(unsigned u) {
+  return (float)__builtin_bit_cast(_Float16, (unsigned short)(u >> 16));
+}
 
 // LDS layout of a 32-wide K slab: rows of 64 bytes (four 16-byte chunks),
 // chunk c of row r stored at position c ^ ((r >> 2) & 3).  Both the 16-byte
@@ -386,27 +411,26 @@ __device__ inline void bf_lstore(const LA& la, BfSmem<BN>& sm, int buf,
 
 // ZERO: the first 16-wide K slice starts the accumulators from zero (the MFMA
 // reads an inline 0 for C) instead of from acc.
-template <int BN, bool ZERO = false>
+template <int BN, typename OP = OpBf16, bool ZERO = false>
 __device__ inline void bf_compute(BfSmem<BN>& sm, int buf, f16v (&acc)[4][BfCfg<BN>::WN]) {
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wm = w >> 1, wn = w & 1;
 #pragma unroll
   for (int ks = 0; ks < 2; ++ks) {
     const int ch = 2 * ks + (l >> 5);
-    bf8 a[4];
+    typename OP::frag a[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int row = wm * 128 + 32 * i + (l & 31);
-      a[i] = lds_frag(&sm.As[buf][row][swz(row, ch)]);
+      a[i] = lds_frag<OP>(&sm.As[buf][row][swz(row, ch)]);
     }
 #pragma unroll
     for (int j = 0; j < BfCfg<BN>::WN; ++j) {
       const int row = wn * (BN / 2) + 32 * j + (l & 31);
-      const bf8 b = lds_frag(&sm.Bs[buf][row][swz(row, ch)]);
+      const typename OP::frag b = lds_frag<OP>(&sm.Bs[buf][row][swz(row, ch)]);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-            a[i], b, (ZERO && ks == 0) ? f16v{} : acc[i][j], 0, 0, 0);
+        acc[i][j] = OP::mfma(a[i], b, (ZERO && ks == 0) ? f16v{} : acc[i][j]);
     }
   }
 }
@@ -437,7 +461,7 @@ __device__ inline int wswz(int row, int chunk) {
 // Issue the copies of the weights of rows [n0, n0 + BN), v in [0, NVW): each
 // wave moves 1 KB segments, lane l's 16 bytes landing at segment + 16 l.
 template <int BN, int NVW>
-__device__ inline void g1_weights_dma(G1Smem<BN, NVW>& sm, const bf16_t* __restrict__ w16,
+__device__ inline void g1_weights_dma(G1Smem<BN, NVW>& sm, const f16_t* __restrict__ w16,
                                       int nvp, int n0) {
   constexpr int CPR = NVW / 8;               // 16-byte chunks per row
   constexpr int RPS = 64 / CPR;              // rows per 1 KB segment
@@ -447,7 +471,7 @@ __device__ inline void g1_weights_dma(G1Smem<BN, NVW>& sm, const bf16_t* __restr
   // chunk (l % CPR) ^ (row % CPR) does not depend on q
   const int rl0 = w * RPS + l / CPR;
   const int c = (l % CPR) ^ (rl0 & (CPR - 1));
-  const bf16_t* src = w16 + (long)(n0 + rl0) * nvp + 8 * c;
+  const f16_t* src = w16 + (long)(n0 + rl0) * nvp + 8 * c;
   bf16_t* dst = &sm.wt[0][0] + w * 512;
   for (int q = 0; q < SEGS / 4; ++q) {
     __builtin_amdgcn_global_load_lds(src, dst, 16, 0, 0);
@@ -457,12 +481,15 @@ __device__ inline void g1_weights_dma(G1Smem<BN, NVW>& sm, const bf16_t* __restr
 }
 
 template <int BN, int SEG, int NVW>
-__device__ inline void gemm1_bf16_body(const GemmDims& d, int M, int nb,
-                                       const bf16_t* __restrict__ psi_c_rc,
-                                       const float* __restrict__ psi_v_rv,
-                                       const bf16_t* __restrict__ psi_v_rv16,
-                                       const bf16_t* __restrict__ u,
-                                       float* __restrict__ rho_part) {
+__device__ inline void gemm1_f16_body(const GemmDims& d, int M, int nb,
+                                      const f16_t* __restrict__ psi_c_rc16,
+                                      const float* __restrict__ psi_v_rv,
+                                      const f16_t* __restrict__ psi_v_rv16,
+                                      const f16_t* __restrict__ u16,
+                                      float* __restrict__ rho_part) {
+  // FP16 bit patterns travel through the same 16-bit staging as BF16
+  const bf16_t* psi_c_rc = reinterpret_cast<const bf16_t*>(psi_c_rc16);
+  const bf16_t* u = reinterpret_cast<const bf16_t*>(u16);
   constexpr int WN = BfCfg<BN>::WN;
   __shared__ G1Smem<BN, NVW> sm;
   const int mt = (M + HM - 1) / HM, nt = d.nrp / BN;
@@ -485,7 +512,7 @@ __device__ inline void gemm1_bf16_body(const GemmDims& d, int M, int nb,
     if constexpr (NVW > 0) g1_weights_dma<BN, NVW>(sm, psi_v_rv16, d.nvp, n0);
     // K step 0 (nsteps >= 2: N_c is padded to a multiple of 64)
     bf_gload(la, psi_c_rc, d.ncp, m0, n0, HK, x);
-    bf_compute<BN, true>(sm.st, 0, acc);
+    bf_compute<BN, OpF16, true>(sm.st, 0, acc);
     bf_lstore(la, sm.st, 1, x);
     __syncthreads();
     for (int i = 1; i < nsteps; ++i) {
@@ -495,7 +522,7 @@ __device__ inline void gemm1_bf16_body(const GemmDims& d, int M, int nb,
         bf_gload(la, psi_c_rc, d.ncp, m0, n0, (i + 1) * HK, x);
       else if (ti + 1 < nt1)
         bf_gload(la, psi_c_rc, d.ncp, m0, n0 + BN, 0, x);
-      bf_compute(sm.st, cur, acc);
+      bf_compute<BN, OpF16>(sm.st, cur, acc);
       if (more) bf_lstore(la, sm.st, cur ^ 1, x);
       __syncthreads();
     }
@@ -534,10 +561,10 @@ __device__ inline void gemm1_bf16_body(const GemmDims& d, int M, int nb,
                 const int ch = (vbase + 32 * i + 8 * g) >> 3;
                 const uint2 wv =
                     *reinterpret_cast<const uint2*>(&sm.wt[rl][wswz<NVW>(rl, ch) + 4 * (l >> 5)]);
-                s += lo_bf16(wv.x) * acc[sg + i][j][4 * g + 0];
-                s += hi_bf16(wv.x) * acc[sg + i][j][4 * g + 1];
-                s += lo_bf16(wv.y) * acc[sg + i][j][4 * g + 2];
-                s += hi_bf16(wv.y) * acc[sg + i][j][4 * g + 3];
+                s += lo_f16(wv.x) * acc[sg + i][j][4 * g + 0];
+                s += hi_f16(wv.x) * acc[sg + i][j][4 * g + 1];
+                s += lo_f16(wv.y) * acc[sg + i][j][4 * g + 2];
+                s += hi_f16(wv.y) * acc[sg + i][j][4 * g + 3];
               }
             }
           } else {
@@ -562,10 +589,10 @@ __device__ inline void gemm1_bf16_body(const GemmDims& d, int M, int nb,
 
 template <int SEG, int NVW>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
-gemm1_bf16_n128_kernel(GemmDims d, int M, int nb, const bf16_t* __restrict__ psi_c_rc,
-                       const float* __restrict__ psi_v_rv, const bf16_t* __restrict__ psi_v_rv16,
-                       const bf16_t* __restrict__ u, float* __restrict__ rho_part) {
-  gemm1_bf16_body<128, SEG, NVW>(d, M, nb, psi_c_rc, psi_v_rv, psi_v_rv16, u, rho_part);
+gemm1_f16_n128_kernel(GemmDims d, int M, int nb, const f16_t* __restrict__ psi_c_rc,
+                      const float* __restrict__ psi_v_rv, const f16_t* __restrict__ psi_v_rv16,
+                      const f16_t* __restrict__ u, float* __restrict__ rho_part) {
+  gemm1_f16_body<128, SEG, NVW>(d, M, nb, psi_c_rc, psi_v_rv, psi_v_rv16, u, rho_part);
 }
 
 // Second GEMM over one split of the grid sum: global loads two K steps ahead,
@@ -668,16 +695,16 @@ void gemm2_f64m(const GemmDims& d, int nb, int splitk, const double* psi_v_t,
   GWL_HIP(hipGetLastError());
 }
 
-int gemm1_bf16_vtiles(const GemmDims& d) { return d.nvp >= 128 ? d.nvp / 128 : 1; }
+int gemm1_f16_vtiles(const GemmDims& d) { return d.nvp >= 128 ? d.nvp / 128 : 1; }
 
-void gemm1_bf16(const GemmDims& d, int nb, const bf16_t* psi_c_rc, const float* psi_v_rv,
-                const bf16_t* psi_v_rv16, const bf16_t* u, float* rho_part, hipStream_t st) {
+void gemm1_f16(const GemmDims& d, int nb, const f16_t* psi_c_rc, const float* psi_v_rv,
+               const f16_t* psi_v_rv16, const f16_t* u, float* rho_part, hipStream_t st) {
   if (nb <= 0) return;
   const int M = nb * d.nvp;
   const int blocks = gemm1_grid(ceil_div(M, HM), ceil_div(d.nrp / 128, G1_TILES));
 #define GWL_G1(SEGV, NVWV)                                                                   \
-  gemm1_bf16_n128_kernel<SEGV, NVWV><<<blocks, 256, 0, st>>>(d, M, nb, psi_c_rc, psi_v_rv, \
-                                                             psi_v_rv16, u, rho_part)
+  gemm1_f16_n128_kernel<SEGV, NVWV><<<blocks, 256, 0, st>>>(d, M, nb, psi_c_rc, psi_v_rv, \
+                                                            psi_v_rv16, u, rho_part)
   if (d.nvp == 64) GWL_G1(2, 64);
   else if (d.nvp == 128) GWL_G1(4, 128);
   else GWL_G1(4, 0);

@@ -1,5 +1,6 @@
-// Factored pair-space product, plain LDS-tiled FMA version (FP64, and BF16
-// operands with FP32 accumulation).  The MFMA kernels are checked against it.
+// Factored pair-space product, plain LDS-tiled FMA version (FP64, and the
+// mixed path's FP16 / BF16 operands with FP32 accumulation).  The MFMA kernels
+// are checked against it.
 //
 // First GEMM with fused row-dot (the density of a pair vector u = Delta^1/2 x):
 //   rho_b(r) = sum_v phi_v(r) sum_c phi_c(r) u_b[v, c]
@@ -18,6 +19,7 @@ constexpr int TM = 64, TN = 64, TK = 16, LDT = 64 + 1;
 
 __device__ inline double ldx(const double* p, long i) { return p[i]; }
 __device__ inline float ldx(const bf16_t* p, long i) { return bf16_to_f32(p[i]); }
+__device__ inline float ldx(const f16_t* p, long i) { return f16_to_f32(p[i]); }
 __device__ inline float ldx(const float* p, long i) { return p[i]; }
 
 // A = accumulation type (double or float); TO = operand storage; TW = weights.
@@ -130,13 +132,13 @@ void gemm1_f64(const GemmDims& d, int nb, const double* psi_c_rc, const double* 
   GWL_HIP(hipGetLastError());
 }
 
-int gemm1_bf16s_vtiles(const GemmDims& d) { return d.nvp / TN; }
+int gemm1_f16s_vtiles(const GemmDims& d) { return d.nvp / TN; }
 
-void gemm1_bf16s(const GemmDims& d, int nb, const bf16_t* psi_c_rc, const float* psi_v_rv,
-                 const bf16_t* u, float* rho_part, hipStream_t st) {
+void gemm1_f16s(const GemmDims& d, int nb, const f16_t* psi_c_rc, const float* psi_v_rv,
+                const f16_t* u, float* rho_part, hipStream_t st) {
   if (nb <= 0) return;
   dim3 grid(d.nrp / TM, d.nvp / TN, nb);
-  gemm1_simple_kernel<float, bf16_t, float><<<grid, 256, 0, st>>>(d, psi_c_rc, psi_v_rv, u,
+  gemm1_simple_kernel<float, f16_t, float><<<grid, 256, 0, st>>>(d, psi_c_rc, psi_v_rv, u,
                                                                   rho_part, nb);
   GWL_HIP(hipGetLastError());
 }

@@ -71,6 +71,28 @@ void check_ctx(gwl_ctx* c) { GWL_CHECK(c != nullptr, GWL_EINVAL, "null context")
 
 }  // namespace
 
+namespace {
+
+// Largest 2-norm among n_vec device vectors of length N_vc (sets the FP16
+// operand scale for caller-given vectors).
+double max_row_norm(gwl_ctx* ctx, const double* x, int n_vec) {
+  DevBuf<double> nrm;
+  nrm.ensure(n_vec);
+  row_norm2(x, ctx->nvc, n_vec, nrm.p, ctx->stream);
+  std::vector<double> h(n_vec);
+  GWL_HIP(hipMemcpyAsync(h.data(), nrm.p, n_vec * sizeof(double), hipMemcpyDeviceToHost,
+                         ctx->stream));
+  GWL_HIP(hipStreamSynchronize(ctx->stream));
+  double m = 0.0;
+  for (double v : h) {
+    GWL_CHECK(std::isfinite(v), GWL_EINVAL, "non-finite input vector");
+    m = std::max(m, v);
+  }
+  return m;
+}
+
+}  // namespace
+
 extern "C" {
 
 void gwl_default_options(gwl_options* o) {
@@ -160,17 +182,22 @@ gwl_status gwl_setup(const void* orbitals, int orb_dtype, int orb_on_device, int
     // energies, Delta
     c.eps_ha.resize(n_orb);
     for (int i = 0; i < n_orb; ++i) c.eps_ha[i] = energies_ev[i] / kHartreeEv;
-    std::vector<double> d2(c.nvc), sd(c.nvc);
+    std::vector<double> d1(c.nvc), d2(c.nvc), sd(c.nvc);
     double dmin = 1e300;
     for (int v = 0; v < c.nv; ++v)
       for (int cc = 0; cc < c.nc; ++cc) {
         const double d = c.eps_ha[c.nv + cc] - c.eps_ha[v];
+        d1[(size_t)v * c.nc + cc] = d;
         d2[(size_t)v * c.nc + cc] = d * d;
         sd[(size_t)v * c.nc + cc] = std::sqrt(d);
         dmin = std::min(dmin, d);
       }
+    c.sd_max = 0.0;
+    for (double v : sd) c.sd_max = std::max(c.sd_max, v);
+    c.delta1.ensure(c.nvc);
     c.delta2.ensure(c.nvc);
     c.sdelta.ensure(c.nvc);
+    GWL_HIP(hipMemcpy(c.delta1.p, d1.data(), c.nvc * 8, hipMemcpyHostToDevice));
     GWL_HIP(hipMemcpy(c.delta2.p, d2.data(), c.nvc * 8, hipMemcpyHostToDevice));
     GWL_HIP(hipMemcpy(c.sdelta.p, sd.data(), c.nvc * 8, hipMemcpyHostToDevice));
 
@@ -215,15 +242,26 @@ gwl_status gwl_setup(const void* orbitals, int orb_dtype, int orb_on_device, int
       c.psi_v_rv64.ensure(vrv.size());
       GWL_HIP(hipMemcpy(c.psi_c_rc64.p, crc.data(), crc.size() * 8, hipMemcpyHostToDevice));
       GWL_HIP(hipMemcpy(c.psi_v_rv64.p, vrv.data(), vrv.size() * 8, hipMemcpyHostToDevice));
-      // mixed-precision copies
-      std::vector<bf16_t> t16((size_t)(nvp + alloc_rows_c(ncp)) * nrp, 0), c16(crc.size());
+      // mixed-precision copies: BF16 for the second GEMM; FP16 for the first
+      // GEMM's orbital operand and row-dot weights, scaled by a power of two
+      // that puts the largest orbital value near 2^11
+      double omax = 0.0;
+      for (double v : host) omax = std::max(omax, std::fabs(v));
+      {
+        int e = omax > 0.0 ? (int)std::floor(std::log2(2048.0 / omax)) : 0;
+        e = std::max(-60, std::min(60, e));
+        c.orb16_scale = std::ldexp(1.0, e);
+      }
+      const double os = c.orb16_scale;
+      std::vector<bf16_t> t16((size_t)(nvp + alloc_rows_c(ncp)) * nrp, 0);
+      std::vector<f16_t> c16(crc.size());
       for (size_t i = 0; i < host.size(); ++i) t16[i] = f32_to_bf16((float)host[i]);
-      for (size_t i = 0; i < crc.size(); ++i) c16[i] = f32_to_bf16((float)crc[i]);
+      for (size_t i = 0; i < crc.size(); ++i) c16[i] = f32_to_f16((float)(os * crc[i]));
       std::vector<float> v32(vrv.size());
-      std::vector<bf16_t> v16(vrv.size());
+      std::vector<f16_t> v16(vrv.size());
       for (size_t i = 0; i < vrv.size(); ++i) {
-        v32[i] = (float)vrv[i];
-        v16[i] = f32_to_bf16(v32[i]);
+        v32[i] = (float)(os * vrv[i]);
+        v16[i] = f32_to_f16(v32[i]);
       }
       c.psi_t16.ensure(t16.size());
       c.psi_c_rc16.ensure(c16.size());
@@ -310,6 +348,10 @@ gwl_status gwl_set_option(gwl_ctx* ctx, int key, double value) {
         GWL_CHECK(value == 0 || value == 1, GWL_EINVAL, "kernels must be 0 or 1");
         ctx->fp64_kernel = (int)value;
         break;
+      case GWL_KEY_TDA:
+        GWL_CHECK(value == 0 || value == 1, GWL_EINVAL, "tda must be 0 or 1");
+        ctx->tda = (int)value;
+        break;
       case GWL_KEY_BF16_TILE:
         GWL_CHECK(value == 128 || value == 256, GWL_EINVAL, "BF16 tile must be 128 or 256");
         if (ctx->bf16_tile != (int)value) {
@@ -350,6 +392,7 @@ gwl_status gwl_query(gwl_ctx* ctx, int key, double* out) {
       case GWL_KEY_GEMM_SPLITK: *out = ctx->splitk; break;
       case GWL_KEY_KERNELS: *out = ctx->fp64_kernel; break;
       case GWL_KEY_BF16_TILE: *out = ctx->bf16_tile; break;
+      case GWL_KEY_TDA: *out = ctx->tda; break;
       case GWL_KEY_PROFILE: *out = ctx->profile; break;
       case GWL_KEY_GRAPHS: *out = ctx->use_graphs; break;
       case GWL_KEY_TUNED_BLOCK: *out = ctx->tuned[ctx->precision].B; break;
@@ -406,6 +449,7 @@ gwl_status gwl_apply_c(gwl_ctx* ctx, const double* x, double* y, int n_vec, int 
     ctx->prof_reset();
     const int chunk = std::min(n_vec, 64);
     ctx->ensure_work(chunk, 1, false);
+    if (precision != GWL_FP64) ctx->set_u_bound(max_row_norm(ctx, x, n_vec));
     for (int i0 = 0; i0 < n_vec; i0 += chunk) {
       const int nb = std::min(chunk, n_vec - i0);
       ctx->apply_c_batch(nb, x + (size_t)i0 * ctx->nvc, y + (size_t)i0 * ctx->nvc, precision);
@@ -426,6 +470,7 @@ gwl_status gwl_apply_d(gwl_ctx* ctx, const double* x, double* y, int n_vec, int 
     ctx->prof_reset();
     const int chunk = std::min(n_vec, 64);
     ctx->ensure_work(chunk, 1, false);
+    if (precision != GWL_FP64) ctx->set_u_bound(max_row_norm(ctx, x, n_vec));
     for (int i0 = 0; i0 < n_vec; i0 += chunk) {
       const int nb = std::min(chunk, n_vec - i0);
       ctx->last_c_matvecs += (long)nb * ctx->poly_degree;
@@ -523,7 +568,7 @@ void sigma_device(gwl_ctx* ctx, int P, const int* n_host, int ld, const double* 
   GWL_HIP(hipMemcpy(ctx->eta_n.p, et.data(), P * 8, hipMemcpyHostToDevice));
   GWL_HIP(hipMemcpy(ctx->omega.p, om.data(), n_omega * 8, hipMemcpyHostToDevice));
   cfrac_sigma(P, ctx->coef_a.p, ctx->coef_b.p, ctx->out_len.p, ctx->norm2.p, ld, ctx->e_n.p,
-              ctx->eta_n.p, ctx->omega.p, n_omega, eta_ev / kHartreeEv, ctx->sig.p,
+              ctx->eta_n.p, ctx->omega.p, n_omega, eta_ev / kHartreeEv, ctx->tda, ctx->sig.p,
               ctx->stream);
 }
 

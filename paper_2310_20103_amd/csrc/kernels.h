@@ -67,9 +67,9 @@ void gemm2_f64(const GemmDims& d, int nb, int splitk, const double* psi_v_t,
                const double* psi_c_t, const double* vpot, double* ypart, hipStream_t st);
 
 // BF16 operands, FP32 accumulation, plain FMA tiles (checks the MFMA kernels).
-int gemm1_bf16s_vtiles(const GemmDims& d);
-void gemm1_bf16s(const GemmDims& d, int nb, const bf16_t* psi_c_rc, const float* psi_v_rv,
-                 const bf16_t* u, float* rho_part, hipStream_t st);
+int gemm1_f16s_vtiles(const GemmDims& d);
+void gemm1_f16s(const GemmDims& d, int nb, const f16_t* psi_c_rc, const float* psi_v_rv,
+                const f16_t* u, float* rho_part, hipStream_t st);
 void gemm2_bf16s(const GemmDims& d, int nb, int splitk, const bf16_t* psi_v_t,
                  const bf16_t* psi_c_t, const float* vpot, float* ypart, hipStream_t st);
 
@@ -81,11 +81,12 @@ void gemm2_f64m(const GemmDims& d, int nb, int splitk, const double* psi_v_t,
                 const double* psi_c_t, const double* vpot, double* ypart, hipStream_t st);
 
 // BF16 operands, FP32 accumulation, on MFMA.
-int gemm1_bf16_vtiles(const GemmDims& d);
-// psi_v_rv: FP32 [N_rp][N_vp] epilogue weights; psi_v_rv16: the same in BF16
-// (used when N_vp is 64 or 128)
-void gemm1_bf16(const GemmDims& d, int nb, const bf16_t* psi_c_rc, const float* psi_v_rv,
-                const bf16_t* psi_v_rv16, const bf16_t* u, float* rho_part, hipStream_t st);
+int gemm1_f16_vtiles(const GemmDims& d);
+// First GEMM of the mixed path: FP16 operands (u scaled by a power of two),
+// FP32 accumulation.  psi_v_rv: FP32 [N_rp][N_vp] epilogue weights;
+// psi_v_rv16: the same in FP16 (used when N_vp is 64 or 128)
+void gemm1_f16(const GemmDims& d, int nb, const f16_t* psi_c_rc, const float* psi_v_rv,
+               const f16_t* psi_v_rv16, const f16_t* u, float* rho_part, hipStream_t st);
 // bn = block tile width of the second GEMM (128 or 256)
 int gemm2_bf16_blocks(const GemmDims& d, int nb, int bn);  // blocks per split of the K range
 int gemm2_f64m_blocks(const GemmDims& d, int nb);
@@ -99,13 +100,26 @@ struct PairGeom {
   const double* delta2;  // Delta^2   [nvc]
   const double* sdelta;  // Delta^1/2 [nvc]
   double dv;
+  const double* delta = nullptr;  // Delta [nvc] (Tamm-Dancoff product)
+  // FP16 operand scaling: cast_u writes uscale * value; combine multiplies the
+  // second GEMM's sum by yscale = 1 / uscale (powers of two, exact)
+  double uscale = 1.0, yscale = 1.0;
+  // Tamm-Dancoff: the operand is x itself (no Delta^1/2), combine mode 3 gives
+  // A x = Delta x + K x, coupling vectors are (nm|vc)
+  int tda = 0;
+  // cast_u / combine only: GEMM operand row b belongs to pair-vector slot
+  // rows[b] (device, nb entries); nullptr = row b is slot b
+  const int* rows = nullptr;
 };
 
 // Elementwise orbital products rho_i = phi_{n_i} phi_{m_i} (FP64), [cnt][NRp].
 void pair_product(const double* psi_t, long ld, int nr, const int* m_idx, const int* n_idx,
                   int cnt, double* rho, hipStream_t st);
 
-// u[b] = cast(Delta^1/2 * x[b]) into the padded operand layout.
+// out[i] = ||x_i||_2 for nrows rows of length n (FP64, fixed reduction order).
+void row_norm2(const double* x, long n, int nrows, double* out, hipStream_t st);
+
+// u[b] = cast(Delta^1/2 * x[slot(b)]) into the padded operand layout.
 template <typename U>
 void cast_u(const PairGeom& g, int nb, const double* x, long ldx, U* u, hipStream_t st);
 
@@ -113,6 +127,8 @@ void cast_u(const PairGeom& g, int nb, const double* x, long ldx, U* u, hipStrea
 // cx = Delta^2 x + 2 dV Delta^1/2 y.  mode 0: out = cx.  mode 1 (first
 // Chebyshev step): tn = (2 cx - (hi+lo) x)/(hi-lo); acc = c0 x + c1 tn.
 // mode 2: tn = 2 (2 cx - (hi+lo) x)/(hi-lo) - tp; acc += cj tn.
+// mode 3 (Tamm-Dancoff, g.tda): out = Delta x + dV y.
+// Row b of ypart / u pairs with slot g.rows[b] of x, tp, out, acc, kx_out.
 // If u != null also writes u = cast(Delta^1/2 tn) (mode 1, 2) for the next product;
 // if kx_out != null also writes the coupling part K Delta^1/2 x = dV y.
 template <typename Y, typename U>
@@ -160,7 +176,7 @@ void lz_beta(const SlotState& s, int nb, double* q, double* qprev, double* w, do
 // sig[p][w] (complex, eV) for pairs p, Eq. 12 with Eq. 14.
 void cfrac_sigma(int npairs, const double* coef_a, const double* coef_b, const int* lens,
                  const double* norm2, int ld, const double* e_n, const double* eta_n,
-                 const double* omega_ha, int nomega, double delta_ha, double* sig,
+                 const double* omega_ha, int nomega, double delta_ha, int tda, double* sig,
                  hipStream_t st);
 // out[q][w] = sum_{p in [q*per, (q+1)*per)} sig[p][w], fixed order.
 void sum_groups(const double* sig, int ngroups, int per, int nomega, double* out,

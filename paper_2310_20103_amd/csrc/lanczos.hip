@@ -39,7 +39,7 @@ __device__ inline U to_op(double v);
 template <>
 __device__ inline double to_op<double>(double v) { return v; }
 template <>
-__device__ inline bf16_t to_op<bf16_t>(double v) { return f32_to_bf16((float)v); }
+__device__ inline f16_t to_op<f16_t>(double v) { return f32_to_f16((float)v); }
 
 __global__ void pair_product_kernel(const double* __restrict__ psi_t, long ld, int nr,
                                     const int* __restrict__ m_idx, const int* __restrict__ n_idx,
@@ -55,11 +55,12 @@ __global__ void pair_product_kernel(const double* __restrict__ psi_t, long ld, i
 template <typename U>
 __global__ void cast_u_kernel(PairGeom g, const double* __restrict__ x, long ldx, U* __restrict__ u) {
   const int b = blockIdx.y;
-  const double* xb = x + (long)b * ldx;
+  const int slot = g.rows ? g.rows[b] : b;
+  const double* xb = x + (long)slot * ldx;
   U* ub = u + (long)b * g.nvp * g.ncp;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < g.nvc; i += (long)gridDim.x * blockDim.x) {
     const int v = (int)(i / g.nc), c = (int)(i - (long)v * g.nc);
-    ub[(long)v * g.ncp + c] = to_op<U>(g.sdelta[i] * xb[i]);
+    ub[(long)v * g.ncp + c] = to_op<U>(g.uscale * (g.tda ? xb[i] : g.sdelta[i] * xb[i]));
   }
 }
 
@@ -70,19 +71,25 @@ __global__ void combine_kernel(PairGeom g, int nb, int splitk, const Y* __restri
                                double lo, double hi, double c0, double cj, U* __restrict__ u,
                                double* __restrict__ kx_out) {
   const int b = blockIdx.y;
+  const int slot = g.rows ? g.rows[b] : b;
   const long stride_s = (long)nb * g.nvp * g.ncp;
   const Y* yb = ypart + (long)b * g.nvp * g.ncp;
-  const double* xb = x + (long)b * g.nvc;
+  const double* xb = x + (long)slot * g.nvc;
   const double inv = 1.0 / (hi - lo);
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < g.nvc; i += (long)gridDim.x * blockDim.x) {
     const int v = (int)(i / g.nc), c = (int)(i - (long)v * g.nc);
     const long off = (long)v * g.ncp + c;
     double y = 0.0;
     for (int s = 0; s < splitk; ++s) y += (double)yb[s * stride_s + off];
+    y *= g.yscale;
     const double xi = xb[i];
+    const long o = (long)slot * g.nvc + i;
+    if (mode == 3) {  // A x = Delta x + K x
+      out[o] = g.delta[i] * xi + g.dv * y;
+      continue;
+    }
     const double sd = g.sdelta[i];
     const double cx = g.delta2[i] * xi + 2.0 * g.dv * sd * y;
-    const long o = (long)b * g.nvc + i;
     if (kx_out) kx_out[o] = g.dv * y;  // K Delta^1/2 x
     if (mode == 0) {
       out[o] = cx;
@@ -98,7 +105,7 @@ __global__ void combine_kernel(PairGeom g, int nb, int splitk, const Y* __restri
       acc[o] += cj * tn;
     }
     out[o] = tn;
-    if (u) u[(long)b * g.nvp * g.ncp + off] = to_op<U>(sd * tn);
+    if (u) u[(long)b * g.nvp * g.ncp + off] = to_op<U>(g.uscale * sd * tn);
   }
 }
 
@@ -113,7 +120,8 @@ __global__ void coupling_finish_kernel(PairGeom g, int cnt, int splitk, const Y*
     const long off = (long)v * g.ncp + c;
     double y = 0.0;
     for (int s = 0; s < splitk; ++s) y += (double)yb[s * stride_s + off];
-    p[(long)i * ldp + e] = g.dv * g.sdelta[e] * y;
+    // P_nm = (nm|vc) Delta^1/2, or (nm|vc) itself for Tamm-Dancoff
+    p[(long)i * ldp + e] = g.tda ? g.dv * y : g.dv * g.sdelta[e] * y;
   }
 }
 
@@ -285,6 +293,26 @@ void pair_product(const double* psi_t, long ld, int nr, const int* m_idx, const 
   GWL_HIP(hipGetLastError());
 }
 
+__global__ void row_norm2_kernel(const double* __restrict__ x, long n, double* __restrict__ out) {
+  __shared__ double red[NT];
+  const double* xr = x + (long)blockIdx.x * n;
+  double acc = 0.0;
+  for (long i = threadIdx.x; i < n; i += blockDim.x) acc += xr[i] * xr[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = sqrt(red[0]);
+}
+
+void row_norm2(const double* x, long n, int nrows, double* out, hipStream_t st) {
+  if (nrows <= 0) return;
+  row_norm2_kernel<<<nrows, NT, 0, st>>>(x, n, out);
+  GWL_HIP(hipGetLastError());
+}
+
 template <typename U>
 void cast_u(const PairGeom& g, int nb, const double* x, long ldx, U* u, hipStream_t st) {
   if (nb <= 0) return;
@@ -293,7 +321,7 @@ void cast_u(const PairGeom& g, int nb, const double* x, long ldx, U* u, hipStrea
   GWL_HIP(hipGetLastError());
 }
 template void cast_u<double>(const PairGeom&, int, const double*, long, double*, hipStream_t);
-template void cast_u<bf16_t>(const PairGeom&, int, const double*, long, bf16_t*, hipStream_t);
+template void cast_u<f16_t>(const PairGeom&, int, const double*, long, f16_t*, hipStream_t);
 
 template <typename Y, typename U>
 void combine(const PairGeom& g, int nb, int splitk, const Y* ypart, const double* x,
@@ -308,9 +336,9 @@ void combine(const PairGeom& g, int nb, int splitk, const Y* ypart, const double
 template void combine<double, double>(const PairGeom&, int, int, const double*, const double*,
                                       const double*, double*, double*, int, double, double,
                                       double, double, double*, hipStream_t, double*);
-template void combine<float, bf16_t>(const PairGeom&, int, int, const float*, const double*,
-                                     const double*, double*, double*, int, double, double,
-                                     double, double, bf16_t*, hipStream_t, double*);
+template void combine<float, f16_t>(const PairGeom&, int, int, const float*, const double*,
+                                    const double*, double*, double*, int, double, double,
+                                    double, double, f16_t*, hipStream_t, double*);
 
 template <typename Y>
 void coupling_finish(const PairGeom& g, int cnt, int splitk, const Y* ypart, double* p_out,

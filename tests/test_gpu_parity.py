@@ -189,6 +189,30 @@ def test_uneven_lengths_with_refill(small):
         ctx.close()
 
 
+def test_uneven_lengths_mixed_compacted(small):
+    """Mixed precision with slots falling idle: the product then runs over
+    the busy slots only (rows gathered in the cast, scattered in the combine);
+    longest runs are scheduled first."""
+    _say("uneven lengths mixed, block 3")
+    ctx = make_ctx(small.sys, precision="mixed", interval=(small.lo, small.hi), block=3)
+    try:
+        m = int(small.sys.qp_states[0])
+        ns = [4, 9, 30, 17, 2]
+        lens = [6, 40, 12, 25, 3]
+        a, b, n2, ol = ctx.lanczos_pairs([m] * len(ns), ns, lens)
+        for i, n in enumerate(ns):
+            ra, rb, rn2 = small.pr.lanczos_coeffs(m, lens[i], small.lo, small.hi,
+                                                  small.wl.poly_degree, n_list=[n])[0]
+            assert ol[i] == lens[i]
+            # BF16 operands perturb the operator by ~1e-6; later Lanczos
+            # coefficients amplify that, the first ones do not
+            assert relerr(a[i, :min(8, lens[i])], ra[:8]) <= 1e-5
+            assert relerr(a[i, :lens[i]], ra) <= 1e-3
+            assert np.all(a[i, lens[i]:] == 0)
+    finally:
+        ctx.close()
+
+
 def test_breakdown_short_fraction():
     """N_vc = 6 < L = 12: the recurrence must stop at an invariant subspace."""
     _say("breakdown tiny 2+3")
