@@ -201,6 +201,30 @@ gwl_status gwl_apply_c(gwl_ctx* ctx, const double* x, double* y, int n_vec,
 gwl_status gwl_apply_d(gwl_ctx* ctx, const double* x, double* y, int n_vec,
                        int precision);
 
+/* Exchange part of the self-energy, Sigma^ex_mm = -sum_v (vm|vm) (Eq. 6; the
+ * frequency-independent term of Eq. 5), in eV, for n_qp states: pair
+ * densities phi_v phi_m on the grid, the same FFT Poisson solve and kernel as
+ * the correlation part (FP64 throughout), and a fixed-order grid sum.
+ * qp_states: host [n_qp], 0-based orbital indices; sigma_x_out: host [n_qp].
+ * Independent of the precision and Tamm-Dancoff options. */
+gwl_status gwl_sigma_x(gwl_ctx* ctx, const int* qp_states, int n_qp, double* sigma_x_out);
+
+/* Quasiparticle energy from the graphical solution of the G0W0 equation
+ * E = eps + Sigma^ex + Re Sigma^corr(E) - v_xc on a frequency grid (the
+ * paper evaluates Eq. 14 for a series of frequencies for this purpose):
+ * the zeros of f(w) = eps + sigma_x + Re sigma_c(w) - vxc - w are located by
+ * sign changes between neighbouring grid points and linear interpolation; the
+ * root nearest eps is returned in *e_qp with the renormalisation factor
+ * *z = 1 / (1 - d Re Sigma^corr / dw) from the slope of that segment.
+ * omega_ev: host [n_omega], strictly increasing, n_omega >= 2; sigma_c: host
+ * [n_omega][2] (real, imaginary) eV, as returned by gwl_sigma_c; all energies
+ * in eV; v_xc comes from the mean-field calculation.  Host only (no context,
+ * no device work).  GWL_ENUMERIC (with NaN outputs) when f never changes sign
+ * on the grid. */
+gwl_status gwl_qp_solve(const double* omega_ev, int n_omega, const double* sigma_c,
+                        double eps_ev, double sigma_x_ev, double vxc_ev, double* e_qp,
+                        double* z);
+
 /* Coupling vectors P_nm = (nm|vc) Delta^1/2 for count (m, n) pairs.
  * m_idx, n_idx host [count]; p: device float64 [count][N_v*N_c]. */
 gwl_status gwl_coupling(gwl_ctx* ctx, const int* m_idx, const int* n_idx,

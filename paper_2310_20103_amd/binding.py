@@ -63,6 +63,8 @@ _SIGS = {
     "gwl_apply_c": (_I, [_P, _P, _P, _I, _I]),
     "gwl_apply_d": (_I, [_P, _P, _P, _I, _I]),
     "gwl_coupling": (_I, [_P, _P, _P, _I, _P]),
+    "gwl_sigma_x": (_I, [_P, _P, _I, _P]),
+    "gwl_qp_solve": (_I, [_P, _I, _P, _D, _D, _D, _P, _P]),
     "gwl_set_option": (_I, [_P, _I, _D]),
     "gwl_query": (_I, [_P, _I, ct.POINTER(_D)]),
     "gwl_last_error": (ct.c_char_p, []),
@@ -324,6 +326,14 @@ class Context:
                                  int(x.shape[0]), PRECISIONS[precision]))
         return out
 
+    def sigma_x(self, qp_states):
+        """Exchange self-energy Sigma^ex_mm (eV) for each state."""
+        q = _i32(qp_states)
+        out = np.zeros(len(q))
+        if len(q):
+            _check(lib().gwl_sigma_x(self._h, _ptr(q), len(q), _ptr(out)))
+        return out
+
     def coupling(self, m_idx, n_idx, device="cuda"):
         import torch
         m, n = _i32(m_idx), _i32(n_idx)
@@ -331,3 +341,16 @@ class Context:
         _sync_torch()
         _check(lib().gwl_coupling(self._h, _ptr(m), _ptr(n), len(m), _dev(out, torch.float64)))
         return out
+
+
+def qp_solve(omega_ev, sigma_c, eps_ev: float, sigma_x_ev: float, vxc_ev: float = 0.0):
+    """(E_qp, Z) from the graphical solution on the frequency grid (eV);
+    raises GwlError when the equation has no root on the grid."""
+    om = _f64(omega_ev)
+    sc = np.asarray(sigma_c, dtype=np.complex128).reshape(len(om))
+    s2 = np.ascontiguousarray(np.stack([sc.real, sc.imag], axis=-1))
+    e = np.zeros(1)
+    z = np.zeros(1)
+    _check(lib().gwl_qp_solve(_ptr(om), len(om), _ptr(s2), float(eps_ev), float(sigma_x_ev),
+                              float(vxc_ev), _ptr(e), _ptr(z)))
+    return float(e[0]), float(z[0])

@@ -239,7 +239,10 @@ gemm2_f64m_kernel(GemmDims d, int M, int splitk, int kchunk, const double* __res
 // BN = 128 (its per-tile row-dot epilogue needs a second wave per SIMD to
 // hide it); the second GEMM takes either, 256 by default.
 constexpr int HM = 256, HK = 32, HLD = HK;  // LDS row: 32 bf16 = 64 B, swizzled
-constexpr int G1_TILES = 4;                 // N tiles walked by one first-GEMM block
+// N tiles walked by one first-GEMM block.  One: co-resident blocks then start
+// at different times and their row-dot epilogues overlap the other block's
+// MFMAs (measured 5 % faster than walks of 2, 4 or 8 tiles).
+constexpr int G1_TILES = 1;
 template <int BN>
 struct BfCfg {
   static constexpr int WN = BN / 64;       // 32-col blocks per wave
@@ -553,6 +556,7 @@ __device__ inline void gemm1_f16_body(const GemmDims& d, int M, int nb,
           const int rl = wn * (BN / 2) + 32 * j + (l & 31);
           const int r = n0 + rl;
           float s = 0.f;
+          float s4[4] = {0.f, 0.f, 0.f, 0.f};
           if constexpr (NVW > 0) {
 #pragma unroll
             for (int i = 0; i < SEG; ++i) {
@@ -561,10 +565,10 @@ __device__ inline void gemm1_f16_body(const GemmDims& d, int M, int nb,
                 const int ch = (vbase + 32 * i + 8 * g) >> 3;
                 const uint2 wv =
                     *reinterpret_cast<const uint2*>(&sm.wt[rl][wswz<NVW>(rl, ch) + 4 * (l >> 5)]);
-                s += lo_f16(wv.x) * acc[sg + i][j][4 * g + 0];
-                s += hi_f16(wv.x) * acc[sg + i][j][4 * g + 1];
-                s += lo_f16(wv.y) * acc[sg + i][j][4 * g + 2];
-                s += hi_f16(wv.y) * acc[sg + i][j][4 * g + 3];
+                s4[0] += lo_f16(wv.x) * acc[sg + i][j][4 * g + 0];
+                s4[1] += hi_f16(wv.x) * acc[sg + i][j][4 * g + 1];
+                s4[2] += lo_f16(wv.y) * acc[sg + i][j][4 * g + 2];
+                s4[3] += hi_f16(wv.y) * acc[sg + i][j][4 * g + 3];
               }
             }
           } else {
@@ -579,6 +583,7 @@ __device__ inline void gemm1_f16_body(const GemmDims& d, int M, int nb,
               }
             }
           }
+          s += (s4[0] + s4[1]) + (s4[2] + s4[3]);  // four shorter FMA chains
           s += __shfl_xor(s, 32, 64);
           if (l < 32) rho_part[((long)vt * nb + b) * d.nrp + r] = s;
         }

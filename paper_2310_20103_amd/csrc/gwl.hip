@@ -18,6 +18,8 @@
 #include <string>
 #include <vector>
 
+#include <limits>
+
 #include "context.h"
 
 namespace gwl {
@@ -479,6 +481,87 @@ gwl_status gwl_apply_d(gwl_ctx* ctx, const double* x, double* y, int n_vec, int 
     }
     GWL_HIP(hipStreamSynchronize(ctx->stream));
     ctx->prof_flush();
+  });
+}
+
+gwl_status gwl_sigma_x(gwl_ctx* ctx, const int* qp_states, int n_qp, double* sigma_x_out) {
+  return guarded([&] {
+    check_ctx(ctx);
+    GWL_CHECK(n_qp >= 0, GWL_EINVAL, "n_qp < 0");
+    if (n_qp == 0) return;
+    GWL_CHECK(qp_states && sigma_x_out, GWL_EINVAL, "null pointer");
+    for (int i = 0; i < n_qp; ++i)
+      GWL_CHECK(qp_states[i] >= 0 && qp_states[i] < ctx->n_orb, GWL_EINVAL,
+                "qp state out of range");
+    gwl_ctx& c = *ctx;
+    const int nv = c.nv;
+    const int chunk = std::min(nv, 64);
+    c.ensure_work(chunk, 1, false);
+    DevBuf<double> e;
+    e.ensure((size_t)nv);
+    std::vector<int> mr(chunk), vr(chunk);
+    std::vector<double> he(nv);
+    double* rp = reinterpret_cast<double*>(c.rho.p);
+    for (int q = 0; q < n_qp; ++q) {
+      for (int v0 = 0; v0 < nv; v0 += chunk) {
+        const int cnt = std::min(chunk, nv - v0);
+        for (int i = 0; i < cnt; ++i) {
+          mr[i] = c.orb_row(qp_states[q]);
+          vr[i] = c.orb_row(v0 + i);
+        }
+        GWL_HIP(hipStreamSynchronize(c.stream));
+        GWL_HIP(hipMemcpy(c.s_m.p, mr.data(), cnt * sizeof(int), hipMemcpyHostToDevice));
+        GWL_HIP(hipMemcpy(c.s_n.p, vr.data(), cnt * sizeof(int), hipMemcpyHostToDevice));
+        pair_product(c.psi_t.p, c.gd.nrp, (int)c.nr, c.s_m.p, c.s_n.p, cnt, rp, c.stream);
+        poisson_launch<double>(c.pg64, rp, c.gd.nrp, 0, 1, c.vpot64.p, c.gd.nrp, cnt,
+                               reinterpret_cast<cplx<double>*>(c.fftx.p), c.stream);
+        pair_energy(rp, c.vpot64.p, c.gd.nrp, (int)c.nr, c.dv, cnt, e.p + v0, c.stream);
+      }
+      GWL_HIP(hipMemcpyAsync(he.data(), e.p, nv * sizeof(double), hipMemcpyDeviceToHost,
+                             c.stream));
+      GWL_HIP(hipStreamSynchronize(c.stream));
+      double sx = 0.0;
+      for (int v = 0; v < nv; ++v) sx -= he[v];
+      sigma_x_out[q] = sx * kHartreeEv;
+    }
+    GWL_CHECK(finite_all(sigma_x_out, n_qp), GWL_ENUMERIC, "non-finite exchange self-energy");
+  });
+}
+
+gwl_status gwl_qp_solve(const double* omega_ev, int n_omega, const double* sigma_c,
+                        double eps_ev, double sigma_x_ev, double vxc_ev, double* e_qp,
+                        double* z) {
+  return guarded([&] {
+    GWL_CHECK(omega_ev && sigma_c && e_qp && z, GWL_EINVAL, "null pointer");
+    GWL_CHECK(n_omega >= 2, GWL_EINVAL, "need at least two frequencies");
+    for (int i = 0; i + 1 < n_omega; ++i)
+      GWL_CHECK(omega_ev[i + 1] > omega_ev[i], GWL_EINVAL, "frequencies must increase");
+    *e_qp = std::numeric_limits<double>::quiet_NaN();
+    *z = std::numeric_limits<double>::quiet_NaN();
+    // f(w) = e + Sigma^x + Re Sigma^c(w) - v_xc - w; roots by sign change and
+    // linear interpolation, the one nearest e wins
+    auto f = [&](int i) { return eps_ev + sigma_x_ev + sigma_c[2 * i] - vxc_ev - omega_ev[i]; };
+    int best_seg = -1;
+    double best = 0.0;
+    for (int i = 0; i + 1 < n_omega; ++i) {
+      const double f0 = f(i), f1 = f(i + 1);
+      double root;
+      if (f0 == 0.0)
+        root = omega_ev[i];
+      else if ((f0 < 0.0) != (f1 < 0.0) && f1 != 0.0)
+        root = omega_ev[i] - f0 * (omega_ev[i + 1] - omega_ev[i]) / (f1 - f0);
+      else
+        continue;
+      if (best_seg < 0 || std::fabs(root - eps_ev) < std::fabs(best - eps_ev)) {
+        best = root;
+        best_seg = i;
+      }
+    }
+    GWL_CHECK(best_seg >= 0, GWL_ENUMERIC, "the quasiparticle equation has no root on the grid");
+    const double slope = (sigma_c[2 * (best_seg + 1)] - sigma_c[2 * best_seg]) /
+                         (omega_ev[best_seg + 1] - omega_ev[best_seg]);
+    *e_qp = best;
+    *z = 1.0 / (1.0 - slope);
   });
 }
 

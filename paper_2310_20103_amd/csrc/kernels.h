@@ -116,6 +116,10 @@ struct PairGeom {
 void pair_product(const double* psi_t, long ld, int nr, const int* m_idx, const int* n_idx,
                   int cnt, double* rho, hipStream_t st);
 
+// out[i] = dv sum_{r < nr} rho_i(r) V_i(r) for cnt fields (row stride ld).
+void pair_energy(const double* rho, const double* vpot, long ld, int nr, double dv, int cnt,
+                 double* out, hipStream_t st);
+
 // out[i] = ||x_i||_2 for nrows rows of length n (FP64, fixed reduction order).
 void row_norm2(const double* x, long n, int nrows, double* out, hipStream_t st);
 

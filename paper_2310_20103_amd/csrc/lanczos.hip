@@ -293,6 +293,30 @@ void pair_product(const double* psi_t, long ld, int nr, const int* m_idx, const 
   GWL_HIP(hipGetLastError());
 }
 
+// out[i] = dv sum_{r < nr} rho_i(r) V_i(r), fixed reduction order.
+__global__ void pair_energy_kernel(const double* __restrict__ rho, const double* __restrict__ vpot,
+                                   long ld, int nr, double dv, double* __restrict__ out) {
+  __shared__ double red[NT];
+  const double* a = rho + (long)blockIdx.x * ld;
+  const double* b = vpot + (long)blockIdx.x * ld;
+  double acc = 0.0;
+  for (long i = threadIdx.x; i < nr; i += blockDim.x) acc += a[i] * b[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = dv * red[0];
+}
+
+void pair_energy(const double* rho, const double* vpot, long ld, int nr, double dv, int cnt,
+                 double* out, hipStream_t st) {
+  if (cnt <= 0) return;
+  pair_energy_kernel<<<cnt, NT, 0, st>>>(rho, vpot, ld, nr, dv, out);
+  GWL_HIP(hipGetLastError());
+}
+
 __global__ void row_norm2_kernel(const double* __restrict__ x, long n, double* __restrict__ out) {
   __shared__ double red[NT];
   const double* xr = x + (long)blockIdx.x * n;
