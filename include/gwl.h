@@ -270,7 +270,7 @@ enum {
   GWL_KEY_BF16_TILE = 26,       /* set/query: block tile width of the second BF16 GEMM, 256
                                    (default: one wave per SIMD, accumulators in AGPRs) or
                                    128 (two waves per SIMD) */
-  GWL_KEY_TDA = 27              /* set/query: 0 (default) = the full method above; 1 =
+  GWL_KEY_TDA = 27,             /* set/query: 0 (default) = the full method above; 1 =
                                    Tamm-Dancoff approximation (B = 0 in the Casida matrix,
                                    the variant the paper's closing discussion names): the
                                    Lanczos operator is A = Delta + K (no square root, no
@@ -281,6 +281,20 @@ enum {
                                    gwl_sigma_from_coeffs and gwl_coupling; gwl_apply_c and
                                    gwl_apply_d keep their meaning; gwl_sigma_c_vjp returns
                                    GWL_EUNSUPPORTED while it is set. */
+  GWL_KEY_QUADRATURE = 28       /* set/query: 0 (default) = Lanczos on D = p_g(C) (Eqs. 12-14);
+                                   1 = Lanczos on C itself from P_nm, n_lanczos counting
+                                   C-products, and Sigma(w, n) evaluated by the Gauss
+                                   quadrature of the tridiagonal T (Ritz values theta_k,
+                                   weights ||P||^2 u_k(0)^2 from an implicit QL iteration):
+                                   sum_k w_k [theta_k^-1/2 - (theta_k^1/2 + eta_n z_n)^-1] / z_n,
+                                   i.e. Eq. 11 with the spectral measure of C probed directly,
+                                   without the polynomial fit of the square root.  Applies to
+                                   gwl_sigma_c, gwl_sigma_c_range, gwl_lanczos_pairs and
+                                   gwl_sigma_from_coeffs; ignored while GWL_KEY_TDA is set;
+                                   FP64 only (the Ritz-value quadrature amplifies the mixed
+                                   product's rounding: 5e-3 eV at L = 28 on a smooth test
+                                   case), so the mixed precision returns GWL_EUNSUPPORTED;
+                                   gwl_sigma_c_vjp returns GWL_EUNSUPPORTED while it is set. */
 };
 /* The autotuner runs on the first gwl_sigma_c / gwl_sigma_c_range /
  * gwl_lanczos_pairs call with block = 0: it times one C-product for

@@ -24,6 +24,7 @@ KEY_PRECISION, KEY_REORTH, KEY_BLOCK, KEY_POLY_LO, KEY_POLY_HI, KEY_POLY_DEGREE 
 KEY_N_VC, KEY_LAST_MS_TOTAL, KEY_LAST_C_MATVECS, KEY_GEMM_SPLITK, KEY_KERNELS = 7, 9, 10, 11, 12
 KEY_PROFILE = 13
 KEY_GRAPHS, KEY_TUNED_BLOCK, KEY_TUNED_SPLITK, KEY_BF16_TILE, KEY_TDA = 23, 24, 25, 26, 27
+KEY_QUADRATURE = 28
 KEY_PROF = {"gemm1": (14, 15, 16), "gemm2": (17, 18, 19), "fft": (20, 21, 22)}
 PRECISIONS = {"fp64": FP64, "mixed": MIXED_BF16, "bf16": MIXED_BF16}
 
@@ -229,6 +230,10 @@ class Context:
     def set_tda(self, on: bool):
         """Tamm-Dancoff approximation on (Lanczos on A = Delta + K) or off."""
         self.set_option(KEY_TDA, 1 if on else 0)
+
+    def set_quadrature(self, on: bool):
+        """Lanczos on C with Gauss quadrature (on) or Lanczos on p_g(C) (off)."""
+        self.set_option(KEY_QUADRATURE, 1 if on else 0)
 
     def profile_totals(self):
         """{kernel: (event ms, launches, pair vectors)} of the last call when

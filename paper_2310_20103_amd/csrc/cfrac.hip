@@ -77,6 +77,118 @@ cfrac_kernel(const double* __restrict__ ca, const double* __restrict__ cb,
   }
 }
 
+// ---------------------------------------------------------------- quadrature
+// Lanczos on C + Gauss quadrature: the eigenvalues theta_k of each pair's
+// tridiagonal T and the first components u_k(0) of its eigenvectors, by the
+// implicit QL iteration with shifts (Bowdler, Martin, Reinsch and Wilkinson)
+// applying each plane rotation to the first row of the eigenvector matrix
+// only (Golub and Welsch).  One thread per pair; d, e, z are that pair's rows
+// of the scratch arrays (FP64).  On return d = theta, z = ||P||^2 u(0)^2.
+// status[p] = 1 if an eigenvalue needed more than 60 sweeps.
+__global__ void quad_eig_kernel(int npairs, const double* __restrict__ ca,
+                                const double* __restrict__ cb, const int* __restrict__ lens,
+                                const double* __restrict__ norm2, int ld, double* __restrict__ qd,
+                                double* __restrict__ qe, double* __restrict__ qz,
+                                int* __restrict__ status) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npairs) return;
+  const int n = lens[p];
+  double* d = qd + (long)p * ld;
+  double* e = qe + (long)p * ld;
+  double* z = qz + (long)p * ld;
+  for (int i = 0; i < n; ++i) {
+    d[i] = ca[(long)p * ld + i];
+    e[i] = (i + 1 < n) ? cb[(long)p * ld + i] : 0.0;  // e[i] couples i and i + 1
+    z[i] = (i == 0) ? 1.0 : 0.0;
+  }
+  int bad = 0;
+  for (int l = 0; l < n; ++l) {
+    int sweeps = 0;
+    while (true) {
+      int m = l;
+      for (; m < n - 1; ++m) {
+        const double dd = fabs(d[m]) + fabs(d[m + 1]);
+        if (fabs(e[m]) <= 2.220446049250313e-16 * dd) break;  // below one ulp of the diagonal
+      }
+      if (m == l) break;
+      if (++sweeps > 60) {
+        bad = 1;
+        break;
+      }
+      // shift from the leading 2 x 2 block
+      double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+      double r = hypot(g, 1.0);
+      g = d[m] - d[l] + e[l] / (g + (g >= 0.0 ? r : -r));
+      double s = 1.0, c = 1.0, pp = 0.0;
+      int i = m - 1;
+      bool underflow = false;
+      for (; i >= l; --i) {
+        const double f = s * e[i], b = c * e[i];
+        r = hypot(f, g);
+        e[i + 1] = r;
+        if (r == 0.0) {
+          d[i + 1] -= pp;
+          e[m] = 0.0;
+          underflow = true;
+          break;
+        }
+        s = f / r;
+        c = g / r;
+        g = d[i + 1] - pp;
+        r = (d[i] - g) * s + 2.0 * c * b;
+        pp = s * r;
+        d[i + 1] = g + pp;
+        g = c * r - b;
+        const double zf = z[i + 1];
+        z[i + 1] = s * z[i] + c * zf;
+        z[i] = c * z[i] - s * zf;
+      }
+      if (underflow) continue;
+      d[l] -= pp;
+      e[l] = g;
+      e[m] = 0.0;
+    }
+  }
+  const double n2 = norm2[p];
+  for (int i = 0; i < n; ++i) z[i] = n2 * z[i] * z[i];
+  status[p] = bad;
+}
+
+// Sigma(w, n) = sum_k w_k [1/sqrt(theta_k) - 1/(sqrt(theta_k) + eta z)] / z.
+__global__ void __launch_bounds__(256)
+quad_sigma_kernel(const double* __restrict__ qd, const double* __restrict__ qz,
+                  const int* __restrict__ lens, int ld, const double* __restrict__ e_n,
+                  const double* __restrict__ eta_n, const double* __restrict__ omega, int nomega,
+                  double delta, double* __restrict__ sig) {
+  __shared__ double so[CF_MAXL];
+  __shared__ double sw[CF_MAXL];
+  const int p = blockIdx.y;
+  const int L = lens[p];
+  for (int k = threadIdx.x; k < L; k += blockDim.x) {
+    so[k] = sqrt(fmax(qd[(long)p * ld + k], 0.0));
+    sw[k] = qz[(long)p * ld + k];
+  }
+  __syncthreads();
+  const double en = e_n[p], eta = eta_n[p];
+  for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < nomega; w += gridDim.x * blockDim.x) {
+    const double zr = omega[w] - en, zi = -eta * delta;
+    double ar = 0.0, ai = 0.0;  // sum_k w_k [1/O_k - 1/(O_k + eta z)]
+    for (int k = 0; k < L; ++k) {
+      const double o = so[k];
+      if (o <= 0.0 || sw[k] == 0.0) continue;
+      const double dr = o + eta * zr, di = eta * zi;
+      const double inv = 1.0 / (dr * dr + di * di);
+      ar += sw[k] * (1.0 / o - dr * inv);
+      ai += sw[k] * (di * inv);
+    }
+    const double dz = 1.0 / (zr * zr + zi * zi);
+    const double sr = (ar * zr + ai * zi) * dz;
+    const double si = (ai * zr - ar * zi) * dz;
+    sig[((long)p * nomega + w) * 2] = sr * kHartreeEv;
+    sig[((long)p * nomega + w) * 2 + 1] = si * kHartreeEv;
+  }
+}
+
 __global__ void sum_groups_kernel(const double* __restrict__ sig, int per, int nomega,
                                   double* __restrict__ out) {
   const int q = blockIdx.y;
@@ -98,6 +210,21 @@ void cfrac_sigma(int npairs, const double* coef_a, const double* coef_b, const i
   dim3 grid(ceil_div(nomega, 256), npairs);
   cfrac_kernel<<<grid, 256, 0, st>>>(coef_a, coef_b, lens, norm2, ld, e_n, eta_n, omega_ha,
                                      nomega, delta_ha, tda, sig);
+  GWL_HIP(hipGetLastError());
+}
+
+void quad_sigma(int npairs, const double* coef_a, const double* coef_b, const int* lens,
+                const double* norm2, int ld, const double* e_n, const double* eta_n,
+                const double* omega_ha, int nomega, double delta_ha, double* qd, double* qe,
+                double* qz, int* status, double* sig, hipStream_t st) {
+  if (npairs <= 0 || nomega <= 0) return;
+  GWL_CHECK(ld <= CF_MAXL, GWL_EINVAL, "Lanczos length exceeds 4000");
+  quad_eig_kernel<<<ceil_div(npairs, 64), 64, 0, st>>>(npairs, coef_a, coef_b, lens, norm2, ld,
+                                                        qd, qe, qz, status);
+  GWL_HIP(hipGetLastError());
+  dim3 grid(ceil_div(nomega, 256), npairs);
+  quad_sigma_kernel<<<grid, 256, 0, st>>>(qd, qz, lens, ld, e_n, eta_n, omega_ha, nomega,
+                                          delta_ha, sig);
   GWL_HIP(hipGetLastError());
 }
 

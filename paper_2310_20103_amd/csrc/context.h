@@ -135,6 +135,10 @@ struct gwl_ctx {
   int fp64_kernel = 1;  // 0 = plain FMA tiles, 1 = MFMA (both precisions)
   int bf16_tile = 256;  // block tile width of the second BF16 MFMA GEMM
   int tda = 0;          // 1: Tamm-Dancoff (Lanczos on A = Delta + K from (nm|vc))
+  int quadrature = 0;   // 1: Lanczos on C + Gauss quadrature (no polynomial)
+  DevBuf<double> qd, qe, qz;  // quadrature scratch [P][L]
+  DevBuf<int> qstat;          // [P]
+  bool lanczos_on_c() const { return quadrature && !tda; }
   // FP16 first GEMM of the mixed path: the orbital operands carry orb16_scale
   // and the pair-vector operand u_scale (powers of two chosen from bounds so
   // that no element exceeds 2^14); the combine undoes both

@@ -354,6 +354,10 @@ gwl_status gwl_set_option(gwl_ctx* ctx, int key, double value) {
         GWL_CHECK(value == 0 || value == 1, GWL_EINVAL, "tda must be 0 or 1");
         ctx->tda = (int)value;
         break;
+      case GWL_KEY_QUADRATURE:
+        GWL_CHECK(value == 0 || value == 1, GWL_EINVAL, "quadrature must be 0 or 1");
+        ctx->quadrature = (int)value;
+        break;
       case GWL_KEY_BF16_TILE:
         GWL_CHECK(value == 128 || value == 256, GWL_EINVAL, "BF16 tile must be 128 or 256");
         if (ctx->bf16_tile != (int)value) {
@@ -395,6 +399,7 @@ gwl_status gwl_query(gwl_ctx* ctx, int key, double* out) {
       case GWL_KEY_KERNELS: *out = ctx->fp64_kernel; break;
       case GWL_KEY_BF16_TILE: *out = ctx->bf16_tile; break;
       case GWL_KEY_TDA: *out = ctx->tda; break;
+      case GWL_KEY_QUADRATURE: *out = ctx->quadrature; break;
       case GWL_KEY_PROFILE: *out = ctx->profile; break;
       case GWL_KEY_GRAPHS: *out = ctx->use_graphs; break;
       case GWL_KEY_TUNED_BLOCK: *out = ctx->tuned[ctx->precision].B; break;
@@ -606,7 +611,9 @@ gwl_status gwl_lanczos_pairs(gwl_ctx* ctx, const int* m_idx, const int* n_idx, c
     auto t0 = std::chrono::steady_clock::now();
     ctx->last_c_matvecs = 0;
     ctx->prof_reset();
-    ctx->run_pairs(n_pairs, m_idx, n_idx, lengths, lmax);
+    GWL_CHECK(!ctx->lanczos_on_c() || ctx->precision == GWL_FP64, GWL_EUNSUPPORTED,
+              "the quadrature variant runs in FP64 only");
+    ctx->run_pairs(n_pairs, m_idx, n_idx, lengths, lmax, ctx->lanczos_on_c());
     std::vector<double> a((size_t)n_pairs * lmax), b((size_t)n_pairs * lmax), n2(n_pairs);
     std::vector<int> ol(n_pairs);
     GWL_HIP(hipMemcpy(a.data(), ctx->coef_a.p, a.size() * 8, hipMemcpyDeviceToHost));
@@ -650,9 +657,25 @@ void sigma_device(gwl_ctx* ctx, int P, const int* n_host, int ld, const double* 
   GWL_HIP(hipMemcpy(ctx->e_n.p, en.data(), P * 8, hipMemcpyHostToDevice));
   GWL_HIP(hipMemcpy(ctx->eta_n.p, et.data(), P * 8, hipMemcpyHostToDevice));
   GWL_HIP(hipMemcpy(ctx->omega.p, om.data(), n_omega * 8, hipMemcpyHostToDevice));
-  cfrac_sigma(P, ctx->coef_a.p, ctx->coef_b.p, ctx->out_len.p, ctx->norm2.p, ld, ctx->e_n.p,
-              ctx->eta_n.p, ctx->omega.p, n_omega, eta_ev / kHartreeEv, ctx->tda, ctx->sig.p,
-              ctx->stream);
+  if (ctx->lanczos_on_c()) {
+    ctx->qd.ensure((size_t)P * ld);
+    ctx->qe.ensure((size_t)P * ld);
+    ctx->qz.ensure((size_t)P * ld);
+    ctx->qstat.ensure(P);
+    quad_sigma(P, ctx->coef_a.p, ctx->coef_b.p, ctx->out_len.p, ctx->norm2.p, ld, ctx->e_n.p,
+               ctx->eta_n.p, ctx->omega.p, n_omega, eta_ev / kHartreeEv, ctx->qd.p, ctx->qe.p,
+               ctx->qz.p, ctx->qstat.p, ctx->sig.p, ctx->stream);
+    std::vector<int> st(P);
+    GWL_HIP(hipMemcpyAsync(st.data(), ctx->qstat.p, P * sizeof(int), hipMemcpyDeviceToHost,
+                           ctx->stream));
+    GWL_HIP(hipStreamSynchronize(ctx->stream));
+    for (int i = 0; i < P; ++i)
+      GWL_CHECK(st[i] == 0, GWL_ENUMERIC, "tridiagonal eigenvalue iteration did not converge");
+  } else {
+    cfrac_sigma(P, ctx->coef_a.p, ctx->coef_b.p, ctx->out_len.p, ctx->norm2.p, ld, ctx->e_n.p,
+                ctx->eta_n.p, ctx->omega.p, n_omega, eta_ev / kHartreeEv, ctx->tda, ctx->sig.p,
+                ctx->stream);
+  }
 }
 
 }  // namespace
@@ -687,7 +710,9 @@ gwl_status gwl_sigma_c_range(gwl_ctx* ctx, const int* qp_states, int n_qp, int n
         m[(size_t)q * per + j] = qp_states[q];
         n[(size_t)q * per + j] = n_begin + j;
       }
-    ctx->run_pairs(P, m.data(), n.data(), len.data(), n_lanczos);
+    GWL_CHECK(!ctx->lanczos_on_c() || ctx->precision == GWL_FP64, GWL_EUNSUPPORTED,
+              "the quadrature variant runs in FP64 only");
+    ctx->run_pairs(P, m.data(), n.data(), len.data(), n_lanczos, ctx->lanczos_on_c());
     sigma_device(ctx, P, n.data(), n_lanczos, omega_ev, n_omega, eta_ev);
     ctx->sig_sum.ensure((size_t)n_qp * n_omega * 2);
     sum_groups(ctx->sig.p, n_qp, per, n_omega, ctx->sig_sum.p, ctx->stream);

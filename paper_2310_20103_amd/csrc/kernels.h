@@ -182,6 +182,14 @@ void cfrac_sigma(int npairs, const double* coef_a, const double* coef_b, const i
                  const double* norm2, int ld, const double* e_n, const double* eta_n,
                  const double* omega_ha, int nomega, double delta_ha, int tda, double* sig,
                  hipStream_t st);
+// Lanczos-on-C Gauss quadrature: per pair, eigenvalues and first components
+// of T by implicit QL (qd, qe, qz, status: device scratch [npairs][ld] and
+// [npairs]), then Sigma(w, n) = sum_k w_k [theta_k^-1/2 - (theta_k^1/2 +
+// eta z)^-1] / z into sig [npairs][nomega][2] (eV).
+void quad_sigma(int npairs, const double* coef_a, const double* coef_b, const int* lens,
+                const double* norm2, int ld, const double* e_n, const double* eta_n,
+                const double* omega_ha, int nomega, double delta_ha, double* qd, double* qe,
+                double* qz, int* status, double* sig, hipStream_t st);
 // out[q][w] = sum_{p in [q*per, (q+1)*per)} sig[p][w], fixed order.
 void sum_groups(const double* sig, int ngroups, int per, int nomega, double* out,
                 hipStream_t st);
