@@ -230,8 +230,15 @@ def random_fields(n_fields: int, n_r: int, seed: int) -> np.ndarray:
     return rng.standard_normal((n_fields, n_r))
 
 
+def random_grid_points(n_points: int, n_r: int, seed: int) -> np.ndarray:
+    """Seeded distinct grid-point indices in [0, n_r), sorted, int32 (test
+    interpolation points)."""
+    rng = np.random.default_rng([seed, 9])
+    return np.sort(rng.choice(n_r, size=n_points, replace=False)).astype(np.int32)
+
+
 __all__ = [
     "Workload", "WORKLOADS", "workload", "System", "make_system",
     "make_orbitals", "make_energies", "frontier_states", "omega_grid",
-    "pair_draw", "random_pair_vectors", "random_fields",
+    "pair_draw", "random_pair_vectors", "random_fields", "random_grid_points",
 ]
