@@ -28,6 +28,10 @@ Two further measurements print their own line:
                   grid48_v64c256 (48^3 grid, 64 + 256 orbitals, L = 120,
                   32 frequencies) for one quasiparticle state; the ratio of
                   the two times.
+  --mode isdf     the headline configuration with smooth orbitals and the K
+                  product on N_mu = 4 N_orb seeded grid points (ISDF, FP64):
+                  setup time, spectra/s over --steps blocks, and the ISDF
+                  error of Sigma against the grid product on a sample.
 """
 from __future__ import annotations
 
@@ -213,10 +217,75 @@ def smooth_stress_error(G, gi):
     return out
 
 
+def run_isdf(args):
+    import torch
+    import gw_inputs as gi
+    import paper_2310_20103_amd as G
+    wl = gi.workload("grid64_v128c512", name="grid64_v128c512_smooth", smooth_sigma=1.0)
+    t = time.perf_counter()
+    phi = gi.make_orbitals(wl)
+    eps = gi.make_energies(wl)
+    qp = gi.frontier_states(eps, wl.n_occ, wl.n_qp_occ, wl.n_qp_emp)
+    omega = gi.omega_grid(wl)
+    n_mu = 4 * wl.n_orb
+    pts = gi.random_grid_points(n_mu, wl.n_r, seed=wl.seed)
+    log(f"isdf inputs {time.perf_counter() - t:.1f}s")
+    box = tuple(k * wl.h for k in wl.grid)
+    B = min(args.block, wl.n_orb)
+    ctx = G.Context(phi, eps, wl.n_occ, wl.grid, box, precision="fp64",
+                    poly_degree=wl.poly_degree, reorth="full", block=B)
+    # accuracy sample on the grid first (same interval for both products)
+    ns = list(np.linspace(0, wl.n_orb - 1, 8).astype(int))
+    m0 = int(qp[0])
+    acc_L = 40
+    a, b, n2, ol = ctx.lanczos_pairs([m0] * len(ns), ns, [acc_L] * len(ns))
+    s_grid = ctx.sigma_from_coeffs(ns, a, b, n2, ol, omega, wl.eta)
+    lo, hi = ctx.interval
+    ctx.close()
+    ctx = G.Context(phi, eps, wl.n_occ, wl.grid, box, precision="fp64",
+                    poly_degree=wl.poly_degree, poly_lo=lo, poly_hi=hi, reorth="full", block=B)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    ctx.isdf_setup(pts)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t
+    log(f"isdf setup {t_setup:.1f}s")
+    a, b, n2, ol = ctx.lanczos_pairs([m0] * len(ns), ns, [acc_L] * len(ns))
+    s_isdf = ctx.sigma_from_coeffs(ns, a, b, n2, ol, omega, wl.eta)
+    ctx.lanczos_pairs([m0] * B, list(range(B)), [1] * B)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    n_vec = 0
+    for s in range(args.steps):
+        n0 = (s * B) % wl.n_orb
+        n1 = min(wl.n_orb, n0 + B)
+        ctx.sigma_c_range([m0], n0, n1, omega, wl.eta, wl.n_lanczos)
+        n_vec += n1 - n0
+        log(f"isdf step {s} done")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    ctx.close()
+    print(json.dumps({
+        "metric": "Sigma_c spectra/s with the ISDF product, FP64", "unit": "spectra/s",
+        "value": round(n_vec / wl.n_orb / dt, 6), "n_gpus": 1, "higher_is_better": True,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": wl.name, "grid": list(wl.grid), "n_occ": wl.n_occ,
+                   "n_emp": wl.n_emp, "n_mu": n_mu, "points": "seeded random grid points",
+                   "n_lanczos": wl.n_lanczos, "n_omega": wl.n_omega, "block": B,
+                   "steps": args.steps},
+        "ms_per_step": round(dt / max(args.steps, 1) * 1e3, 1),
+        "setup_s": round(t_setup, 2),
+        "isdf_vs_grid_sigma": {"max_abs_diff_ev": float(np.max(np.abs(s_isdf - s_grid))),
+                               "max_abs_sigma_ev": float(np.max(np.abs(s_grid))),
+                               "sample": f"8 start vectors, L={acc_L}, FP64, all omega"}}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--mode", choices=("headline", "uneven", "adjoint"), default="headline")
+    ap.add_argument("--mode", choices=("headline", "uneven", "adjoint", "isdf"),
+                    default="headline")
     ap.add_argument("--pairs", type=int, default=256, help="uneven mode: pairs measured")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=0)
@@ -238,6 +307,8 @@ def main():
         if args.block == 128:
             args.block = 64
         return run_adjoint(args)
+    if args.mode == "isdf":
+        return run_isdf(args)
 
     import torch
     import gw_inputs as gi

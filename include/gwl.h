@@ -201,6 +201,23 @@ gwl_status gwl_apply_c(gwl_ctx* ctx, const double* x, double* y, int n_vec,
 gwl_status gwl_apply_d(gwl_ctx* ctx, const double* x, double* y, int n_vec,
                        int precision);
 
+/* Interpolative separable density fitting of the pair densities (Eqs. 15-17)
+ * at n_mu caller-chosen grid points (host [n_mu], strictly increasing indices
+ * into the C-order grid, z fastest): coefficients C^mu_vc = phi_v(r_mu)
+ * phi_c(r_mu), auxiliary functions zeta = Z C^T (C C^T)^-1 (least-squares
+ * fit of the pair densities Z), two-centre integrals M = dV zeta^T V[zeta].
+ * Afterwards (and whenever GWL_KEY_ISDF is 1) every K product uses
+ * K = C^T M C: the first and second GEMMs run on the N_mu sampled orbital
+ * values and a dense (M / dV) product replaces the FFT Poisson solve.  The
+ * coupling integrals (nm|vc) stay exact on the grid.  An estimated interval
+ * (poly_hi <= 0 at setup) is estimated again for the ISDF operator.  Device
+ * memory during setup: about 3 N_r N_mu doubles.  GWL_ENUMERIC when C C^T is
+ * not numerically positive definite at the points.  The ISDF product runs in
+ * FP64 only (GWL_EUNSUPPORTED for the mixed precision): summing over N_mu
+ * points instead of N_r averages the 16-bit operand rounding over far fewer
+ * terms. */
+gwl_status gwl_isdf_setup(gwl_ctx* ctx, const int* points, int n_mu);
+
 /* Exchange part of the self-energy, Sigma^ex_mm = -sum_v (vm|vm) (Eq. 6; the
  * frequency-independent term of Eq. 5), in eV, for n_qp states: pair
  * densities phi_v phi_m on the grid, the same FFT Poisson solve and kernel as
@@ -281,7 +298,7 @@ enum {
                                    gwl_sigma_from_coeffs and gwl_coupling; gwl_apply_c and
                                    gwl_apply_d keep their meaning; gwl_sigma_c_vjp returns
                                    GWL_EUNSUPPORTED while it is set. */
-  GWL_KEY_QUADRATURE = 28       /* set/query: 0 (default) = Lanczos on D = p_g(C) (Eqs. 12-14);
+  GWL_KEY_QUADRATURE = 28,      /* set/query: 0 (default) = Lanczos on D = p_g(C) (Eqs. 12-14);
                                    1 = Lanczos on C itself from P_nm, n_lanczos counting
                                    C-products, and Sigma(w, n) evaluated by the Gauss
                                    quadrature of the tridiagonal T (Ritz values theta_k,
@@ -295,6 +312,9 @@ enum {
                                    product's rounding: 5e-3 eV at L = 28 on a smooth test
                                    case), so the mixed precision returns GWL_EUNSUPPORTED;
                                    gwl_sigma_c_vjp returns GWL_EUNSUPPORTED while it is set. */
+  GWL_KEY_ISDF = 29,            /* set/query: 1 = the K product on the ISDF points of the last
+                                   gwl_isdf_setup (GWL_ESTATE before one), 0 = on the grid */
+  GWL_KEY_ISDF_NMU = 30         /* query: number of ISDF points set up, 0 if none */
 };
 /* The autotuner runs on the first gwl_sigma_c / gwl_sigma_c_range /
  * gwl_lanczos_pairs call with block = 0: it times one C-product for

@@ -24,7 +24,7 @@ KEY_PRECISION, KEY_REORTH, KEY_BLOCK, KEY_POLY_LO, KEY_POLY_HI, KEY_POLY_DEGREE 
 KEY_N_VC, KEY_LAST_MS_TOTAL, KEY_LAST_C_MATVECS, KEY_GEMM_SPLITK, KEY_KERNELS = 7, 9, 10, 11, 12
 KEY_PROFILE = 13
 KEY_GRAPHS, KEY_TUNED_BLOCK, KEY_TUNED_SPLITK, KEY_BF16_TILE, KEY_TDA = 23, 24, 25, 26, 27
-KEY_QUADRATURE = 28
+KEY_QUADRATURE, KEY_ISDF, KEY_ISDF_NMU = 28, 29, 30
 KEY_PROF = {"gemm1": (14, 15, 16), "gemm2": (17, 18, 19), "fft": (20, 21, 22)}
 PRECISIONS = {"fp64": FP64, "mixed": MIXED_BF16, "bf16": MIXED_BF16}
 
@@ -65,6 +65,7 @@ _SIGS = {
     "gwl_apply_d": (_I, [_P, _P, _P, _I, _I]),
     "gwl_coupling": (_I, [_P, _P, _P, _I, _P]),
     "gwl_sigma_x": (_I, [_P, _P, _I, _P]),
+    "gwl_isdf_setup": (_I, [_P, _P, _I]),
     "gwl_qp_solve": (_I, [_P, _I, _P, _D, _D, _D, _P, _P]),
     "gwl_set_option": (_I, [_P, _I, _D]),
     "gwl_query": (_I, [_P, _I, ct.POINTER(_D)]),
@@ -230,6 +231,15 @@ class Context:
     def set_tda(self, on: bool):
         """Tamm-Dancoff approximation on (Lanczos on A = Delta + K) or off."""
         self.set_option(KEY_TDA, 1 if on else 0)
+
+    def isdf_setup(self, points):
+        """ISDF of the pair densities at the given grid-point indices; turns
+        the ISDF product on."""
+        p = _i32(points)
+        _check(lib().gwl_isdf_setup(self._h, _ptr(p), len(p)))
+
+    def set_isdf(self, on: bool):
+        self.set_option(KEY_ISDF, 1 if on else 0)
 
     def set_quadrature(self, on: bool):
         """Lanczos on C with Gauss quadrature (on) or Lanczos on p_g(C) (off)."""

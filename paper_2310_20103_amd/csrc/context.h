@@ -136,6 +136,20 @@ struct gwl_ctx {
   int bf16_tile = 256;  // block tile width of the second BF16 MFMA GEMM
   int tda = 0;          // 1: Tamm-Dancoff (Lanczos on A = Delta + K from (nm|vc))
   int quadrature = 0;   // 1: Lanczos on C + Gauss quadrature (no polynomial)
+  bool poly_hi_auto = false;  // the interval's upper end is estimated (re-done for ISDF)
+
+  // ISDF of the pair densities: the K product runs on N_mu interpolation
+  // points with the Coulomb matrix M / dV in place of the FFT Poisson solve
+  int isdf_on = 0, isdf_ready = 0, n_mu = 0;
+  GemmDims gdi{};                     // dims with the grid replaced by the points
+  DevBuf<double> ipsi_t, ipsi_c_rc64, ipsi_v_rv64, mmat64;  // mmat: [NRp_i][NRp_i]
+  DevBuf<bf16_t> ipsi_t16;
+  DevBuf<f16_t> ipsi_c_rc16, ipsi_v_rv16;
+  DevBuf<float> ipsi_v_rv32, mmat32;
+  DevBuf<int> ipoints;
+  void* blas = nullptr;               // rocblas_handle, created with the ISDF setup
+  const GemmDims& kd() const { return isdf_on ? gdi : gd; }
+  void set_isdf(int on);
   DevBuf<double> qd, qe, qz;  // quadrature scratch [P][L]
   DevBuf<int> qstat;          // [P]
   bool lanczos_on_c() const { return quadrature && !tda; }
@@ -301,15 +315,16 @@ struct gwl_ctx {
     return heuristic_splitk(nb, prec);
   }
   int heuristic_splitk(int nb, int prec) const {
+    const GemmDims& d = kd();
     long blocks;
     if (!fp64_kernel)
-      blocks = (long)nb * (gd.nvp / 64) * ceil_div(gd.ncp, 64);
+      blocks = (long)nb * (d.nvp / 64) * ceil_div(d.ncp, 64);
     else if (prec == GWL_FP64)
-      blocks = gemm2_f64m_blocks(gd, nb);
+      blocks = gemm2_f64m_blocks(d, nb);
     else
-      blocks = gemm2_bf16_blocks(gd, nb, bf16_tile);
+      blocks = gemm2_bf16_blocks(d, nb, bf16_tile);
     int s = 1;
-    while (blocks * s < 1024 && s < 32 && (long)gd.nrp / (s * 2) >= 2048) s *= 2;
+    while (blocks * s < 1024 && s < 32 && (long)d.nrp / (s * 2) >= 2048) s *= 2;
     return s;
   }
 
@@ -351,62 +366,85 @@ struct gwl_ctx {
   int orb_row(int n) const { return n < nv ? n : gd.nvp + (n - nv); }
 
   // ---------------------------------------------------------------- products
+  // The middle step of the K product: FFT Poisson on the grid, or y = (M/dV) rho
+  // on the ISDF points (rho partials of the first GEMM summed over v tiles).
+  void middle_step(int nb, int prec, int nvt, const void* rho_in, void* v_out);
+
   // ypart <- second GEMM of K applied to u (u already cast for nb vectors).
   void k_product(int nb, int prec, int S) {
     hipStream_t st = stream;
+    const bool is = isdf_on;
+    // On N_mu points the 16-bit operand rounding of the second GEMM averages
+    // over far fewer terms than on the grid (an emulation gave a 2.5e-3
+    // relative error in K x against 4.6e-4 on the grid), so ISDF is FP64 only.
+    GWL_CHECK(!is || prec == GWL_FP64, GWL_EUNSUPPORTED, "the ISDF product runs in FP64 only");
+    const GemmDims& d = kd();
     if (prec == GWL_FP64) {
       const double* uu = u64.p;
       double* rp = reinterpret_cast<double*>(rho.p);
       double* vp = vpot64.p;
       double* yp = reinterpret_cast<double*>(ypart.p);
+      const double* crc = is ? ipsi_c_rc64.p : psi_c_rc64.p;
+      const double* vrv = is ? ipsi_v_rv64.p : psi_v_rv64.p;
+      const double* pt = is ? ipsi_t.p : psi_t.p;
       int nvt;
       prof_begin();
       if (fp64_kernel) {
-        gemm1_f64m(gd, nb, psi_c_rc64.p, psi_v_rv64.p, uu, rp, st);
-        nvt = gemm1_f64m_vtiles(gd);
+        gemm1_f64m(d, nb, crc, vrv, uu, rp, st);
+        nvt = gemm1_f64m_vtiles(d);
       } else {
-        gemm1_f64(gd, nb, psi_c_rc64.p, psi_v_rv64.p, uu, rp, st);
-        nvt = gemm1_f64_vtiles(gd);
+        gemm1_f64(d, nb, crc, vrv, uu, rp, st);
+        nvt = gemm1_f64_vtiles(d);
       }
       prof_end(0, nb);
       prof_begin();
-      poisson_launch<double>(pg64, rp, gd.nrp, (long)nb * gd.nrp, nvt, vp, gd.nrp, nb,
-                             reinterpret_cast<cplx<double>*>(fftx.p), st);
+      if (is)
+        middle_step(nb, prec, nvt, rp, vp);
+      else
+        poisson_launch<double>(pg64, rp, d.nrp, (long)nb * d.nrp, nvt, vp, d.nrp, nb,
+                               reinterpret_cast<cplx<double>*>(fftx.p), st);
       prof_end(2, nb);
-      const double* pv = psi_t.p;
-      const double* pc = psi_t.p + (size_t)gd.nvp * gd.nrp;
+      const double* pv = pt;
+      const double* pc = pt + (size_t)d.nvp * d.nrp;
       prof_begin();
       if (fp64_kernel)
-        gemm2_f64m(gd, nb, S, pv, pc, vp, yp, st);
+        gemm2_f64m(d, nb, S, pv, pc, vp, yp, st);
       else
-        gemm2_f64(gd, nb, S, pv, pc, vp, yp, st);
+        gemm2_f64(d, nb, S, pv, pc, vp, yp, st);
       prof_end(1, nb);
     } else {
       const f16_t* uu = u16.p;
       float* rp = reinterpret_cast<float*>(rho.p);
       float* vp = vpot32.p;
       float* yp = reinterpret_cast<float*>(ypart.p);
+      const f16_t* crc = is ? ipsi_c_rc16.p : psi_c_rc16.p;
+      const f16_t* vrv16 = is ? ipsi_v_rv16.p : psi_v_rv16.p;
+      const float* vrv32 = is ? ipsi_v_rv32.p : psi_v_rv32.p;
+      const bf16_t* pt = is ? ipsi_t16.p : psi_t16.p;
       int nvt;
       prof_begin();
       if (fp64_kernel) {
-        gemm1_f16(gd, nb, psi_c_rc16.p, psi_v_rv32.p, psi_v_rv16.p, uu, rp, st);
-        nvt = gemm1_f16_vtiles(gd);
+        gemm1_f16(d, nb, crc, vrv32, vrv16, uu, rp, st);
+        nvt = gemm1_f16_vtiles(d);
       } else {
-        gemm1_f16s(gd, nb, psi_c_rc16.p, psi_v_rv32.p, uu, rp, st);
-        nvt = gemm1_f16s_vtiles(gd);
+        gemm1_f16s(d, nb, crc, vrv32, uu, rp, st);
+        nvt = gemm1_f16s_vtiles(d);
       }
       prof_end(0, nb);
       prof_begin();
-      poisson_launch<float>(pg32, rp, gd.nrp, (long)nb * gd.nrp, nvt, vp, gd.nrp, nb,
-                            reinterpret_cast<cplx<float>*>(fftx.p), st);
+      if (is)
+        middle_step(nb, prec, nvt, rp, vp);
+      else
+        poisson_launch<float>(pg32, rp, d.nrp, (long)nb * d.nrp, nvt, vp, d.nrp, nb,
+                              reinterpret_cast<cplx<float>*>(fftx.p), st);
       prof_end(2, nb);
-      const bf16_t* pv = psi_t16.p;
-      const bf16_t* pc = psi_t16.p + (size_t)gd.nvp * gd.nrp;
+      const bf16_t* pv = pt;
+      const bf16_t* pc = pt + (size_t)d.nvp * d.nrp;
       prof_begin();
       if (fp64_kernel)
-        gemm2_bf16(gd, nb, bf16_tile, S, pv, pc, vp, yp, st);
+        gemm2_bf16(d, nb, bf16_tile, S, pv, pc, vp, yp, st);
       else
-        gemm2_bf16s(gd, nb, S, pv, pc, vp, yp, st);
+        gemm2_bf16s(d, nb, S, pv, pc, vp, yp, st);
       prof_end(1, nb);
     }
   }
@@ -514,7 +552,7 @@ struct gwl_ctx {
       apply_d_batch(nb, q.p, w.p, prec, false);
       return;
     }
-    if (!use_graphs || profile) {
+    if (!use_graphs || profile || isdf_on) {  // (the ISDF product calls rocBLAS)
       apply_d_batch(nb, q.p, w.p, prec, false);
       return;
     }
@@ -565,7 +603,7 @@ struct gwl_ctx {
   std::string tune_key(int prec) const {
     return "gfx950:" + std::to_string(nr) + ":" + std::to_string(nv) + ":" +
            std::to_string(nc) + ":" + std::to_string(prec) + ":" + std::to_string(fp64_kernel) + ":" +
-           std::to_string(bf16_tile);
+           std::to_string(bf16_tile) + ":" + std::to_string(isdf_on ? n_mu : 0);
   }
 
   bool tune_cache_read(int prec, Tune& t) const {
@@ -616,7 +654,7 @@ struct gwl_ctx {
         ensure_work(B, 1, false);
         const int s0 = heuristic_splitk(B, prec);
         for (int S : {s0 / 2, s0, s0 * 2}) {
-          if (S < 1 || S > 32 || (S > 1 && (long)gd.nrp / S < 1024)) continue;
+          if (S < 1 || S > 32 || (S > 1 && (long)kd().nrp / S < 1024)) continue;
           cast(B, q.p, prec);
           k_product(B, prec, S);  // warm
           GWL_HIP(hipEventRecord(e0, stream));

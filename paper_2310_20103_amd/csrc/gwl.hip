@@ -20,6 +20,8 @@
 
 #include <limits>
 
+#include <rocblas/rocblas.h>
+
 #include "context.h"
 
 namespace gwl {
@@ -303,6 +305,7 @@ gwl_status gwl_setup(const void* orbitals, int orb_dtype, int orb_on_device, int
 
     // Chebyshev interval and coefficients
     c.poly_lo = o.poly_lo > 0 ? o.poly_lo : dmin * dmin;
+    c.poly_hi_auto = !(o.poly_hi > 0);
     if (o.poly_hi > 0) {
       c.poly_hi = o.poly_hi;
     } else {
@@ -322,6 +325,7 @@ void gwl_destroy(gwl_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
   ctx->drop_graph();
+  if (ctx->blas) (void)rocblas_destroy_handle(static_cast<rocblas_handle>(ctx->blas));
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
@@ -357,6 +361,10 @@ gwl_status gwl_set_option(gwl_ctx* ctx, int key, double value) {
       case GWL_KEY_QUADRATURE:
         GWL_CHECK(value == 0 || value == 1, GWL_EINVAL, "quadrature must be 0 or 1");
         ctx->quadrature = (int)value;
+        break;
+      case GWL_KEY_ISDF:
+        GWL_CHECK(value == 0 || value == 1, GWL_EINVAL, "isdf must be 0 or 1");
+        ctx->set_isdf((int)value);
         break;
       case GWL_KEY_BF16_TILE:
         GWL_CHECK(value == 128 || value == 256, GWL_EINVAL, "BF16 tile must be 128 or 256");
@@ -400,6 +408,8 @@ gwl_status gwl_query(gwl_ctx* ctx, int key, double* out) {
       case GWL_KEY_BF16_TILE: *out = ctx->bf16_tile; break;
       case GWL_KEY_TDA: *out = ctx->tda; break;
       case GWL_KEY_QUADRATURE: *out = ctx->quadrature; break;
+      case GWL_KEY_ISDF: *out = ctx->isdf_on; break;
+      case GWL_KEY_ISDF_NMU: *out = ctx->isdf_ready ? ctx->n_mu : 0; break;
       case GWL_KEY_PROFILE: *out = ctx->profile; break;
       case GWL_KEY_GRAPHS: *out = ctx->use_graphs; break;
       case GWL_KEY_TUNED_BLOCK: *out = ctx->tuned[ctx->precision].B; break;

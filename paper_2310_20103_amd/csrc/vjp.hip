@@ -45,8 +45,9 @@ extern "C" gwl_status gwl_sigma_c_vjp(gwl_ctx* ctx, const int* qp_states, int n_
   try {
     GWL_CHECK(ctx != nullptr, GWL_EINVAL, "null context");
     gwl_ctx& c = *ctx;
-    GWL_CHECK(!c.tda && !c.quadrature, GWL_EUNSUPPORTED,
-              "the adjoint covers the polynomial method only (not Tamm-Dancoff or quadrature)");
+    GWL_CHECK(!c.tda && !c.quadrature && !c.isdf_on, GWL_EUNSUPPORTED,
+              "the adjoint covers the polynomial method on the grid only (not Tamm-Dancoff, "
+              "quadrature or ISDF)");
     GWL_CHECK(n_qp >= 1 && n_omega >= 1, GWL_EINVAL, "need n_qp >= 1 and n_omega >= 1");
     GWL_CHECK(qp_states && omega_ev && grad_sigma && grad_energies && grad_orbitals, GWL_EINVAL,
               "null pointer");

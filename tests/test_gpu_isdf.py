@@ -1,0 +1,110 @@
+"""GPU ISDF product (gwl_isdf_setup, GWL_KEY_ISDF) against the oracle.
+
+* C x with the ISDF factorisation: FP64 <= 1e-10 relative to the oracle's
+  dense C_ISDF on a smooth case and on the ragged case;
+* Sigma through the whole path: FP64 <= 1e-8 relative (smooth orbitals,
+  N_mu = 4 N_orb seeded random points); the mixed precision is refused;
+* turning ISDF off restores the grid product; bad points and enabling
+  without a setup are errors.
+"""
+import numpy as np
+import pytest
+
+import gw_inputs as gi
+import oracle
+from oracle import isdf as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def relerr(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(b)), 1e-300))
+
+
+class Case:
+    def __init__(self, base, n_mu_per_orb=4, **kw):
+        self.wl = gi.workload(base, **kw)
+        self.sys = gi.make_system(self.wl)
+        self.points = gi.random_grid_points(n_mu_per_orb * self.wl.n_orb, self.wl.n_r, seed=21)
+        self.pr = I.IsdfProblem(self.sys.phi, self.sys.energies_ev, self.wl.n_occ,
+                                self.wl.grid, self.wl.h, self.points)
+        self.lo, self.hi = oracle.default_interval(self.pr)
+
+
+def make_ctx(case, precision="fp64", **kw):
+    import paper_2310_20103_amd as G
+    wl = case.wl
+    ctx = G.Context(case.sys.phi, case.sys.energies_ev, wl.n_occ, wl.grid,
+                    tuple(n * wl.h for n in wl.grid), precision=precision,
+                    poly_degree=wl.poly_degree, poly_lo=case.lo, poly_hi=case.hi, **kw)
+    ctx.isdf_setup(case.points)
+    return ctx
+
+
+@pytest.fixture(scope="module")
+def smooth():
+    _say("isdf smooth case 24^3, 8+32, 160 points")
+    return Case("grid24_v8c32", name="smooth", smooth_sigma=1.0, n_lanczos=24, n_omega=41)
+
+
+@pytest.fixture(scope="module")
+def ragged():
+    _say("isdf ragged case 12x18x8, 5+19, 96 points")
+    return Case("grid24_v8c32", name="ragged", seed=77, grid=(12, 18, 8), box=7.0, n_occ=5,
+                n_emp=19, smooth_sigma=1.0, n_lanczos=12, n_omega=21)
+
+
+@pytest.mark.parametrize("which", ["smooth", "ragged"])
+def test_apply_c_fp64(request, which):
+    import paper_2310_20103_amd as G
+    case = request.getfixturevalue(which)
+    _say("isdf apply_c fp64", which)
+    x = gi.random_pair_vectors(3, case.wl.n_vc, seed=5)
+    with make_ctx(case) as ctx:
+        assert ctx.query(G.KEY_ISDF) == 1 and ctx.query(G.KEY_ISDF_NMU) == len(case.points)
+        got = ctx.apply_c(torch.tensor(x, device="cuda")).cpu().numpy()
+    assert relerr(got, x @ case.pr.C.T) <= 1e-10
+
+
+def test_sigma_fp64_mixed_refused(smooth):
+    import paper_2310_20103_amd as G
+    _say("isdf sigma fp64; mixed refused")
+    wl = smooth.wl
+    with make_ctx(smooth) as ctx:
+        got64 = ctx.sigma_c(smooth.sys.qp_states, smooth.sys.omega_ev, wl.eta, wl.n_lanczos)
+        ctx.set_precision("mixed")
+        with pytest.raises(G.GwlError):
+            ctx.sigma_c(smooth.sys.qp_states[:1], smooth.sys.omega_ev, wl.eta, 4)
+    for i, m in enumerate(smooth.sys.qp_states):
+        ref = smooth.pr.sigma_lanczos(int(m), smooth.sys.omega_ev, wl.eta, wl.n_lanczos,
+                                      smooth.lo, smooth.hi, wl.poly_degree)
+        assert np.max(np.abs(ref)) > 0.1
+        assert relerr(got64[i], ref) <= 1e-8
+
+
+def test_switch_off_and_errors(smooth):
+    import paper_2310_20103_amd as G
+    _say("isdf off / errors")
+    wl = smooth.wl
+    grid = oracle.Problem(smooth.sys.phi, smooth.sys.energies_ev, wl.n_occ, wl.grid, wl.h)
+    x = gi.random_pair_vectors(2, wl.n_vc, seed=6)
+    with make_ctx(smooth) as ctx:
+        ctx.set_isdf(False)
+        got = ctx.apply_c(torch.tensor(x, device="cuda")).cpu().numpy()
+        assert relerr(got, x @ grid.C.T) <= 1e-11
+        with pytest.raises(G.GwlError):
+            ctx.isdf_setup([5, 3, 9])                        # not increasing
+        with pytest.raises(G.GwlError):
+            ctx.isdf_setup([0, wl.n_r])                      # out of range
+    ctx2 = G.Context(smooth.sys.phi, smooth.sys.energies_ev, wl.n_occ, wl.grid,
+                     tuple(n * wl.h for n in wl.grid), poly_lo=smooth.lo, poly_hi=smooth.hi)
+    try:
+        with pytest.raises(G.GwlError):
+            ctx2.set_isdf(True)
+    finally:
+        ctx2.close()
