@@ -28,10 +28,12 @@ Two further measurements print their own line:
                   grid48_v64c256 (48^3 grid, 64 + 256 orbitals, L = 120,
                   32 frequencies) for one quasiparticle state; the ratio of
                   the two times.
-  --mode isdf     the headline configuration with smooth orbitals and the K
-                  product on N_mu = 4 N_orb seeded grid points (ISDF, FP64):
-                  setup time, spectra/s over --steps blocks, and the ISDF
-                  error of Sigma against the grid product on a sample.
+  --mode isdf     smooth orbitals of grid48_v64c256 (or --workload) with the
+                  K product on N_mu = r N_orb seeded grid points (ISDF, FP64;
+                  r = --isdf-ratio, 4 by default as in the paper's runs):
+                  setup time, spectra/s over --steps blocks against the grid
+                  FP64 product on a window, and the ISDF error of Sigma
+                  against the grid product on a sample.
 """
 from __future__ import annotations
 
@@ -221,13 +223,14 @@ def run_isdf(args):
     import torch
     import gw_inputs as gi
     import paper_2310_20103_amd as G
-    wl = gi.workload("grid64_v128c512", name="grid64_v128c512_smooth", smooth_sigma=1.0)
+    base = args.workload if args.workload != "grid64_v128c512" else "grid48_v64c256"
+    wl = gi.workload(base, name=base + "_smooth", smooth_sigma=1.0)
     t = time.perf_counter()
     phi = gi.make_orbitals(wl)
     eps = gi.make_energies(wl)
     qp = gi.frontier_states(eps, wl.n_occ, wl.n_qp_occ, wl.n_qp_emp)
     omega = gi.omega_grid(wl)
-    n_mu = 4 * wl.n_orb
+    n_mu = min(wl.n_r, args.isdf_ratio * wl.n_orb)
     pts = gi.random_grid_points(n_mu, wl.n_r, seed=wl.seed)
     log(f"isdf inputs {time.perf_counter() - t:.1f}s")
     box = tuple(k * wl.h for k in wl.grid)
@@ -244,6 +247,14 @@ def run_isdf(args):
     ctx.close()
     ctx = G.Context(phi, eps, wl.n_occ, wl.grid, box, precision="fp64",
                     poly_degree=wl.poly_degree, poly_lo=lo, poly_hi=hi, reorth="full", block=B)
+    # grid FP64 window for comparison: B vectors x 2 Lanczos steps
+    ctx.lanczos_pairs([m0] * B, list(range(B)), [1] * B)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    ctx.lanczos_pairs([m0] * B, list(range(B)), [2] * B)
+    torch.cuda.synchronize()
+    grid_value = 1.0 / ((time.perf_counter() - t) / (2 * B) * wl.n_lanczos * wl.n_orb)
+    log(f"grid fp64 window: {grid_value:.3g} spectra/s")
     torch.cuda.synchronize()
     t = time.perf_counter()
     ctx.isdf_setup(pts)
@@ -275,6 +286,8 @@ def run_isdf(args):
                    "steps": args.steps},
         "ms_per_step": round(dt / max(args.steps, 1) * 1e3, 1),
         "setup_s": round(t_setup, 2),
+        "grid_fp64_spectra_per_s": grid_value,
+        "isdf_vs_grid_fp64": round(n_vec / wl.n_orb / dt / grid_value, 2),
         "isdf_vs_grid_sigma": {"max_abs_diff_ev": float(np.max(np.abs(s_isdf - s_grid))),
                                "max_abs_sigma_ev": float(np.max(np.abs(s_grid))),
                                "sample": f"8 start vectors, L={acc_L}, FP64, all omega"}}),
@@ -287,6 +300,7 @@ def main():
     ap.add_argument("--mode", choices=("headline", "uneven", "adjoint", "isdf"),
                     default="headline")
     ap.add_argument("--pairs", type=int, default=256, help="uneven mode: pairs measured")
+    ap.add_argument("--isdf-ratio", type=int, default=4, help="isdf mode: N_mu / N_orb")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--block", type=int, default=128)
