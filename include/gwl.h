@@ -218,6 +218,25 @@ gwl_status gwl_apply_d(gwl_ctx* ctx, const double* x, double* y, int n_vec,
  * terms. */
 gwl_status gwl_isdf_setup(gwl_ctx* ctx, const int* points, int n_mu);
 
+/* Interpolation points for gwl_isdf_setup by weighted K-means over the grid
+ * (the paper names ISDF but not its point selection; this is the centroidal
+ * Voronoi reading).  Weight w(r) = (sum_v phi_v(r)^2)(sum_c phi_c(r)^2) of
+ * the context's orbitals, quantised to integers (2^30 at its maximum) so that
+ * cluster sums are exact; Lloyd iterations from the n_init initial centroids
+ * init_points (host, grid indices r = (x n_y + y) n_z + z, repeats allowed)
+ * under the periodic minimum-image distance, ties to the lower centroid; a
+ * centroid moves to the W-weighted mean of its members (displacements wrapped
+ * into [-n/2, n/2) about its nearest grid point); stops when an assignment
+ * repeats the previous one or after max_iter updates.  Each non-empty cluster
+ * gives its member nearest the centroid (ties to the lower index).
+ * points_out: host [n_init], receives *n_points <= n_init strictly increasing
+ * indices (ready for gwl_isdf_setup); *n_assign: assignment passes made.
+ * FP64, deterministic bit for bit; device scratch about 28 bytes per grid
+ * point, allocated and freed by the call.  GWL_EINVAL for bad arguments or
+ * weights that vanish everywhere. */
+gwl_status gwl_isdf_kmeans(gwl_ctx* ctx, const int* init_points, int n_init, int max_iter,
+                           int* points_out, int* n_points, int* n_assign);
+
 /* Exchange part of the self-energy, Sigma^ex_mm = -sum_v (vm|vm) (Eq. 6; the
  * frequency-independent term of Eq. 5), in eV, for n_qp states: pair
  * densities phi_v phi_m on the grid, the same FFT Poisson solve and kernel as

@@ -66,6 +66,7 @@ _SIGS = {
     "gwl_coupling": (_I, [_P, _P, _P, _I, _P]),
     "gwl_sigma_x": (_I, [_P, _P, _I, _P]),
     "gwl_isdf_setup": (_I, [_P, _P, _I]),
+    "gwl_isdf_kmeans": (_I, [_P, _P, _I, _I, _P, _P, _P]),
     "gwl_qp_solve": (_I, [_P, _I, _P, _D, _D, _D, _P, _P]),
     "gwl_set_option": (_I, [_P, _I, _D]),
     "gwl_query": (_I, [_P, _I, ct.POINTER(_D)]),
@@ -237,6 +238,16 @@ class Context:
         the ISDF product on."""
         p = _i32(points)
         _check(lib().gwl_isdf_setup(self._h, _ptr(p), len(p)))
+
+    def isdf_kmeans(self, init_points, max_iter=50):
+        """Weighted K-means interpolation points from the initial centroids
+        (grid indices): (strictly increasing points, assignment passes)."""
+        p = _i32(init_points)
+        out = np.zeros(len(p), dtype=np.int32)
+        n_pts, n_as = ct.c_int(0), ct.c_int(0)
+        _check(lib().gwl_isdf_kmeans(self._h, _ptr(p), len(p), int(max_iter), _ptr(out),
+                                     ct.byref(n_pts), ct.byref(n_as)))
+        return out[:n_pts.value].copy(), n_as.value
 
     def set_isdf(self, on: bool):
         self.set_option(KEY_ISDF, 1 if on else 0)

@@ -5,7 +5,10 @@
 * Sigma through the whole path: FP64 <= 1e-8 relative (smooth orbitals,
   N_mu = 4 N_orb seeded random points); the mixed precision is refused;
 * turning ISDF off restores the grid product; bad points and enabling
-  without a setup are errors.
+  without a setup are errors;
+* K-means interpolation points equal the oracle's bit for bit (isotropic and
+  anisotropic boxes, repeated initial centroids, a single pass) and fit C
+  better than the random points they start from.
 """
 import numpy as np
 import pytest
@@ -108,3 +111,61 @@ def test_switch_off_and_errors(smooth):
             ctx2.set_isdf(True)
     finally:
         ctx2.close()
+
+
+@pytest.mark.parametrize("which", ["smooth", "ragged"])
+def test_kmeans_points_match_oracle(request, which):
+    """gwl_isdf_kmeans gives the oracle's points and assignment count bit for
+    bit (integer results of exactly reproduced FP64 decisions); the ragged
+    grid runs in an anisotropic box (spacing differs per axis)."""
+    import paper_2310_20103_amd as G
+    case = request.getfixturevalue(which)
+    wl = case.wl
+    _say("isdf kmeans vs oracle", which)
+    box = tuple(n * wl.h for n in wl.grid) if which == "smooth" else (7.0, 9.1, 5.3)
+    spacing = tuple(b / n for b, n in zip(box, wl.grid))
+    init = gi.random_grid_points(len(case.points), wl.n_r, seed=31)
+    ref, ref_n = I.kmeans_points(I.kmeans_weights(case.sys.phi, wl.n_occ), wl.grid, spacing,
+                                 init, 25)
+    with G.Context(case.sys.phi, case.sys.energies_ev, wl.n_occ, wl.grid, box,
+                   poly_lo=case.lo, poly_hi=case.hi) as ctx:
+        got, got_n = ctx.isdf_kmeans(init, 25)
+    assert got_n == ref_n
+    assert np.array_equal(got, ref)
+
+
+def test_kmeans_edges(smooth):
+    """Repeated initial centroids leave clusters empty (fewer points), a
+    single assignment pass at max_iter = 0, and bad arguments are errors."""
+    import paper_2310_20103_amd as G
+    wl = smooth.wl
+    _say("isdf kmeans edges")
+    spacing = tuple((n * wl.h) / n for n in wl.grid)
+    w = I.kmeans_weights(smooth.sys.phi, wl.n_occ)
+    init = [17, 17, 4000, 9000, 9000, 12000]
+    with make_ctx(smooth) as ctx:
+        for it in (0, 3):
+            got, got_n = ctx.isdf_kmeans(init, it)
+            ref, ref_n = I.kmeans_points(w, wl.grid, spacing, init, it)
+            assert got_n == ref_n and np.array_equal(got, ref)
+        assert ctx.isdf_kmeans(init, 0)[1] == 1 and len(ctx.isdf_kmeans(init, 0)[0]) == 4
+        with pytest.raises(G.GwlError):
+            ctx.isdf_kmeans([0, wl.n_r], 5)
+        with pytest.raises(G.GwlError):
+            ctx.isdf_kmeans([1, 2], -1)
+
+
+def test_kmeans_points_fit_better(smooth):
+    """C x with ISDF on the K-means points is closer to the grid product than
+    with the random points they started from (same count)."""
+    wl = smooth.wl
+    _say("isdf kmeans fit vs random")
+    grid = oracle.Problem(smooth.sys.phi, smooth.sys.energies_ev, wl.n_occ, wl.grid, wl.h)
+    x = gi.random_pair_vectors(3, wl.n_vc, seed=8)
+    ref = x @ grid.C.T
+    with make_ctx(smooth) as ctx:
+        pts, _ = ctx.isdf_kmeans(smooth.points, 30)
+        err_rand = relerr(ctx.apply_c(torch.tensor(x, device="cuda")).cpu().numpy(), ref)
+        ctx.isdf_setup(pts)
+        err_km = relerr(ctx.apply_c(torch.tensor(x, device="cuda")).cpu().numpy(), ref)
+    assert err_km < 0.9 * err_rand
