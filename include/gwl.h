@@ -132,6 +132,19 @@ gwl_status gwl_sigma_c(gwl_ctx* ctx, const int* qp_states, int n_qp,
                        const double* omega_ev, int n_omega, double eta_ev,
                        int n_lanczos, double* sigma_out);
 
+/* Off-diagonal Sigma^corr_mm2(w) of two states (the paper's closing remarks
+ * point to a band Lanczos for off-diagonal elements).  The per-n term of
+ * Eqs. 12-14 is a quadratic form in the Lanczos start vector, so the
+ * bilinear form is a quarter of the difference of the runs from
+ * P_nm + P_nm2 and P_nm - P_nm2 (polarisation identity): 2 n_orb Lanczos
+ * runs of length n_lanczos, otherwise as gwl_sigma_c (the same precision,
+ * Tamm-Dancoff, quadrature and ISDF options apply).  m2 = m gives
+ * gwl_sigma_c's diagonal element.  sigma_out: host [n_omega][2] (re, im), eV.
+ * Device scratch: 2 n_orb N_vc doubles for the start vectors, freed on
+ * return.  Errors as gwl_sigma_c. */
+gwl_status gwl_sigma_c_offdiag(gwl_ctx* ctx, int m, int m2, const double* omega_ev, int n_omega,
+                               double eta_ev, int n_lanczos, double* sigma_out);
+
 /* Partial sum of Eq. 10: for every m in qp_states, sigma_out[q][w] =
  * sum_{n = n_begin}^{n_end - 1} Sigma_mm(w, n), same units and layout as
  * gwl_sigma_c (which is the range [0, n_orb)).  Disjoint n-ranges add up to

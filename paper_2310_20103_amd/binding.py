@@ -66,6 +66,7 @@ _SIGS = {
     "gwl_coupling": (_I, [_P, _P, _P, _I, _P]),
     "gwl_sigma_x": (_I, [_P, _P, _I, _P]),
     "gwl_isdf_setup": (_I, [_P, _P, _I]),
+    "gwl_sigma_c_offdiag": (_I, [_P, _I, _I, _P, _I, _D, _I, _P]),
     "gwl_isdf_kmeans": (_I, [_P, _P, _I, _I, _P, _P, _P]),
     "gwl_qp_solve": (_I, [_P, _I, _P, _D, _D, _D, _P, _P]),
     "gwl_set_option": (_I, [_P, _I, _D]),
@@ -270,6 +271,15 @@ class Context:
         _check(lib().gwl_sigma_c(self._h, _ptr(q), len(q), _ptr(om), len(om), float(eta_ev),
                                  int(n_lanczos), _ptr(out)))
         return out[..., 0] + 1j * out[..., 1]
+
+    def sigma_c_offdiag(self, m: int, m2: int, omega_ev, eta_ev: float,
+                        n_lanczos: int) -> np.ndarray:
+        """Off-diagonal Sigma^corr_mm2(omega) in eV, complex128 [n_omega]."""
+        om = _f64(omega_ev)
+        out = np.zeros((len(om), 2), dtype=np.float64)
+        _check(lib().gwl_sigma_c_offdiag(self._h, int(m), int(m2), _ptr(om), len(om),
+                                         float(eta_ev), int(n_lanczos), _ptr(out)))
+        return out[:, 0] + 1j * out[:, 1]
 
     def sigma_c_range(self, qp_states, n_begin: int, n_end: int, omega_ev, eta_ev: float,
                       n_lanczos: int) -> np.ndarray:

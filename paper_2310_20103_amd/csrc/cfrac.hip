@@ -199,6 +199,19 @@ __global__ void sum_groups_kernel(const double* __restrict__ sig, int per, int n
   }
 }
 
+// out[e] = (sum_n sig[2n][e] - sig[2n+1][e]) / 4, n in order: the
+// polarisation identity over runs from P_nm + P_nm' (even pairs) and
+// P_nm - P_nm' (odd pairs)
+__global__ void sum_polar_kernel(const double* __restrict__ sig, int nn, int nomega,
+                                 double* __restrict__ out) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < 2 * nomega; e += gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int n = 0; n < nn; ++n)
+      s += sig[((long)(2 * n) * nomega) * 2 + e] - sig[((long)(2 * n + 1) * nomega) * 2 + e];
+    out[e] = 0.25 * s;
+  }
+}
+
 }  // namespace
 
 void cfrac_sigma(int npairs, const double* coef_a, const double* coef_b, const int* lens,
@@ -233,6 +246,12 @@ void sum_groups(const double* sig, int ngroups, int per, int nomega, double* out
   if (ngroups <= 0) return;
   dim3 grid(ceil_div(2 * nomega, 256), ngroups);
   sum_groups_kernel<<<grid, 256, 0, st>>>(sig, per, nomega, out);
+  GWL_HIP(hipGetLastError());
+}
+
+void sum_polar(const double* sig, int nn, int nomega, double* out, hipStream_t st) {
+  if (nn <= 0 || nomega <= 0) return;
+  sum_polar_kernel<<<ceil_div(2 * nomega, 256), 256, 0, st>>>(sig, nn, nomega, out);
   GWL_HIP(hipGetLastError());
 }
 

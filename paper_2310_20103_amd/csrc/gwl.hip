@@ -746,6 +746,58 @@ gwl_status gwl_sigma_c(gwl_ctx* ctx, const int* qp_states, int n_qp, const doubl
                            n_lanczos, sigma_out);
 }
 
+gwl_status gwl_sigma_c_offdiag(gwl_ctx* ctx, int m, int m2, const double* omega_ev, int n_omega,
+                               double eta_ev, int n_lanczos, double* sigma_out) {
+  return guarded([&] {
+    check_ctx(ctx);
+    GWL_CHECK(n_omega >= 0, GWL_EINVAL, "negative count");
+    if (n_omega == 0) return;
+    GWL_CHECK(omega_ev && sigma_out, GWL_EINVAL, "null pointer");
+    GWL_CHECK(m >= 0 && m < ctx->n_orb && m2 >= 0 && m2 < ctx->n_orb, GWL_EINVAL,
+              "qp state out of range");
+    GWL_CHECK(std::isfinite(eta_ev) && eta_ev > 0, GWL_EINVAL, "eta must be > 0");
+    GWL_CHECK(n_lanczos >= 1 && n_lanczos <= 4000, GWL_EINVAL,
+              "n_lanczos must be in [1, 4000]");
+    GWL_CHECK(finite_all(omega_ev, n_omega), GWL_EINVAL, "non-finite frequency");
+    GWL_CHECK(!ctx->lanczos_on_c() || ctx->precision == GWL_FP64, GWL_EUNSUPPORTED,
+              "the quadrature variant runs in FP64 only");
+    auto t0 = std::chrono::steady_clock::now();
+    ctx->last_c_matvecs = 0;
+    ctx->prof_reset();
+    const int no = ctx->n_orb;
+    const long nvc = ctx->nvc;
+    // start vectors: rows 2n, 2n + 1 = P_nm + P_nm2, P_nm - P_nm2
+    DevBuf<double> start, pa, pb;
+    start.ensure((size_t)2 * no * nvc);
+    const int chunk = std::min(no, 64);
+    pa.ensure((size_t)chunk * nvc);
+    pb.ensure((size_t)chunk * nvc);
+    std::vector<int> mv(chunk, m), m2v(chunk, m2), nv(chunk);
+    for (int n0 = 0; n0 < no; n0 += chunk) {
+      const int cnt = std::min(chunk, no - n0);
+      for (int i = 0; i < cnt; ++i) nv[i] = n0 + i;
+      ctx->coupling_batch(cnt, mv.data(), nv.data(), pa.p, nvc);
+      ctx->coupling_batch(cnt, m2v.data(), nv.data(), pb.p, nvc);
+      polar_rows(pa.p, pb.p, nvc, cnt, start.p + (size_t)2 * n0 * nvc, ctx->stream);
+    }
+    const int P = 2 * no;
+    std::vector<int> pm(P, m), pn(P), len(P, n_lanczos);
+    for (int i = 0; i < P; ++i) pn[i] = i / 2;
+    ctx->run_pairs(P, pm.data(), pn.data(), len.data(), n_lanczos, ctx->lanczos_on_c(),
+                   start.p);
+    sigma_device(ctx, P, pn.data(), n_lanczos, omega_ev, n_omega, eta_ev);
+    ctx->sig_sum.ensure((size_t)n_omega * 2);
+    sum_polar(ctx->sig.p, no, n_omega, ctx->sig_sum.p, ctx->stream);
+    GWL_HIP(hipMemcpyAsync(sigma_out, ctx->sig_sum.p, sizeof(double) * n_omega * 2,
+                           hipMemcpyDeviceToHost, ctx->stream));
+    GWL_HIP(hipStreamSynchronize(ctx->stream));
+    GWL_CHECK(finite_all(sigma_out, (size_t)n_omega * 2), GWL_ENUMERIC,
+              "non-finite self-energy");
+    ctx->last_ms_total =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  });
+}
+
 gwl_status gwl_sigma_from_coeffs(gwl_ctx* ctx, const int* n_idx, int n_pairs, const double* alpha,
                                  const double* beta, const double* p_norm2, const int* lens,
                                  int ld, const double* omega_ev, int n_omega, double eta_ev,

@@ -191,6 +191,10 @@ void quad_sigma(int npairs, const double* coef_a, const double* coef_b, const in
                 const double* omega_ha, int nomega, double delta_ha, double* qd, double* qe,
                 double* qz, int* status, double* sig, hipStream_t st);
 // out[q][w] = sum_{p in [q*per, (q+1)*per)} sig[p][w], fixed order.
+// dst rows 2i, 2i + 1 = a_i + b_i, a_i - b_i (cnt rows of length n each)
+void polar_rows(const double* a, const double* b, long n, int cnt, double* dst, hipStream_t st);
+// out [nomega][2] = (sum_n sig[2n] - sig[2n+1]) / 4 over nn pairs of rows
+void sum_polar(const double* sig, int nn, int nomega, double* out, hipStream_t st);
 void sum_groups(const double* sig, int ngroups, int per, int nomega, double* out,
                 hipStream_t st);
 

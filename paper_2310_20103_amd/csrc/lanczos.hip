@@ -285,6 +285,27 @@ inline int grid_elems(long n) {
 
 }  // namespace
 
+// dst[2i] = a_i + b_i, dst[2i + 1] = a_i - b_i (rows of length n)
+__global__ void polar_rows_kernel(const double* __restrict__ a, const double* __restrict__ b,
+                                  long n, double* __restrict__ dst) {
+  const int i = blockIdx.y;
+  const double* ai = a + (long)i * n;
+  const double* bi = b + (long)i * n;
+  double* dp = dst + (long)(2 * i) * n;
+  double* dm = dp + n;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n;
+       e += (long)gridDim.x * blockDim.x) {
+    dp[e] = ai[e] + bi[e];
+    dm[e] = ai[e] - bi[e];
+  }
+}
+
+void polar_rows(const double* a, const double* b, long n, int cnt, double* dst, hipStream_t st) {
+  if (cnt <= 0) return;
+  polar_rows_kernel<<<dim3(grid_elems(n), cnt), NT, 0, st>>>(a, b, n, dst);
+  GWL_HIP(hipGetLastError());
+}
+
 void pair_product(const double* psi_t, long ld, int nr, const int* m_idx, const int* n_idx,
                   int cnt, double* rho, hipStream_t st) {
   if (cnt <= 0) return;
