@@ -202,6 +202,8 @@ struct gwl_ctx {
   DevBuf<unsigned char> ypart; // [S][cap][NVp][NCp] x 8
   DevBuf<double> basis;        // [cap][cap_L][nvc]
   DevBuf<double> hbuf;         // [cap][cap_L + 1]
+  DevBuf<double> rw_n0, rw_part;  // reorthogonalisation scratch [cap], [cap][part_len]
+  DevBuf<int> rw_skip;            // [cap]
   DevBuf<int> s_pair, s_k, s_len, s_dead, s_slots, s_m, s_n, s_act;
   // while set, GEMM operand rows map to these slots (see PairGeom::rows)
   const int* cur_rows = nullptr;
@@ -354,6 +356,9 @@ struct gwl_ctx {
       s_n.ensure(nb);
       s_amax.ensure(nb);
       s_bprev.ensure(nb);
+      rw_n0.ensure(nb);
+      rw_part.ensure((size_t)nb * reorth_part_len(nvc));
+      rw_skip.ensure(nb);
       cap = nb;
     }
     if (Lrows + 1 > cap_L || nb * (size_t)(Lrows + 1) > hbuf.n) {
@@ -816,7 +821,7 @@ struct gwl_ctx {
       cur_rows = nullptr;
       lz_alpha(ss, B, q.p, qprev.p, w.p, nvc, stream);
       lz_reorth(ss, B, kmax, reorth, full ? basis.p : nullptr, bstride, q.p, qprev.p, w.p,
-                hbuf.p, nvc, stream);
+                hbuf.p, ReorthScratch{rw_n0.p, rw_part.p, rw_skip.p}, nvc, stream);
       lz_beta(ss, B, q.p, qprev.p, w.p, full ? basis.p : nullptr, bstride, full ? 1 : 0, nvc,
               stream);
       for (int b = 0; b < B; ++b)

@@ -168,10 +168,20 @@ void lz_start(const SlotState& s, int nb_slots, const int* slot_list, int cnt, d
 // a_k = q.w; w -= a_k q + b_k q_prev.
 void lz_alpha(const SlotState& s, int nb, const double* q, const double* qprev, double* w,
               long nvc, hipStream_t st);
-// full (two-pass CGS against basis rows 0..k) or local reorthogonalisation.
+// Scratch of the full reorthogonalisation: wn0 [nb], part [nb][reorth_part_len],
+// skip [nb].
+struct ReorthScratch {
+  double* wn0;
+  double* part;
+  int* skip;
+};
+long reorth_part_len(long nvc);
+// full (classical Gram-Schmidt against basis rows 0..k, a second pass where
+// the first removed more than half of ||w||^2) or local (two passes against
+// q_k, q_{k-1}) reorthogonalisation.
 void lz_reorth(const SlotState& s, int nb, int kmax, int mode, const double* basis,
                long basis_slot_stride, const double* q, const double* qprev, double* w,
-               double* hbuf, long nvc, hipStream_t st);
+               double* hbuf, const ReorthScratch& rs, long nvc, hipStream_t st);
 // b_{k+1} = ||w||; breakdown test; q_prev = q; q = w / b; basis row k+1 = q; k += 1.
 void lz_beta(const SlotState& s, int nb, double* q, double* qprev, double* w, double* basis,
              long basis_slot_stride, int store_basis, long nvc, hipStream_t st);

@@ -184,14 +184,18 @@ __device__ inline bool needs_beta(const SlotState& s, int b) {
   return slot_active(s, b) && s.k[b] < s.len[b] - 1;
 }
 
-// h[b][j] = basis_j . w  (FULL: j <= k; LOCAL: j in {k-1, k} read from q, qprev)
+// h[b][j] = basis_j . w  (FULL: j <= k; LOCAL: j in {k-1, k} read from q, qprev).
+// skip (optional): slots whose second pass is not needed; wn0 (optional):
+// ||w||^2 before the pass, from the j = 0 block.
 __global__ void __launch_bounds__(NT)
 lz_dots_kernel(SlotState s, int mode, const double* __restrict__ basis, long bstride,
                const double* __restrict__ q, const double* __restrict__ qprev,
-               const double* __restrict__ w, double* __restrict__ h, int hld, long nvc) {
+               const double* __restrict__ w, double* __restrict__ h, int hld, long nvc,
+               const int* __restrict__ skip, double* __restrict__ wn0) {
   __shared__ double sh[NT / 64];
   const int j = blockIdx.x, b = blockIdx.y;
   if (!needs_beta(s, b)) return;
+  if (skip && skip[b]) return;
   const int k = s.k[b];
   const double* vb;
   if (mode == GWL_REORTH_FULL) {
@@ -205,21 +209,36 @@ lz_dots_kernel(SlotState s, int mode, const double* __restrict__ basis, long bst
     vb = (j == 0 ? q : qprev) + (long)b * nvc;
   }
   const double* wb = w + (long)b * nvc;
-  double part = 0.0;
-  for (long i = threadIdx.x; i < nvc; i += NT) part += vb[i] * wb[i];
+  double part = 0.0, ww = 0.0;
+  const bool norm = wn0 && j == 0;
+  for (long i = threadIdx.x; i < nvc; i += NT) {
+    const double x = wb[i];
+    part += vb[i] * x;
+    if (norm) ww += x * x;
+  }
   const double t = block_sum(part, sh);
   if (threadIdx.x == 0) h[(long)b * hld + j] = t;
+  if (norm) {
+    const double n2 = block_sum(ww, sh);
+    if (threadIdx.x == 0) wn0[b] = n2;
+  }
 }
 
-__global__ void lz_project_kernel(SlotState s, int mode, const double* __restrict__ basis,
-                                  long bstride, const double* __restrict__ q,
-                                  const double* __restrict__ qprev, double* __restrict__ w,
-                                  const double* __restrict__ h, int hld, long nvc) {
+// w -= sum_j h[b][j] basis_j; part (optional): per-block ||w_new||^2 partial
+// sums [nb][gridDim.x]
+__global__ void __launch_bounds__(NT)
+lz_project_kernel(SlotState s, int mode, const double* __restrict__ basis, long bstride,
+                  const double* __restrict__ q, const double* __restrict__ qprev,
+                  double* __restrict__ w, const double* __restrict__ h, int hld, long nvc,
+                  const int* __restrict__ skip, double* __restrict__ part) {
+  __shared__ double sh[NT / 64];
   const int b = blockIdx.y;
   if (!needs_beta(s, b)) return;
+  if (skip && skip[b]) return;
   const int k = s.k[b];
   const double* hb = h + (long)b * hld;
   double* wb = w + (long)b * nvc;
+  double ww = 0.0;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < nvc; i += (long)gridDim.x * blockDim.x) {
     double acc = 0.0;
     if (mode == GWL_REORTH_FULL) {
@@ -229,8 +248,33 @@ __global__ void lz_project_kernel(SlotState s, int mode, const double* __restric
       acc = hb[0] * q[(long)b * nvc + i];
       if (k > 0) acc += hb[1] * qprev[(long)b * nvc + i];
     }
-    wb[i] -= acc;
+    const double x = wb[i] - acc;
+    wb[i] = x;
+    ww += x * x;
   }
+  if (part) {
+    const double t = block_sum(ww, sh);
+    if (threadIdx.x == 0) part[(long)b * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+// Second-pass test (Daniel, Gragg, Kaufman and Stewart): the first pass
+// removed little of w when ||w_1||^2 >= ||w_0||^2 / 2, and a second pass
+// would change it only at rounding level, so it is skipped.  Partial sums in
+// a fixed order.
+__global__ void __launch_bounds__(NT)
+lz_dgks_kernel(SlotState s, const double* __restrict__ part, int nblk,
+               const double* __restrict__ wn0, int* __restrict__ skip) {
+  __shared__ double sh[NT / 64];
+  const int b = blockIdx.x;
+  if (!needs_beta(s, b)) {
+    if (threadIdx.x == 0) skip[b] = 1;
+    return;
+  }
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += NT) v += part[(long)b * nblk + i];
+  const double n1 = block_sum(v, sh);
+  if (threadIdx.x == 0) skip[b] = (n1 >= 0.5 * wn0[b]) ? 1 : 0;
 }
 
 __global__ void __launch_bounds__(NT)
@@ -414,18 +458,28 @@ void lz_alpha(const SlotState& s, int nb, const double* q, const double* qprev, 
 
 void lz_reorth(const SlotState& s, int nb, int kmax, int mode, const double* basis,
                long bstride, const double* q, const double* qprev, double* w, double* hbuf,
-               long nvc, hipStream_t st) {
+               const ReorthScratch& rs, long nvc, hipStream_t st) {
   if (mode == GWL_REORTH_NONE) return;
-  const int nd = (mode == GWL_REORTH_FULL) ? kmax + 1 : 2;
-  const int hld = (mode == GWL_REORTH_FULL) ? s.ld + 1 : 2;
-  for (int pass = 0; pass < 2; ++pass) {
-    lz_dots_kernel<<<dim3(nd, nb), NT, 0, st>>>(s, mode, basis, bstride, q, qprev, w, hbuf,
-                                                hld, nvc);
-    lz_project_kernel<<<dim3(grid_elems(nvc), nb), NT, 0, st>>>(s, mode, basis, bstride, q,
-                                                                qprev, w, hbuf, hld, nvc);
-  }
+  const bool full = (mode == GWL_REORTH_FULL);
+  const int nd = full ? kmax + 1 : 2;
+  const int hld = full ? s.ld + 1 : 2;
+  const int ge = grid_elems(nvc);
+  // FULL: classical Gram-Schmidt, the second pass only where the first
+  // removed more than half of ||w||^2; LOCAL: always two passes
+  lz_dots_kernel<<<dim3(nd, nb), NT, 0, st>>>(s, mode, basis, bstride, q, qprev, w, hbuf, hld,
+                                              nvc, nullptr, full ? rs.wn0 : nullptr);
+  lz_project_kernel<<<dim3(ge, nb), NT, 0, st>>>(s, mode, basis, bstride, q, qprev, w, hbuf,
+                                                 hld, nvc, nullptr, full ? rs.part : nullptr);
+  if (full) lz_dgks_kernel<<<nb, NT, 0, st>>>(s, rs.part, ge, rs.wn0, rs.skip);
+  const int* sk = full ? rs.skip : nullptr;
+  lz_dots_kernel<<<dim3(nd, nb), NT, 0, st>>>(s, mode, basis, bstride, q, qprev, w, hbuf, hld,
+                                              nvc, sk, nullptr);
+  lz_project_kernel<<<dim3(ge, nb), NT, 0, st>>>(s, mode, basis, bstride, q, qprev, w, hbuf,
+                                                 hld, nvc, sk, nullptr);
   GWL_HIP(hipGetLastError());
 }
+
+long reorth_part_len(long nvc) { return grid_elems(nvc); }
 
 void lz_beta(const SlotState& s, int nb, double* q, double* qprev, double* w, double* basis,
              long bstride, int store_basis, long nvc, hipStream_t st) {
