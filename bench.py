@@ -303,10 +303,80 @@ def run_isdf(args):
           flush=True)
 
 
+def run_libref(args):
+    """The two 16-bit GEMM kernels of one B-vector C-product against the
+    vendor BLAS (torch.matmul, hipBLASLt) on the same shapes with plain
+    operands: the second GEMM's shape with its A operand already formed, the
+    first GEMM's shape with its [B N_v, N_r] product written out (neither
+    fused step is included on the library side)."""
+    import torch
+    import gw_inputs as gi
+    import paper_2310_20103_amd as G
+    wl = gi.workload(args.workload)
+    phi = gi.make_orbitals(wl)
+    eps = gi.make_energies(wl)
+    qp = gi.frontier_states(eps, wl.n_occ, wl.n_qp_occ, wl.n_qp_emp)
+    B = min(args.block, wl.n_orb)
+    box = tuple(n * wl.h for n in wl.grid)
+    ctx = G.Context(phi, eps, wl.n_occ, wl.grid, box, precision="mixed",
+                    poly_degree=wl.poly_degree, reorth="full", block=B)
+    m = [int(qp[0])] * B
+    n = list(range(B))
+    ctx.lanczos_pairs(m, n, [1] * B)
+    ctx.set_option(G.KEY_PROFILE, 1)
+    ours = {}
+    for rep in range(3):
+        ctx.lanczos_pairs(m, n, [2] * B)
+        for k, (ms, cnt, _) in ctx.profile_totals().items():
+            if cnt:
+                ours[k] = min(ours.get(k, 1e30), ms / cnt)
+    ctx.close()
+    log("library kernels timed")
+    M, Kc, Nr = B * wl.n_occ, wl.n_emp, wl.n_r
+    flop = 2.0 * M * Kc * Nr
+
+    def timed(fn, reps=5):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    lib = {}
+    for name, dt in (("bf16", torch.bfloat16), ("f16", torch.float16)):
+        a = torch.randn(M, Nr, device="cuda", dtype=dt)
+        bm = torch.randn(Nr, Kc, device="cuda", dtype=dt)
+        lib["gemm2_shape_" + name] = timed(lambda: a @ bm)
+        del a, bm
+        u = torch.randn(M, Kc, device="cuda", dtype=dt)
+        pc = torch.randn(Nr, Kc, device="cuda", dtype=dt)
+        out = torch.empty(M, Nr, device="cuda", dtype=dt)
+        lib["gemm1_shape_" + name] = timed(lambda: torch.matmul(u, pc.t(), out=out))
+        del u, pc, out
+        torch.cuda.empty_cache()
+        log(f"library {name} timed")
+    tf = lambda ms: round(flop / (ms * 1e-3) / 1e12, 1)
+    print(json.dumps({
+        "metric": "16-bit GEMM ms per launch: fused kernels vs vendor BLAS on the same shapes",
+        "config": {"workload": wl.name, "M": M, "N_c": Kc, "N_r": Nr, "block": B},
+        "ours_ms": {k: round(v, 4) for k, v in ours.items()},
+        "ours_tflops": {k: tf(v) for k, v in ours.items() if k.startswith("gemm")},
+        "hipblaslt_ms": {k: round(v, 4) for k, v in lib.items()},
+        "hipblaslt_tflops": {k: tf(v) for k, v in lib.items()},
+        "note": "ours: gemm1 = FP16 GEMM with the fused row-dot (no C written), gemm2 = BF16 "
+                "GEMM forming phi_v*V in staging; library: plain operands, unfused"}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--mode", choices=("headline", "uneven", "adjoint", "isdf"),
+    ap.add_argument("--mode", choices=("headline", "uneven", "adjoint", "isdf", "libref"),
                     default="headline")
     ap.add_argument("--pairs", type=int, default=256, help="uneven mode: pairs measured")
     ap.add_argument("--isdf-ratio", type=int, default=4, help="isdf mode: N_mu / N_orb")
@@ -334,6 +404,8 @@ def main():
         return run_adjoint(args)
     if args.mode == "isdf":
         return run_isdf(args)
+    if args.mode == "libref":
+        return run_libref(args)
 
     import torch
     import gw_inputs as gi
