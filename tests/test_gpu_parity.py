@@ -378,6 +378,56 @@ def test_errors_and_empty(small, ctx_small):
     assert out.shape == (1, 0)
 
 
+# ------------------------------------------------------------------ wide valence space
+@pytest.fixture(scope="module")
+def wide():
+    # N_v = 136 pads to 256: two 128-wide v tiles of the first GEMM (FP32
+    # weights from L2, partial densities summed in the FFT's first pass) and
+    # the general A loader of the second GEMM
+    _say("wide case grid 12^3, 136+12 orbitals")
+    return Case("grid24_v8c32", name="wide", seed=55, grid=(12, 12, 12), box=6.0,
+                n_occ=136, n_emp=12)
+
+
+def test_apply_c_wide_valence(wide):
+    import paper_2310_20103_amd as G
+    _say("apply_c wide valence, fp64 / mixed / plain kernels")
+    ctx = make_ctx(wide.sys, interval=(wide.lo, wide.hi))
+    try:
+        assert ctx.query(G.KEY_N_VC) == 136 * 12
+        x = gi.random_pair_vectors(6, wide.wl.n_vc, seed=14)
+        ref = x @ wide.pr.C.T
+        xt = torch.tensor(x, device="cuda")
+        got64 = ctx.apply_c(xt).cpu().numpy()
+        gotmx = ctx.apply_c(xt, "mixed").cpu().numpy()
+        ctx.set_option(G.KEY_KERNELS, 0)
+        plain = ctx.apply_c(xt, "mixed").cpu().numpy()
+    finally:
+        ctx.close()
+    assert relerr(got64, ref) <= 1e-11
+    assert relerr(gotmx, ref) <= 1e-3
+    dk = ref - wide.pr.delta ** 2 * x
+    assert relerr(gotmx - wide.pr.delta ** 2 * x, dk) <= 2e-2
+    # the plain kernels round the 16-bit operands in another order: their
+    # coupling parts agree to the same 16-bit bar
+    d2x = wide.pr.delta ** 2 * x
+    assert relerr(gotmx - d2x, plain - d2x) <= 2e-2
+
+
+def test_sigma_wide_valence(wide):
+    _say("sigma wide valence fp64, 2 QP states, L = 8")
+    wl = wide.wl
+    om = np.linspace(-15, 15, 31)
+    ctx = make_ctx(wide.sys, interval=(wide.lo, wide.hi))
+    try:
+        got = ctx.sigma_c(wide.sys.qp_states, om, wl.eta, 8)
+    finally:
+        ctx.close()
+    for i, m in enumerate(wide.sys.qp_states):
+        ref = wide.pr.sigma_lanczos(int(m), om, wl.eta, 8, wide.lo, wide.hi, wl.poly_degree)
+        assert relerr(got[i], ref) <= 1e-8
+
+
 # ------------------------------------------------------------------ kernel variants
 @pytest.mark.parametrize("which", ["small", "ragged"])
 def test_mfma_matches_plain_kernels(request, which):
