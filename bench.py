@@ -303,6 +303,82 @@ def run_isdf(args):
           flush=True)
 
 
+def run_large(args):
+    """The 128^3, 512 + 1,024-orbital configuration (FP32 orbitals, pair dim
+    524,288): a steady-state window of the mixed-precision path at B vectors,
+    extrapolated to the full spectrum, and the mixed-vs-FP64 error on a
+    sample.  The window is the difference of a 1-step and a (1 + k)-step
+    Lanczos run over the same B start vectors, so the coupling-vector build
+    and the setup drop out."""
+    import torch
+    import gw_inputs as gi
+    import paper_2310_20103_amd as G
+    wl = gi.workload("grid128_v512c1024")
+    t = time.perf_counter()
+    phi = gi.make_orbitals(wl, dtype=np.float32, progress=log)
+    eps = gi.make_energies(wl)
+    qp = gi.frontier_states(eps, wl.n_occ, wl.n_qp_occ, wl.n_qp_emp)
+    omega = gi.omega_grid(wl)
+    log(f"large inputs {time.perf_counter() - t:.1f}s ({phi.nbytes / 2**30:.1f} GiB FP32 orbitals)")
+    B = min(args.block, wl.n_orb)
+    box = tuple(k * wl.h for k in wl.grid)
+    t = time.perf_counter()
+    ctx = G.Context(phi, eps, wl.n_occ, wl.grid, box, precision="mixed",
+                    poly_degree=wl.poly_degree, reorth="full", block=B)
+    del phi
+    log(f"large setup {time.perf_counter() - t:.1f}s, interval {ctx.interval}")
+    m0 = int(qp[0])
+    pairs = ([m0] * B, list(range(B)))
+    k = max(1, args.steps)
+
+    def run(L):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.lanczos_pairs(pairs[0], pairs[1], [L] * B)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    run(1)
+    t1 = run(1)
+    ctx.set_option(G.KEY_PROFILE, 1)
+    tk = run(1 + k)
+    prof = {kk: v for kk, v in ctx.profile_totals().items()}
+    ctx.set_option(G.KEY_PROFILE, 0)
+    per_step = (tk - t1) / k
+    log(f"large window: L=1 {t1:.2f}s, L={1 + k} {tk:.2f}s, {per_step:.3f}s per step")
+    per_vec_step = per_step / B
+    value = 1.0 / (per_vec_step * wl.n_lanczos * wl.n_orb)
+    flop_step = 4.0 * wl.n_r * wl.n_occ * wl.n_emp * wl.poly_degree * B
+    # accuracy: mixed vs FP64 on a sample of start vectors, short fractions
+    ns = list(np.linspace(0, wl.n_orb - 1, 4).astype(int))
+    acc_L = 2
+    a, b, n2, ol = ctx.lanczos_pairs([m0] * len(ns), ns, [acc_L] * len(ns))
+    s_mx = ctx.sigma_from_coeffs(ns, a, b, n2, ol, omega, wl.eta)
+    ctx.set_precision("fp64")
+    a, b, n2, ol = ctx.lanczos_pairs([m0] * len(ns), ns, [acc_L] * len(ns))
+    s_64 = ctx.sigma_from_coeffs(ns, a, b, n2, ol, omega, wl.eta)
+    ctx.close()
+    kern = {kk: round(ms / cnt, 3) for kk, (ms, cnt, _) in prof.items() if cnt}
+    gflop = 2.0 * wl.n_r * wl.n_occ * wl.n_emp * B
+    print(json.dumps({
+        "metric": "Sigma_c spectra/s, mixed, steady-state window extrapolated",
+        "unit": "spectra/s", "value": value, "n_gpus": 1, "higher_is_better": True,
+        "dtype": "f16/bf16", "data": "synthetic",
+        "config": {"workload": wl.name, "grid": list(wl.grid), "n_occ": wl.n_occ,
+                   "n_emp": wl.n_emp, "pair_dim": wl.n_vc, "orbitals": "FP32",
+                   "n_lanczos": wl.n_lanczos, "n_omega": wl.n_omega, "block": B,
+                   "window": f"{B} vectors, Lanczos runs of 1 and {1 + k} steps"},
+        "seconds_per_lanczos_step": round(per_step, 4),
+        "matvec_tflops": round(flop_step / per_step / 1e12, 1),
+        "kernel_ms_per_launch": kern,
+        "gemm_tflops": {kk: round(gflop / (v * 1e-3) / 1e12, 1) for kk, v in kern.items()
+                        if kk.startswith("gemm")},
+        "accuracy": {"max_abs_err_ev": float(np.max(np.abs(s_mx - s_64))),
+                     "max_abs_sigma_ev": float(np.max(np.abs(s_64))),
+                     "sample": f"{len(ns)} start vectors, L={acc_L}, mixed vs FP64 GPU"}}),
+          flush=True)
+
+
 def run_libref(args):
     """The two 16-bit GEMM kernels of one B-vector C-product against the
     vendor BLAS (torch.matmul, hipBLASLt) on the same shapes with plain
@@ -376,7 +452,8 @@ def run_libref(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--mode", choices=("headline", "uneven", "adjoint", "isdf", "libref"),
+    ap.add_argument("--mode", choices=("headline", "uneven", "adjoint", "isdf", "libref",
+                                       "large"),
                     default="headline")
     ap.add_argument("--pairs", type=int, default=256, help="uneven mode: pairs measured")
     ap.add_argument("--isdf-ratio", type=int, default=4, help="isdf mode: N_mu / N_orb")
@@ -406,6 +483,8 @@ def main():
         return run_isdf(args)
     if args.mode == "libref":
         return run_libref(args)
+    if args.mode == "large":
+        return run_large(args)
 
     import torch
     import gw_inputs as gi

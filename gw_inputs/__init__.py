@@ -145,16 +145,21 @@ def _lowpass(g: np.ndarray, grid, h: float, sigma: float) -> np.ndarray:
     return out
 
 
-def make_orbitals(wl: Workload) -> np.ndarray:
-    """Seeded orthonormal real orbitals, shape [N_orb, N_r], float64."""
+def make_orbitals(wl: Workload, dtype=np.float64, progress=None) -> np.ndarray:
+    """Seeded orthonormal real orbitals, shape [N_orb, N_r] (float64, or
+    rounded to dtype at the end).  progress(msg), if given, is called after
+    each of the long steps."""
+    say = progress or (lambda msg: None)
     rng = np.random.default_rng([wl.seed, 0])
     g = rng.standard_normal((wl.n_r, wl.n_orb))
+    say("orbitals: random matrix drawn")
     if wl.smooth_sigma > 0:
         g = _lowpass(g, wl.grid, wl.h, wl.smooth_sigma)
     q = _thin_q(g)
     del g
+    say("orbitals: orthonormalised")
     q /= np.sqrt(wl.dv)
-    return np.ascontiguousarray(q.T)
+    return q.T.astype(dtype, order="C")
 
 
 def _thin_q(g: np.ndarray) -> np.ndarray:

@@ -320,7 +320,8 @@ __device__ inline u4 scale8(u4 pv, f4v v0, f4v v1) {
 
 // A[(b,v)][r] = bf16(phi_v(r) V_b(r)).  NVP = padded N_v when it is 64 or
 // 128 (a thread's four rows then share one or two phi_v rows and use four or
-// two potentials), 0 otherwise.
+// two potentials), 256 when it is a multiple of 256 (a tile lies inside one
+// pair vector: four phi_v rows, one potential), 0 otherwise.
 template <int NVP>
 struct LoadPsiV16 {
   const bf16_t* psi_v_t;
@@ -328,7 +329,7 @@ struct LoadPsiV16 {
   long nrp;
   int nvp;
   static constexpr int NPV = NVP == 64 ? 1 : (NVP == 128 ? 2 : 4);
-  static constexpr int NB = NVP == 128 ? 2 : 4;
+  static constexpr int NB = NVP == 128 ? 2 : (NVP == 256 ? 1 : 4);
   struct Raw {
     u4 pv[NPV];
     f4v v[NB][2];
@@ -353,6 +354,14 @@ struct LoadPsiV16 {
         r.v[h][0] = *reinterpret_cast<const f4v*>(vp);
         r.v[h][1] = *reinterpret_cast<const f4v*>(vp + 4);
       }
+    } else if constexpr (NVP == 256) {
+      const int b = m0 / nvp, v0 = m0 - b * nvp + r0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        r.pv[q] = *reinterpret_cast<const u4*>(psi_v_t + (long)(v0 + 64 * q) * nrp + k);
+      const float* vp = vpot + (long)b * nrp + k;
+      r.v[0][0] = *reinterpret_cast<const f4v*>(vp);
+      r.v[0][1] = *reinterpret_cast<const f4v*>(vp + 4);
     } else {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -368,6 +377,7 @@ struct LoadPsiV16 {
   __device__ u4 finish(const Raw& r, int q) const {
     if constexpr (NVP == 64) return scale8(r.pv[0], r.v[q][0], r.v[q][1]);
     else if constexpr (NVP == 128) return scale8(r.pv[q & 1], r.v[q >> 1][0], r.v[q >> 1][1]);
+    else if constexpr (NVP == 256) return scale8(r.pv[q], r.v[0][0], r.v[0][1]);
     else return scale8(r.pv[q], r.v[q][0], r.v[q][1]);
   }
 };
@@ -777,10 +787,12 @@ void gemm2_bf16(const GemmDims& d, int nb, int bn, int splitk, const bf16_t* psi
   if (bn == 256) {
     if (d.nvp == 64) GWL_G2(256, 64);
     else if (d.nvp == 128) GWL_G2(256, 128);
+    else if (d.nvp % 256 == 0) GWL_G2(256, 256);
     else GWL_G2(256, 0);
   } else {
     if (d.nvp == 64) GWL_G2(128, 64);
     else if (d.nvp == 128) GWL_G2(128, 128);
+    else if (d.nvp % 256 == 0) GWL_G2(128, 256);
     else GWL_G2(128, 0);
   }
 #undef GWL_G2
