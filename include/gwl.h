@@ -346,13 +346,18 @@ enum {
                                    gwl_sigma_c_vjp returns GWL_EUNSUPPORTED while it is set. */
   GWL_KEY_ISDF = 29,            /* set/query: 1 = the K product on the ISDF points of the last
                                    gwl_isdf_setup (GWL_ESTATE before one), 0 = on the grid */
-  GWL_KEY_ISDF_NMU = 30         /* query: number of ISDF points set up, 0 if none */
+  GWL_KEY_ISDF_NMU = 30,        /* query: number of ISDF points set up, 0 if none */
+  GWL_KEY_TUNED_TILE = 31       /* query: second-GEMM block tile (128 or 256) chosen by the
+                                   autotuner with GWL_KEY_TUNED_BLOCK (the mixed product
+                                   picks it unless GWL_KEY_BF16_TILE was set), 0 before */
 };
 /* The autotuner runs on the first gwl_sigma_c / gwl_sigma_c_range /
  * gwl_lanczos_pairs call with block = 0: it times one C-product for
- * B in {32, 64, 128, 256} and three splits of the second GEMM.  If the
- * environment variable GWL_TUNE_CACHE names a file, choices are read from and
- * appended to it (text: "gfx950:N_r:N_v:N_c:precision:kernels B split us"). */
+ * B in {32, 64, 128, 256} and three splits of the second GEMM, and for the
+ * mixed product both block tiles of the second GEMM (unless
+ * GWL_KEY_BF16_TILE fixed one).  If the environment variable GWL_TUNE_CACHE
+ * names a file, choices are read from and appended to it (text lines
+ * "gfx950:N_r:N_v:N_c:precision:kernels:fixed_tile:n_mu B split tile us"). */
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* gwl_last_error(void);

@@ -134,6 +134,7 @@ struct gwl_ctx {
   int splitk = 0;  // 0 = automatic
   int fp64_kernel = 1;  // 0 = plain FMA tiles, 1 = MFMA (both precisions)
   int bf16_tile = 256;  // block tile width of the second BF16 MFMA GEMM
+  bool tile_fixed = false;  // set by the caller: the autotuner keeps it
   int tda = 0;          // 1: Tamm-Dancoff (Lanczos on A = Delta + K from (nm|vc))
   int quadrature = 0;   // 1: Lanczos on C + Gauss quadrature (no polynomial)
   bool poly_hi_auto = false;  // the interval's upper end is estimated (re-done for ISDF)
@@ -226,7 +227,7 @@ struct gwl_ctx {
 
   // autotuned (block, split) per precision
   struct Tune {
-    int B = 0, S = 0;
+    int B = 0, S = 0, tile = 0;
     double us_per_vec = 0;
   };
   Tune tuned[2];
@@ -608,7 +609,7 @@ struct gwl_ctx {
   std::string tune_key(int prec) const {
     return "gfx950:" + std::to_string(nr) + ":" + std::to_string(nv) + ":" +
            std::to_string(nc) + ":" + std::to_string(prec) + ":" + std::to_string(fp64_kernel) + ":" +
-           std::to_string(bf16_tile) + ":" + std::to_string(isdf_on ? n_mu : 0);
+           std::to_string(tile_fixed ? bf16_tile : 0) + ":" + std::to_string(isdf_on ? n_mu : 0);
   }
 
   bool tune_cache_read(int prec, Tune& t) const {
@@ -617,14 +618,15 @@ struct gwl_ctx {
     FILE* f = std::fopen(path, "r");
     if (!f) return false;
     char key[256];
-    int b = 0, sk = 0;
+    int b = 0, sk = 0, tile = 0;
     double us = 0;
     bool found = false;
     const std::string want = tune_key(prec);
-    while (std::fscanf(f, "%255s %d %d %lf", key, &b, &sk, &us) == 4)
-      if (want == key && b > 0 && sk > 0) {
+    while (std::fscanf(f, "%255s %d %d %d %lf", key, &b, &sk, &tile, &us) == 5)
+      if (want == key && b > 0 && sk > 0 && (tile == 128 || tile == 256)) {
         t.B = b;
         t.S = sk;
+        t.tile = tile;
         t.us_per_vec = us;
         found = true;
       }
@@ -637,42 +639,54 @@ struct gwl_ctx {
     if (!path || !*path) return;
     FILE* f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%s %d %d %.3f\n", tune_key(prec).c_str(), t.B, t.S, t.us_per_vec);
+    std::fprintf(f, "%s %d %d %d %.3f\n", tune_key(prec).c_str(), t.B, t.S, t.tile,
+                 t.us_per_vec);
     std::fclose(f);
   }
 
+  // The mixed product with the MFMA kernels also chooses the second GEMM's
+  // block tile (256 or 128 wide) unless the caller fixed it.
   Tune autotune(int prec, int bmax) {
     Tune best = tuned[prec];
     if (best.B > 0) return best;
+    const bool pick_tile = prec == GWL_MIXED_BF16 && fp64_kernel && !tile_fixed;
     if (tune_cache_read(prec, best)) {
+      if (pick_tile) set_tile(best.tile);
+      best.tile = bf16_tile;
       tuned[prec] = best;
       return best;
     }
     const int cands[] = {32, 64, 128, 256};
+    std::vector<int> tiles = {bf16_tile};
+    if (pick_tile) tiles = {256, 128};
     hipEvent_t e0, e1;
     GWL_HIP(hipEventCreate(&e0));
     GWL_HIP(hipEventCreate(&e1));
     best.us_per_vec = 1e300;
     try {
-      for (int B : cands) {
-        if (B > bmax && B != cands[0]) break;
-        ensure_work(B, 1, false);
-        const int s0 = heuristic_splitk(B, prec);
-        for (int S : {s0 / 2, s0, s0 * 2}) {
-          if (S < 1 || S > 32 || (S > 1 && (long)kd().nrp / S < 1024)) continue;
-          cast(B, q.p, prec);
-          k_product(B, prec, S);  // warm
-          GWL_HIP(hipEventRecord(e0, stream));
-          for (int r = 0; r < 2; ++r) k_product(B, prec, S);
-          GWL_HIP(hipEventRecord(e1, stream));
-          GWL_HIP(hipEventSynchronize(e1));
-          float ms = 0;
-          GWL_HIP(hipEventElapsedTime(&ms, e0, e1));
-          const double us = 1e3 * ms / 2 / B;
-          if (us < best.us_per_vec * 0.97) {
-            best.B = B;
-            best.S = S;
-            best.us_per_vec = us;
+      for (int tile : tiles) {
+        bf16_tile = tile;
+        for (int B : cands) {
+          if (B > bmax && B != cands[0]) break;
+          ensure_work(B, 1, false);
+          const int s0 = heuristic_splitk(B, prec);
+          for (int S : {s0 / 2, s0, s0 * 2}) {
+            if (S < 1 || S > 32 || (S > 1 && (long)kd().nrp / S < 1024)) continue;
+            cast(B, q.p, prec);
+            k_product(B, prec, S);  // warm
+            GWL_HIP(hipEventRecord(e0, stream));
+            for (int r = 0; r < 2; ++r) k_product(B, prec, S);
+            GWL_HIP(hipEventRecord(e1, stream));
+            GWL_HIP(hipEventSynchronize(e1));
+            float ms = 0;
+            GWL_HIP(hipEventElapsedTime(&ms, e0, e1));
+            const double us = 1e3 * ms / 2 / B;
+            if (us < best.us_per_vec * 0.97) {
+              best.B = B;
+              best.S = S;
+              best.tile = tile;
+              best.us_per_vec = us;
+            }
           }
         }
       }
@@ -684,13 +698,23 @@ struct gwl_ctx {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (best.B <= 0) {  // nothing timed: fall back to the memory rule and heuristic split
+      best.tile = tiles[0];
+      bf16_tile = best.tile;
       best.B = std::max(1, std::min(bmax, 128));
       best.S = heuristic_splitk(best.B, prec);
       best.us_per_vec = 0;
     }
+    set_tile(best.tile);
     tuned[prec] = best;
     tune_cache_write(prec, best);
     return best;
+  }
+
+  // second-GEMM block tile of the mixed product (a captured graph used the old one)
+  void set_tile(int tile) {
+    if (tile != 128 && tile != 256) return;
+    if (bf16_tile != tile) drop_graph();
+    bf16_tile = tile;
   }
 
   // ---------------------------------------------------------------- scheduler

@@ -368,8 +368,9 @@ gwl_status gwl_set_option(gwl_ctx* ctx, int key, double value) {
         break;
       case GWL_KEY_BF16_TILE:
         GWL_CHECK(value == 128 || value == 256, GWL_EINVAL, "BF16 tile must be 128 or 256");
-        if (ctx->bf16_tile != (int)value) {
+        if (ctx->bf16_tile != (int)value || !ctx->tile_fixed) {
           ctx->bf16_tile = (int)value;
+          ctx->tile_fixed = true;
           ctx->tuned[GWL_MIXED_BF16] = gwl_ctx::Tune{};
           ctx->drop_graph();
         }
@@ -414,6 +415,7 @@ gwl_status gwl_query(gwl_ctx* ctx, int key, double* out) {
       case GWL_KEY_GRAPHS: *out = ctx->use_graphs; break;
       case GWL_KEY_TUNED_BLOCK: *out = ctx->tuned[ctx->precision].B; break;
       case GWL_KEY_TUNED_SPLITK: *out = ctx->tuned[ctx->precision].S; break;
+      case GWL_KEY_TUNED_TILE: *out = ctx->tuned[ctx->precision].tile; break;
       case GWL_KEY_PROF_MS_GEMM1: *out = ctx->prof_ms[0]; break;
       case GWL_KEY_PROF_N_GEMM1: *out = (double)ctx->prof_n[0]; break;
       case GWL_KEY_PROF_VEC_GEMM1: *out = (double)ctx->prof_vec[0]; break;

@@ -477,6 +477,28 @@ def test_graph_replay_matches_eager(small):
             assert np.array_equal(a, b)
 
 
+def test_autotuner_mixed_tile(small):
+    """The mixed product's tuner also picks the second GEMM's tile; a tile set
+    by the caller is kept."""
+    import paper_2310_20103_amd as G
+    _say("autotuner, mixed tile")
+    wl = small.wl
+    ctx = make_ctx(small.sys, precision="mixed", interval=(small.lo, small.hi), block=0)
+    try:
+        got = ctx.sigma_c(small.sys.qp_states[:1], small.sys.omega_ev, wl.eta, 8)
+        assert ctx.query(G.KEY_TUNED_TILE) in (128, 256)
+        assert ctx.query(G.KEY_BF16_TILE) == ctx.query(G.KEY_TUNED_TILE)
+        ctx.set_option(G.KEY_BF16_TILE, 128)
+        got128 = ctx.sigma_c(small.sys.qp_states[:1], small.sys.omega_ev, wl.eta, 8)
+        assert ctx.query(G.KEY_TUNED_TILE) == 128 and ctx.query(G.KEY_BF16_TILE) == 128
+    finally:
+        ctx.close()
+    ref = small.pr.sigma_lanczos(int(small.sys.qp_states[0]), small.sys.omega_ev, wl.eta, 8,
+                                 small.lo, small.hi, wl.poly_degree)
+    assert np.max(np.abs(got[0] - ref)) <= 1e-3
+    assert np.max(np.abs(got128[0] - ref)) <= 1e-3
+
+
 def test_autotuner_choice(small, ctx_small):
     import paper_2310_20103_amd as G
     _say("autotuner")
@@ -484,3 +506,4 @@ def test_autotuner_choice(small, ctx_small):
     ctx_small.sigma_c(small.sys.qp_states[:1], small.sys.omega_ev[:4], wl.eta, 2)
     assert ctx_small.query(G.KEY_TUNED_BLOCK) in (32, 64, 128, 256)
     assert 1 <= ctx_small.query(G.KEY_TUNED_SPLITK) <= 32
+    assert ctx_small.query(G.KEY_TUNED_TILE) in (128, 256)
