@@ -134,6 +134,24 @@ def test_kmeans_points_match_oracle(request, which):
     assert np.array_equal(got, ref)
 
 
+def test_kmeans_many_centroids():
+    """More centroids than one LDS chunk of the assignment kernel (1024):
+    1100 centroids on a 16^3 grid, bit for bit against the oracle."""
+    import paper_2310_20103_amd as G
+    _say("isdf kmeans, 1100 centroids on 16^3")
+    wl = gi.workload("grid24_v8c32", name="km1100", seed=41, grid=(16, 16, 16), box=8.0,
+                     n_occ=4, n_emp=12, smooth_sigma=1.0)
+    s = gi.make_system(wl)
+    box = tuple(n * wl.h for n in wl.grid)
+    spacing = tuple(b / n for b, n in zip(box, wl.grid))
+    init = gi.random_grid_points(1100, wl.n_r, seed=42)
+    ref, ref_n = I.kmeans_points(I.kmeans_weights(s.phi, wl.n_occ), wl.grid, spacing, init, 10)
+    with G.Context(s.phi, s.energies_ev, wl.n_occ, wl.grid, box) as ctx:
+        got, got_n = ctx.isdf_kmeans(init, 10)
+    assert got_n == ref_n
+    assert np.array_equal(got, ref)
+
+
 def test_kmeans_edges(smooth):
     """Repeated initial centroids leave clusters empty (fewer points), a
     single assignment pass at max_iter = 0, and bad arguments are errors."""
