@@ -180,7 +180,26 @@ def run_adjoint(args):
     t = time.perf_counter()
     ctx.sigma_c(m, omega, wl.eta, wl.n_lanczos)
     t_full = time.perf_counter() - t
+    lo, hi = ctx.interval
     ctx.close()
+    # central differences of the same forward (FP64, no reorthogonalisation,
+    # the interval held fixed) along seeded random directions, step 1e-5
+    h = 1e-5
+
+    def loss(e, p):
+        with G.Context(p, e, wl.n_occ, wl.grid, box, precision="fp64",
+                       poly_degree=wl.poly_degree, poly_lo=lo, poly_hi=hi, reorth="none",
+                       block=args.block) as c:
+            return float(np.sum((np.conj(cot) * c.sigma_c(m, omega, wl.eta, wl.n_lanczos)).real))
+
+    de = rng.standard_normal(wl.n_orb)
+    dp = rng.standard_normal(phi.shape) * float(np.mean(np.abs(phi)))
+    fd_e = (loss(eps + h * de, phi) - loss(eps - h * de, phi)) / (2 * h)
+    log("adjoint: energy direction done")
+    fd_p = (loss(eps, phi + h * dp) - loss(eps, phi - h * dp)) / (2 * h)
+    log("adjoint: orbital direction done")
+    an_e = float(ge @ de)
+    an_p = float(np.sum(go.cpu().numpy() * dp))
     print(json.dumps({
         "metric": "Sigma_c vector-Jacobian product time / forward time, FP64", "unit": "ratio",
         "value": round(t_vjp / t_fwd, 3), "n_gpus": 1, "higher_is_better": False,
@@ -190,6 +209,10 @@ def run_adjoint(args):
         "forward_s": round(t_fwd, 3), "vjp_s_incl_forward": round(t_vjp, 3),
         "forward_full_reorth_s": round(t_full, 3),
         "vjp_sigma_vs_forward_rel": same,
+        "fd_check": {"step": h, "energies": {"fd": fd_e, "vjp": an_e,
+                                             "rel": abs(fd_e - an_e) / max(abs(fd_e), 1e-300)},
+                     "orbitals": {"fd": fd_p, "vjp": an_p,
+                                  "rel": abs(fd_p - an_p) / max(abs(fd_p), 1e-300)}},
         "grad_norms": {"energies": float(np.linalg.norm(ge)),
                        "orbitals": float(torch.linalg.norm(go).item())}}), flush=True)
 
