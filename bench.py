@@ -121,7 +121,10 @@ def run_uneven(args):
     ctx = G.Context(sysm.phi, sysm.energies_ev, wl.n_occ, wl.grid, box, precision="mixed",
                     poly_degree=wl.poly_degree, reorth="full")
     runs = []
-    for B, graphs in ((32, 1), (64, 1), (128, 1), (256, 1), (128, 0)):
+    cases = ((32, 1), (64, 1), (128, 1), (256, 1), (128, 0))
+    if args.uneven_blocks:
+        cases = tuple((int(b), 1) for b in args.uneven_blocks.split(","))
+    for B, graphs in cases:
         ctx.set_block(B)
         ctx.set_option(G.KEY_GRAPHS, graphs)
         ctx.lanczos_pairs(m[:B], n[:B], [1] * min(B, P))
@@ -479,6 +482,9 @@ def main():
                                        "large"),
                     default="headline")
     ap.add_argument("--pairs", type=int, default=256, help="uneven mode: pairs measured")
+    ap.add_argument("--uneven-blocks", default="",
+                    help="uneven mode: comma-separated block sizes (default: 32,64,128,256 "
+                         "with graphs and 128 without)")
     ap.add_argument("--isdf-ratio", type=int, default=4, help="isdf mode: N_mu / N_orb")
     ap.add_argument("--isdf-points", choices=("kmeans", "random"), default="kmeans",
                     help="isdf mode: interpolation points (K-means or the random start)")
