@@ -90,6 +90,28 @@ def test_sigma_fp64_mixed_refused(smooth):
         assert relerr(got64[i], ref) <= 1e-8
 
 
+def test_isdf_with_quadrature_and_offdiag(smooth):
+    """The ISDF product under the other Sigma routes: Lanczos on C with Gauss
+    quadrature, and the off-diagonal element, against the oracle on the same
+    ISDF operator (FP64 <= 1e-8 relative)."""
+    from oracle import offdiag as O
+    from oracle import quadrature as Q
+    _say("isdf + quadrature, isdf + off-diagonal")
+    wl = smooth.wl
+    m, m2 = int(smooth.sys.qp_states[0]), int(smooth.sys.qp_states[-1])
+    om = smooth.sys.omega_ev
+    with make_ctx(smooth) as ctx:
+        off = ctx.sigma_c_offdiag(m, m2, om, wl.eta, 10)
+        ctx.set_quadrature(True)
+        quad = ctx.sigma_c([m], om, wl.eta, 20)[0]
+    ref_off = O.sigma_lanczos_offdiag(smooth.pr, m, m2, om, wl.eta, 10, smooth.lo, smooth.hi,
+                                      wl.poly_degree)
+    ref_quad = Q.sigma_quadrature(smooth.pr, m, om, wl.eta, 20)
+    assert np.max(np.abs(ref_off)) > 1e-3 and np.max(np.abs(ref_quad)) > 0.1
+    assert relerr(off, ref_off) <= 1e-8
+    assert relerr(quad, ref_quad) <= 1e-8
+
+
 def test_switch_off_and_errors(smooth):
     import paper_2310_20103_amd as G
     _say("isdf off / errors")
