@@ -365,6 +365,17 @@ def run_large(args):
         return time.perf_counter() - t0
 
     run(1)
+    if args.large_splits:
+        # second-GEMM split sweep: one profiled 2-step window per split
+        for sk in (int(x) for x in args.large_splits.split(",")):
+            ctx.set_option(G.KEY_GEMM_SPLITK, sk)
+            run(1)
+            ctx.set_option(G.KEY_PROFILE, 1)
+            run(2)
+            tot = ctx.profile_totals()
+            ctx.set_option(G.KEY_PROFILE, 0)
+            log(f"large split {sk}: gemm2 {tot['gemm2'][0] / tot['gemm2'][1]:.1f} ms per launch")
+        ctx.set_option(G.KEY_GEMM_SPLITK, 0)
     t1 = run(1)
     ctx.set_option(G.KEY_PROFILE, 1)
     tk = run(1 + k)
@@ -482,6 +493,8 @@ def main():
                                        "large"),
                     default="headline")
     ap.add_argument("--pairs", type=int, default=256, help="uneven mode: pairs measured")
+    ap.add_argument("--large-splits", default="",
+                    help="large mode: comma-separated second-GEMM splits to time first")
     ap.add_argument("--uneven-blocks", default="",
                     help="uneven mode: comma-separated block sizes (default: 32,64,128,256 "
                          "with graphs and 128 without)")
