@@ -168,6 +168,8 @@ def run_adjoint(args):
     ctx = G.Context(phi, eps, wl.n_occ, wl.grid, box, precision="fp64",
                     poly_degree=wl.poly_degree, reorth="none", block=args.block)
     ctx.lanczos_pairs([m[0]] * 2, [0, 1], [1, 1])
+    if args.adjoint_checkpoints:
+        ctx.set_option(G.KEY_ADJOINT_STORE, 0)
     torch.cuda.synchronize()
     t = time.perf_counter()
     sig = ctx.sigma_c(m, omega, wl.eta, wl.n_lanczos)
@@ -177,7 +179,8 @@ def run_adjoint(args):
     sig2, ge, go = ctx.sigma_c_vjp(m, omega, wl.eta, wl.n_lanczos, cot)
     torch.cuda.synchronize()
     t_vjp = time.perf_counter() - t
-    log(f"adjoint: vjp {t_vjp:.1f}s")
+    iterates = "stored" if ctx.query(G.KEY_ADJOINT_STORED) == 1 else "recomputed"
+    log(f"adjoint: vjp {t_vjp:.1f}s, iterates {iterates}")
     same = float(np.max(np.abs(sig2 - sig)) / max(np.max(np.abs(sig)), 1e-300))
     ctx.set_reorth("full")
     t = time.perf_counter()
@@ -208,7 +211,8 @@ def run_adjoint(args):
         "value": round(t_vjp / t_fwd, 3), "n_gpus": 1, "higher_is_better": False,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": wl.name, "qp_states": 1, "start_vectors": wl.n_orb,
-                   "n_lanczos": wl.n_lanczos, "n_omega": wl.n_omega, "block": args.block},
+                   "n_lanczos": wl.n_lanczos, "n_omega": wl.n_omega, "block": args.block,
+                   "iterates": iterates},
         "forward_s": round(t_fwd, 3), "vjp_s_incl_forward": round(t_vjp, 3),
         "forward_full_reorth_s": round(t_full, 3),
         "vjp_sigma_vs_forward_rel": same,
@@ -493,6 +497,8 @@ def main():
                                        "large"),
                     default="headline")
     ap.add_argument("--pairs", type=int, default=256, help="uneven mode: pairs measured")
+    ap.add_argument("--adjoint-checkpoints", action="store_true",
+                    help="adjoint mode: recompute the iterates from checkpoints")
     ap.add_argument("--large-splits", default="",
                     help="large mode: comma-separated second-GEMM splits to time first")
     ap.add_argument("--uneven-blocks", default="",

@@ -185,8 +185,12 @@ gwl_status gwl_sigma_from_coeffs(gwl_ctx* ctx, const int* n_idx, int n_pairs,
  *   sigma_out      host [n_qp][n_omega][2] or NULL: the forward Sigma (eV).
  * The forward is the path of gwl_sigma_c in FP64 with the three-term
  * recurrence only (no reorthogonalisation, so the Lanczos vectors can be
- * recomputed exactly from checkpoints every ceil(sqrt(L)) steps instead of
- * being stored); the derivative is exact for that forward.  Orbitals are free
+ * recomputed exactly); the derivative is exact for that forward.  The
+ * backward needs, per step k, q_k, p_g(C) q_k and the Chebyshev iterates of
+ * that product: kept from the forward when they fit (GWL_KEY_ADJOINT_STORE,
+ * GWL_ADJOINT_STORE_MAX), otherwise recomputed from checkpoints of
+ * (q_{k-1}, q_k) every ceil(sqrt(L)) steps, which costs two more p_g(C)
+ * products per step.  Orbitals are free
  * variables (no orthonormality constraint), occupations and the Chebyshev
  * interval [lo, hi] are held fixed.  Holds a dense N_vc x N_vc coupling
  * cotangent and the N_vc pair potentials (GWL_EUNSUPPORTED when too large);
@@ -347,10 +351,22 @@ enum {
   GWL_KEY_ISDF = 29,            /* set/query: 1 = the K product on the ISDF points of the last
                                    gwl_isdf_setup (GWL_ESTATE before one), 0 = on the grid */
   GWL_KEY_ISDF_NMU = 30,        /* query: number of ISDF points set up, 0 if none */
-  GWL_KEY_TUNED_TILE = 31       /* query: second-GEMM block tile (128 or 256) chosen by the
+  GWL_KEY_TUNED_TILE = 31,      /* query: second-GEMM block tile (128 or 256) chosen by the
                                    autotuner with GWL_KEY_TUNED_BLOCK (the mixed product
                                    picks it unless GWL_KEY_BF16_TILE was set), 0 before */
+  GWL_KEY_ADJOINT_STORE = 32,   /* set/query: 1 (default) = gwl_sigma_c_vjp keeps every
+                                   Lanczos step's Chebyshev iterates from its forward when
+                                   they fit in GWL_ADJOINT_STORE_MAX bytes; 0 = always
+                                   recompute them from checkpoints.  Both give bitwise the
+                                   same results. */
+  GWL_KEY_ADJOINT_STORED = 33   /* query: 1 if the last gwl_sigma_c_vjp call kept the
+                                   iterates, 0 if it recomputed them, -1 before a call */
 };
+
+/* Device-memory cap for the iterates kept by gwl_sigma_c_vjp: per Lanczos step
+ * 2g + 2 vectors of B x N_vc doubles (the iterates t_0..t_g, their coupling
+ * parts K Delta^1/2 t_j for j < g, and p_g(C) q_k). */
+#define GWL_ADJOINT_STORE_MAX (32ull << 30)
 /* The autotuner runs on the first gwl_sigma_c / gwl_sigma_c_range /
  * gwl_lanczos_pairs call with block = 0: it times one C-product for
  * B in {32, 64, 128, 256} and three splits of the second GEMM, and for the

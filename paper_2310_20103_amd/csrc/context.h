@@ -137,6 +137,8 @@ struct gwl_ctx {
   bool tile_fixed = false;  // set by the caller: the autotuner keeps it
   int tda = 0;          // 1: Tamm-Dancoff (Lanczos on A = Delta + K from (nm|vc))
   int quadrature = 0;   // 1: Lanczos on C + Gauss quadrature (no polynomial)
+  int adjoint_store = 1;     // 1: the adjoint keeps the forward's iterates when they fit
+  int adjoint_stored = -1;   // what the last adjoint call did (-1: no call yet)
   bool poly_hi_auto = false;  // the interval's upper end is estimated (re-done for ISDF)
 
   // ISDF of the pair densities: the K product runs on N_mu interpolation

@@ -362,6 +362,10 @@ gwl_status gwl_set_option(gwl_ctx* ctx, int key, double value) {
         GWL_CHECK(value == 0 || value == 1, GWL_EINVAL, "quadrature must be 0 or 1");
         ctx->quadrature = (int)value;
         break;
+      case GWL_KEY_ADJOINT_STORE:
+        GWL_CHECK(value == 0 || value == 1, GWL_EINVAL, "adjoint_store must be 0 or 1");
+        ctx->adjoint_store = (int)value;
+        break;
       case GWL_KEY_ISDF:
         GWL_CHECK(value == 0 || value == 1, GWL_EINVAL, "isdf must be 0 or 1");
         ctx->set_isdf((int)value);
@@ -409,6 +413,8 @@ gwl_status gwl_query(gwl_ctx* ctx, int key, double* out) {
       case GWL_KEY_BF16_TILE: *out = ctx->bf16_tile; break;
       case GWL_KEY_TDA: *out = ctx->tda; break;
       case GWL_KEY_QUADRATURE: *out = ctx->quadrature; break;
+      case GWL_KEY_ADJOINT_STORE: *out = ctx->adjoint_store; break;
+      case GWL_KEY_ADJOINT_STORED: *out = ctx->adjoint_stored; break;
       case GWL_KEY_ISDF: *out = ctx->isdf_on; break;
       case GWL_KEY_ISDF_NMU: *out = ctx->isdf_ready ? ctx->n_mu : 0; break;
       case GWL_KEY_PROFILE: *out = ctx->profile; break;

@@ -1,13 +1,17 @@
 // Vector-Jacobian product of Sigma_c (gwl_sigma_c_vjp).
 //
 // Forward: the same path as gwl_sigma_c in FP64 without reorthogonalisation
-// (so the recurrence can be recomputed exactly), checkpointing (q_{k-1}, q_k)
-// and the slot state every ceil(sqrt(L)) steps.  Backward, per block of start
-// vectors: continued-fraction adjoint; then segment by segment (last first)
-// the Lanczos vectors of the segment are recomputed from its checkpoint, and
-// for each step k (last first) the p_g(C) product of q_k is recomputed with
-// its Chebyshev iterates t_j and coupling parts K Delta^1/2 t_j kept, the
-// reverse Lanczos step gives w_bar_k, and the reverse Chebyshev recurrence
+// (so the recurrence can be recomputed exactly).  When they fit in
+// GWL_ADJOINT_STORE_MAX, every step's Chebyshev iterates t_j (t_0 = q_k),
+// coupling parts K Delta^1/2 t_j and w_k = p_g(C) q_k are kept from the
+// forward; otherwise the forward checkpoints (q_{k-1}, q_k) and the slot state
+// every ceil(sqrt(L)) steps, and the backward recomputes, segment by segment
+// (last first), the Lanczos vectors from the checkpoint and then, per step,
+// the product with its iterates (two more p_g(C) products per step; the same
+// kernels in the same order, so both routes agree bitwise).  Backward, per
+// block of start vectors: continued-fraction adjoint; then for each step k
+// (last first) the reverse Lanczos step gives w_bar_k, and the reverse
+// Chebyshev recurrence
 // applied to w_bar_k gives D w_bar_k (added to q_bar_k) together with the
 // outer products s_j t_{j-1}^T that make up C_bar.  C_bar is pushed into
 // Delta_bar directly and into a dense K_bar; the coupling vectors' adjoint
@@ -110,19 +114,31 @@ extern "C" gwl_status gwl_sigma_c_vjp(gwl_ctx* ctx, const int* qp_states, int n_
     DevBuf<double> ck_amax, ck_bprev;
     DevBuf<unsigned char> tscr;
     Pb.ensure(vec);
-    ckq.ensure((size_t)nseg * vec);
-    ckqp.ensure((size_t)nseg * vec);
-    ck_state.ensure((size_t)nseg * 2 * B);
-    ck_amax.ensure((size_t)nseg * B);
-    ck_bprev.ensure((size_t)nseg * B);
-    segq.ensure((size_t)(seg + 1) * vec);
-    T.ensure((size_t)(g + 1) * vec);
-    KT.ensure((size_t)g * vec);
+    // kept iterates per step k: t_0..t_g, K~t_0..K~t_{g-1}, w_k; then q_L and q_{-1}
+    const size_t per_step = (size_t)(2 * g + 2) * vec;
+    const bool store = c.adjoint_store &&
+                       ((size_t)L * per_step + 2 * vec) * sizeof(double) <= GWL_ADJOINT_STORE_MAX;
+    DevBuf<double> It;
+    c.adjoint_stored = store ? 1 : 0;
+    if (store) {
+      It.ensure((size_t)L * per_step + 2 * vec);
+    } else {
+      ckq.ensure((size_t)nseg * vec);
+      ckqp.ensure((size_t)nseg * vec);
+      ck_state.ensure((size_t)nseg * 2 * B);
+      ck_amax.ensure((size_t)nseg * B);
+      ck_bprev.ensure((size_t)nseg * B);
+      segq.ensure((size_t)(seg + 1) * vec);
+      T.ensure((size_t)(g + 1) * vec);
+      KT.ensure((size_t)g * vec);
+      wk.ensure(vec);
+    }
+    double* const q_last = store ? It.p + (size_t)L * per_step : nullptr;
+    double* const q_m1 = store ? q_last + vec : nullptr;
     Sv.ensure((size_t)(g + 1) * vec);
     KS.ensure((size_t)(g + 1) * vec);
     U.ensure((size_t)g * vec);
     V.ensure((size_t)g * vec);
-    wk.ensure(vec);
     wbar.ensure(vec);
     qb0.ensure(vec);
     qb1.ensure(vec);
@@ -182,6 +198,31 @@ extern "C" gwl_status gwl_sigma_c_vjp(gwl_ctx* ctx, const int* qp_states, int n_
       lz_alpha(ss, B, c.q.p, c.qprev.p, c.w.p, nvc, st);
       lz_beta(ss, B, c.q.p, c.qprev.p, c.w.p, nullptr, 0, 0, nvc, st);
     };
+    // w = p_g(C) t_0 for the vectors t_0 = Ti[0], keeping the iterates
+    // t_1..t_g in Ti[1..g] and K~t_j = K Delta^1/2 t_j in KTi[0..g-1]
+    // (the same launches as Context::apply_d_batch, plus the K~t_j output)
+    auto cheb_iterates = [&](double* Ti, double* KTi, double* w) {
+      c.cast(B, Ti, GWL_FP64);
+      for (int j = 0; j < g; ++j) {
+        c.k_product(B, GWL_FP64, S);
+        combine<double, double>(pg, B, S, reinterpret_cast<const double*>(c.ypart.p),
+                                Ti + (size_t)j * vec, j > 0 ? Ti + (size_t)(j - 1) * vec : nullptr,
+                                Ti + (size_t)(j + 1) * vec, w, j == 0 ? 1 : 2, lo, hi,
+                                c.cheb[0], c.cheb[j + 1], j + 1 < g ? c.u64.p : nullptr, st,
+                                KTi + (size_t)j * vec);
+      }
+    };
+    // one forward step that keeps its iterates (store route)
+    auto fwd_step_store = [&](int k) {
+      double* Ti = It.p + (size_t)k * per_step;
+      double* KTi = Ti + (size_t)(g + 1) * vec;
+      double* Wi = Ti + (size_t)(2 * g + 1) * vec;
+      GWL_HIP(hipMemcpyAsync(Ti, c.q.p, vec * 8, hipMemcpyDeviceToDevice, st));
+      cheb_iterates(Ti, KTi, Wi);
+      GWL_HIP(hipMemcpyAsync(c.w.p, Wi, vec * 8, hipMemcpyDeviceToDevice, st));
+      lz_alpha(ss, B, c.q.p, c.qprev.p, c.w.p, nvc, st);
+      lz_beta(ss, B, c.q.p, c.qprev.p, c.w.p, nullptr, 0, 0, nvc, st);
+    };
     auto save_state = [&](int sgi) {
       GWL_HIP(hipMemcpyAsync(ckq.p + (size_t)sgi * vec, c.q.p, vec * 8, hipMemcpyDeviceToDevice, st));
       GWL_HIP(hipMemcpyAsync(ckqp.p + (size_t)sgi * vec, c.qprev.p, vec * 8, hipMemcpyDeviceToDevice, st));
@@ -218,9 +259,15 @@ extern "C" gwl_status gwl_sigma_c_vjp(gwl_ctx* ctx, const int* qp_states, int n_
       c.coupling_batch(nbk, m.data() + p0, n.data() + p0, c.q.p, nvc);
       GWL_HIP(hipMemcpyAsync(Pb.p, c.q.p, vec * 8, hipMemcpyDeviceToDevice, st));
       lz_start(ss, B, c.s_slots.p, nbk, c.q.p, c.qprev.p, nullptr, 0, nvc, st);
-      for (int k = 0; k < L; ++k) {
-        if (k % seg == 0) save_state(k / seg);
-        fwd_step();
+      if (store) {
+        GWL_HIP(hipMemcpyAsync(q_m1, c.qprev.p, vec * 8, hipMemcpyDeviceToDevice, st));
+        for (int k = 0; k < L; ++k) fwd_step_store(k);
+        GWL_HIP(hipMemcpyAsync(q_last, c.q.p, vec * 8, hipMemcpyDeviceToDevice, st));
+      } else {
+        for (int k = 0; k < L; ++k) {
+          if (k % seg == 0) save_state(k / seg);
+          fwd_step();
+        }
       }
       // final lengths (the segment recompute below rewrites out_len step by step)
       GWL_HIP(hipMemcpyAsync(flen.p + p0, c.out_len.p + p0, nbk * 4, hipMemcpyDeviceToDevice, st));
@@ -239,66 +286,73 @@ extern "C" gwl_status gwl_sigma_c_vjp(gwl_ctx* ctx, const int* qp_states, int n_
       GWL_HIP(hipMemsetAsync(qbp, 0, vec * 8, st));
       GWL_HIP(hipMemsetAsync(pend.p, 0, B * 8, st));
       GWL_HIP(hipMemsetAsync(dbar.p, 0, vec * 8, st));
-      for (int sgi = nseg - 1; sgi >= 0; --sgi) {
-        const int k0 = sgi * seg, k1 = std::min(L, k0 + seg);
-        load_state(sgi);
-        GWL_HIP(hipMemcpyAsync(segq.p, c.q.p, vec * 8, hipMemcpyDeviceToDevice, st));
-        for (int k = k0; k < k1; ++k) {
-          fwd_step();
-          GWL_HIP(hipMemcpyAsync(segq.p + (size_t)(k - k0 + 1) * vec, c.q.p, vec * 8,
-                                 hipMemcpyDeviceToDevice, st));
+      // backward step k from q_{k+1}, q_k, q_{k-1}, w_k and the iterates of p_g(C) q_k
+      auto reverse_step = [&](int k, const double* qn, const double* qk, const double* qpv,
+                              const double* Ti, const double* KTi, const double* Wi) {
+        // reverse Lanczos step k
+        adj_lanczos_step(k, B, slot_pair.p, flen.p, L, c.coef_a.p, c.coef_b.p, abar.p,
+                         bbar.p, qn, qk, qpv, Wi, qbn, qbc, qbp, wbar.p, pend.p, nvc, st);
+        // reverse Chebyshev recurrence on x = w_bar_k
+        adj_scale_copy(Sv.p + (size_t)g * vec, wbar.p, c.cheb[g], (long)vec, st);
+        c.cast(B, Sv.p + (size_t)g * vec, GWL_FP64);
+        for (int j = g; j >= 1; --j) {
+          c.k_product(B, GWL_FP64, S);
+          adj_combine(pg, B, S, reinterpret_cast<const double*>(c.ypart.p),
+                      Sv.p + (size_t)j * vec, j < g ? Sv.p + (size_t)(j + 1) * vec : nullptr,
+                      wbar.p, c.cheb[j - 1], j >= 2 ? 2.0 : 1.0, lo, hi,
+                      Sv.p + (size_t)(j - 1) * vec, KS.p + (size_t)j * vec,
+                      j - 1 >= 1 ? c.u64.p : nullptr, st);
         }
-        const double* qprev0 = ckqp.p + (size_t)sgi * vec;
-        for (int k = k1 - 1; k >= k0; --k) {
-          const double* qk = segq.p + (size_t)(k - k0) * vec;
-          const double* qn = segq.p + (size_t)(k - k0 + 1) * vec;
-          const double* qpv = k > k0 ? segq.p + (size_t)(k - k0 - 1) * vec : qprev0;
-          // recompute w_k = p_g(C) q_k keeping t_0..t_{g-1} and K Delta^1/2 t_j
-          GWL_HIP(hipMemcpyAsync(T.p, qk, vec * 8, hipMemcpyDeviceToDevice, st));
-          c.cast(B, T.p, GWL_FP64);
-          for (int j = 0; j < g; ++j) {
-            c.k_product(B, GWL_FP64, S);
-            combine<double, double>(pg, B, S, reinterpret_cast<const double*>(c.ypart.p),
-                                    T.p + (size_t)j * vec, j > 0 ? T.p + (size_t)(j - 1) * vec : nullptr,
-                                    T.p + (size_t)(j + 1) * vec, wk.p, j == 0 ? 1 : 2, lo, hi,
-                                    c.cheb[0], c.cheb[j + 1], j + 1 < g ? c.u64.p : nullptr, st,
-                                    KT.p + (size_t)j * vec);
+        // C_bar = (2/(hi-lo)) [sum_{j>=2} 2 s_j t_{j-1}^T + s_1 t_0^T]
+        for (int j = 1; j <= g; ++j) {
+          const double alpha = (2.0 / (hi - lo)) * (j >= 2 ? 2.0 : 1.0);
+          adj_dbar_uv(pg, B, Sv.p + (size_t)j * vec, KS.p + (size_t)j * vec,
+                      Ti + (size_t)(j - 1) * vec, KTi + (size_t)(j - 1) * vec, alpha,
+                      2.0 * alpha, dbar.p, U.p + (size_t)(j - 1) * vec,
+                      V.p + (size_t)(j - 1) * vec, st);
+        }
+        // K_bar += sum_rows U^T V  (column-major view: Kbar += V_cm U_cm^T)
+        GWL_BLAS(rocblas_dgemm(blas.h, rocblas_operation_none, rocblas_operation_transpose,
+                               (rocblas_int)nvc, (rocblas_int)nvc, (rocblas_int)(g * B), &one,
+                               V.p, (rocblas_int)nvc, U.p, (rocblas_int)nvc, &one, Kbar.p,
+                               (rocblas_int)nvc));
+        // q_bar_k += D w_bar_k
+        adj_axpy(qbc, Sv.p, 1.0, (long)vec, st);
+        // rotate: q_bar_{k+1} <- q_bar_k <- q_bar_{k-1} <- 0
+        double* t = qbn;
+        qbn = qbc;
+        qbc = qbp;
+        qbp = t;
+        GWL_HIP(hipMemsetAsync(qbp, 0, vec * 8, st));
+      };
+      if (store) {
+        for (int k = L - 1; k >= 0; --k) {
+          const double* Ti = It.p + (size_t)k * per_step;
+          const double* qn = k + 1 < L ? Ti + per_step : q_last;
+          const double* qpv = k > 0 ? Ti - per_step : q_m1;
+          reverse_step(k, qn, Ti, qpv, Ti, Ti + (size_t)(g + 1) * vec,
+                       Ti + (size_t)(2 * g + 1) * vec);
+        }
+      } else {
+        for (int sgi = nseg - 1; sgi >= 0; --sgi) {
+          const int k0 = sgi * seg, k1 = std::min(L, k0 + seg);
+          load_state(sgi);
+          GWL_HIP(hipMemcpyAsync(segq.p, c.q.p, vec * 8, hipMemcpyDeviceToDevice, st));
+          for (int k = k0; k < k1; ++k) {
+            fwd_step();
+            GWL_HIP(hipMemcpyAsync(segq.p + (size_t)(k - k0 + 1) * vec, c.q.p, vec * 8,
+                                   hipMemcpyDeviceToDevice, st));
           }
-          // reverse Lanczos step k
-          adj_lanczos_step(k, B, slot_pair.p, flen.p, L, c.coef_a.p, c.coef_b.p, abar.p,
-                           bbar.p, qn, qk, qpv, wk.p, qbn, qbc, qbp, wbar.p, pend.p, nvc, st);
-          // reverse Chebyshev recurrence on x = w_bar_k
-          adj_scale_copy(Sv.p + (size_t)g * vec, wbar.p, c.cheb[g], (long)vec, st);
-          c.cast(B, Sv.p + (size_t)g * vec, GWL_FP64);
-          for (int j = g; j >= 1; --j) {
-            c.k_product(B, GWL_FP64, S);
-            adj_combine(pg, B, S, reinterpret_cast<const double*>(c.ypart.p),
-                        Sv.p + (size_t)j * vec, j < g ? Sv.p + (size_t)(j + 1) * vec : nullptr,
-                        wbar.p, c.cheb[j - 1], j >= 2 ? 2.0 : 1.0, lo, hi,
-                        Sv.p + (size_t)(j - 1) * vec, KS.p + (size_t)j * vec,
-                        j - 1 >= 1 ? c.u64.p : nullptr, st);
+          const double* qprev0 = ckqp.p + (size_t)sgi * vec;
+          for (int k = k1 - 1; k >= k0; --k) {
+            const double* qk = segq.p + (size_t)(k - k0) * vec;
+            const double* qn = segq.p + (size_t)(k - k0 + 1) * vec;
+            const double* qpv = k > k0 ? segq.p + (size_t)(k - k0 - 1) * vec : qprev0;
+            // recompute w_k = p_g(C) q_k keeping t_0..t_{g-1} and K Delta^1/2 t_j
+            GWL_HIP(hipMemcpyAsync(T.p, qk, vec * 8, hipMemcpyDeviceToDevice, st));
+            cheb_iterates(T.p, KT.p, wk.p);
+            reverse_step(k, qn, qk, qpv, T.p, KT.p, wk.p);
           }
-          // C_bar = (2/(hi-lo)) [sum_{j>=2} 2 s_j t_{j-1}^T + s_1 t_0^T]
-          for (int j = 1; j <= g; ++j) {
-            const double alpha = (2.0 / (hi - lo)) * (j >= 2 ? 2.0 : 1.0);
-            adj_dbar_uv(pg, B, Sv.p + (size_t)j * vec, KS.p + (size_t)j * vec,
-                        T.p + (size_t)(j - 1) * vec, KT.p + (size_t)(j - 1) * vec, alpha,
-                        2.0 * alpha, dbar.p, U.p + (size_t)(j - 1) * vec,
-                        V.p + (size_t)(j - 1) * vec, st);
-          }
-          // K_bar += sum_rows U^T V  (column-major view: Kbar += V_cm U_cm^T)
-          GWL_BLAS(rocblas_dgemm(blas.h, rocblas_operation_none, rocblas_operation_transpose,
-                                 (rocblas_int)nvc, (rocblas_int)nvc, (rocblas_int)(g * B), &one,
-                                 V.p, (rocblas_int)nvc, U.p, (rocblas_int)nvc, &one, Kbar.p,
-                                 (rocblas_int)nvc));
-          // q_bar_k += D w_bar_k
-          adj_axpy(qbc, Sv.p, 1.0, (long)vec, st);
-          // rotate: q_bar_{k+1} <- q_bar_k <- q_bar_{k-1} <- 0
-          double* t = qbn;
-          qbn = qbc;
-          qbc = qbp;
-          qbp = t;
-          GWL_HIP(hipMemsetAsync(qbp, 0, vec * 8, st));
         }
       }
       // start vector adjoint: q_bar_0 is now in qbn

@@ -109,3 +109,26 @@ def test_vjp_deterministic(tiny):
             out.append((sig, ge, go.cpu().numpy()))
     for a, b in zip(out[0], out[1]):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("n_lanczos", [7, 17])
+def test_vjp_stored_iterates_match_checkpoints(tiny, n_lanczos):
+    """The backward from iterates kept in the forward and the backward that
+    recomputes them from checkpoints run the same kernels in the same order:
+    bitwise-equal results (L = 7: a ragged last checkpoint segment; L = 17 >
+    N_vc = 15: every recurrence ends early at an invariant subspace)."""
+    import paper_2310_20103_amd as GW
+    s, wl, lo, hi, om, G = tiny
+    _say(f"vjp stored iterates vs checkpoints, L={n_lanczos}, block 4")
+    out = {}
+    for store in (1, 0):
+        with _ctx(s.phi, s.energies_ev, wl, lo, hi, block=4) as c:
+            assert c.query(GW.KEY_ADJOINT_STORED) == -1
+            assert c.query(GW.KEY_ADJOINT_STORE) == 1
+            c.set_option(GW.KEY_ADJOINT_STORE, store)
+            sig, ge, go = c.sigma_c_vjp(s.qp_states, om, wl.eta, n_lanczos, G)
+            assert c.query(GW.KEY_ADJOINT_STORED) == store
+            out[store] = (sig, ge, go.cpu().numpy())
+    for a, b in zip(out[1], out[0]):
+        assert np.all(np.isfinite(a))
+        assert np.array_equal(a, b)
