@@ -356,9 +356,10 @@ enum {
                                    picks it unless GWL_KEY_BF16_TILE was set), 0 before */
   GWL_KEY_ADJOINT_STORE = 32,   /* set/query: 1 (default) = gwl_sigma_c_vjp keeps every
                                    Lanczos step's Chebyshev iterates from its forward when
-                                   they fit in GWL_ADJOINT_STORE_MAX bytes; 0 = always
-                                   recompute them from checkpoints.  Both give bitwise the
-                                   same results. */
+                                   they fit in GWL_ADJOINT_STORE_MAX bytes and that much
+                                   device memory can be allocated; 0 = always recompute
+                                   them from checkpoints.  Both give bitwise the same
+                                   results. */
   GWL_KEY_ADJOINT_STORED = 33   /* query: 1 if the last gwl_sigma_c_vjp call kept the
                                    iterates, 0 if it recomputed them, -1 before a call */
 };

@@ -116,13 +116,21 @@ extern "C" gwl_status gwl_sigma_c_vjp(gwl_ctx* ctx, const int* qp_states, int n_
     Pb.ensure(vec);
     // kept iterates per step k: t_0..t_g, K~t_0..K~t_{g-1}, w_k; then q_L and q_{-1}
     const size_t per_step = (size_t)(2 * g + 2) * vec;
-    const bool store = c.adjoint_store &&
-                       ((size_t)L * per_step + 2 * vec) * sizeof(double) <= GWL_ADJOINT_STORE_MAX;
+    bool store = c.adjoint_store &&
+                 ((size_t)L * per_step + 2 * vec) * sizeof(double) <= GWL_ADJOINT_STORE_MAX;
     DevBuf<double> It;
-    c.adjoint_stored = store ? 1 : 0;
     if (store) {
-      It.ensure((size_t)L * per_step + 2 * vec);
-    } else {
+      try {
+        It.ensure((size_t)L * per_step + 2 * vec);
+      } catch (const Error& e) {
+        // not enough free device memory: recompute from checkpoints instead
+        if (e.code != GWL_ENOMEM) throw;
+        (void)hipGetLastError();
+        store = false;
+      }
+    }
+    c.adjoint_stored = store ? 1 : 0;
+    if (!store) {
       ckq.ensure((size_t)nseg * vec);
       ckqp.ensure((size_t)nseg * vec);
       ck_state.ensure((size_t)nseg * 2 * B);
