@@ -142,6 +142,28 @@ def test_apply_c_mixed(request, which):
     assert relerr(gk, dk) <= 2e-2
 
 
+@pytest.mark.parametrize("n_emp", [100, 150, 260])
+def test_apply_c_conduction_k_steps(n_emp):
+    """C x with N_c padded to 128, 192 and 320: the K loops of the GEMMs over
+    the conduction index run 4, 6 and 10 steps of 32 (the mixed first GEMM
+    has a peeled head and tail of two steps each around its main loop)."""
+    case = Case("grid24_v8c32", name=f"ksteps{n_emp}", seed=90 + n_emp, grid=(16, 16, 16),
+                box=8.0, n_occ=4, n_emp=n_emp, n_qp_occ=1, n_qp_emp=1, n_lanczos=4,
+                n_omega=5)
+    _say("apply_c conduction K steps", n_emp)
+    x = gi.random_pair_vectors(3, case.wl.n_vc, seed=6)
+    ref = x @ case.pr.C.T
+    dk = ref - case.pr.delta ** 2 * x
+    for prec in ("fp64", "mixed"):
+        with make_ctx(case.sys, precision=prec, interval=(case.lo, case.hi)) as ctx:
+            got = ctx.apply_c(torch.tensor(x, device="cuda"), prec).cpu().numpy()
+        if prec == "fp64":
+            assert relerr(got, ref) <= 1e-11
+        else:
+            assert relerr(got, ref) <= 1e-3
+            assert relerr(got - case.pr.delta ** 2 * x, dk) <= 2e-2
+
+
 @pytest.mark.parametrize("which", ["small", "ragged"])
 def test_apply_d_fp64(request, which):
     case = request.getfixturevalue(which)
