@@ -372,6 +372,7 @@ extern "C" gwl_status gwl_sigma_c_vjp(gwl_ctx* ctx, const int* qp_states, int n_
     // ---- energies: Delta_bar -> e_bar, plus the explicit z_n terms
     std::vector<double> dtot(nvc), eb(P);
     GWL_HIP(hipStreamSynchronize(st));
+    It.release();  // the kept iterates are done with; the orbital stage needs the room
     GWL_HIP(hipMemcpy(dtot.data(), dbar_tot.p, nvc * 8, hipMemcpyDeviceToHost));
     GWL_HIP(hipMemcpy(eb.data(), ebar.p, P * 8, hipMemcpyDeviceToHost));
     std::vector<double> ge(c.n_orb, 0.0);
