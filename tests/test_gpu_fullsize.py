@@ -11,6 +11,9 @@ the oracle computed one at a time by its matrix-free FP64 route:
   small fraction of C x);
 * coupling vectors P_nm of the first QP state for n = 0, 300, 639 (FP64
   <= 1e-10);
+* all 128 vectors of a second batch: the Gram matrix x_i . C x_j is
+  symmetric and x . C x >= x . Delta^2 x, in FP64 (1e-12) and mixed
+  (2e-3 on the coupling part; measured 1.6e-4);
 * two Lanczos steps on p_7(C) for the benchmark's first batch (m = first QP
   state, n = 0..127), pairs 0 and 77: a_0, a_1, b_1 and ||P||^2 against the
   oracle's Lanczos from the same start vector: FP64 <= 1e-9 relative, mixed
@@ -72,6 +75,25 @@ def test_apply_c_full_size(full):
         assert relerr(got64[r], ref) <= 1e-10
         assert relerr(gotmx[r], ref) <= 1e-3
         assert relerr(gotmx[r] - pr.delta ** 2 * x[r], dk) <= 2e-2
+
+
+def test_apply_c_symmetry_and_bound_full_size(full):
+    """Properties that hold at any size, over all 128 vectors of the batch: the
+    Gram matrix x_i . C x_j is symmetric (C is), and x . C x >= x . Delta^2 x
+    (the coupling term 2 Delta^1/2 K Delta^1/2 is positive semidefinite)."""
+    wl, phi, eps, qp, ctx, pr = full
+    _say("full size C x symmetry and lower bound, 128 vectors")
+    x = gi.random_pair_vectors(128, wl.n_vc, seed=13)
+    xt = torch.tensor(x, device="cuda")
+    d2x = pr.delta ** 2 * x
+    for prec, sym_tol in (("fp64", 1e-12), ("mixed", 2e-3)):
+        cx = ctx.apply_c(xt, prec).cpu().numpy()
+        gk = x @ (cx - d2x).T  # coupling part of the Gram matrix
+        asym = np.max(np.abs(gk - gk.T)) / np.max(np.abs(gk))
+        _say(f"  {prec}: coupling Gram asymmetry {asym:.2e}, "
+             f"min diagonal {np.min(np.diag(gk)):.3e}")
+        assert asym <= sym_tol
+        assert np.min(np.diag(gk)) >= -sym_tol * np.max(np.abs(gk))
 
 
 def test_coupling_full_size(full):

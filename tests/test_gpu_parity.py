@@ -30,13 +30,13 @@ def box_of(wl):
     return tuple(n * wl.h for n in wl.grid)
 
 
-def make_ctx(sysm, precision="fp64", interval=None, **kw):
+def make_ctx(sysm, precision="fp64", interval=None, poly_degree_override=None, **kw):
     import paper_2310_20103_amd as G
     wl = sysm.wl
     lo, hi = interval if interval is not None else (0.0, 0.0)
+    g = wl.poly_degree if poly_degree_override is None else poly_degree_override
     return G.Context(sysm.phi, sysm.energies_ev, wl.n_occ, wl.grid, box_of(wl),
-                     precision=precision, poly_degree=wl.poly_degree, poly_lo=lo, poly_hi=hi,
-                     **kw)
+                     precision=precision, poly_degree=g, poly_lo=lo, poly_hi=hi, **kw)
 
 
 def relerr(a, b):
@@ -267,6 +267,35 @@ def test_sigma_fp64_small(small, ctx_small):
                                      small.lo, small.hi, wl.poly_degree)
         assert relerr(got[i], ref) <= 1e-8
         assert np.all(np.isfinite(got[i]))
+
+
+def test_sigma_error_falls_with_degree_and_length(small):
+    """Analogues of the paper's convergence checks in the polynomial degree g
+    and the Lanczos length L (Fig. 1): the GPU's FP64 Sigma approaches the
+    exact one as g grows (at L = N_vc, where the recurrence is exhausted) and
+    approaches the L -> N_vc limit Sigma_Dg as L grows (g = 7); every point
+    matches the oracle's Lanczos Sigma."""
+    wl, pr, lo, hi = small.wl, small.pr, small.lo, small.hi
+    m = int(small.sys.qp_states[0])
+    om = small.sys.omega_ev
+    sx = pr.sigma_exact(m, om, wl.eta)
+    errs_g = []
+    for g in (3, 7, 12):
+        _say(f"sigma vs degree g={g}")
+        with make_ctx(small.sys, interval=(lo, hi), poly_degree_override=g) as c:
+            got = c.sigma_c([m], om, wl.eta, wl.n_vc)[0]
+        assert relerr(got, pr.sigma_lanczos(m, om, wl.eta, wl.n_vc, lo, hi, g)) <= 1e-8
+        errs_g.append(float(np.max(np.abs(got - sx))))
+    assert errs_g[0] > errs_g[1] > errs_g[2], errs_g
+    sdg = pr.sigma_dg(m, om, wl.eta, lo, hi, wl.poly_degree)
+    errs_l = []
+    with make_ctx(small.sys, interval=(lo, hi)) as c:
+        for L in (4, 16, 64):
+            _say(f"sigma vs length L={L}")
+            got = c.sigma_c([m], om, wl.eta, L)[0]
+            assert relerr(got, pr.sigma_lanczos(m, om, wl.eta, L, lo, hi, wl.poly_degree)) <= 1e-8
+            errs_l.append(float(np.max(np.abs(got - sdg))))
+    assert errs_l[0] > errs_l[1] > errs_l[2], errs_l
 
 
 def test_sigma_fp64_ragged(ragged, ctx_ragged):
