@@ -80,7 +80,9 @@ typedef enum {
 typedef enum {
   GWL_REORTH_NONE = 0,   /* plain three-term recurrence */
   GWL_REORTH_LOCAL = 1,  /* re-project against q_k and q_{k-1} */
-  GWL_REORTH_FULL = 2    /* two-pass classical Gram-Schmidt against all q_j */
+  GWL_REORTH_FULL = 2    /* classical Gram-Schmidt against all q_j, with a second
+                            pass for the slots whose first pass removed more than
+                            half of ||w||^2 */
 } gwl_reorth;
 
 typedef struct {

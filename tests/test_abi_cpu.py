@@ -46,3 +46,33 @@ def test_host_only_calls():
     assert L.gwl_query(None, B.KEY_N_VC, ctypes.byref(out)) == B.GWL_EINVAL
     assert b"null context" in L.gwl_last_error()
     L.gwl_destroy(None)
+
+
+def _header_enum(prefix):
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    return {m.group(1): int(m.group(2))
+            for m in re.finditer(r"\b" + prefix + r"([A-Z0-9_]+)\s*=\s*(-?\d+)", text)}
+
+
+def test_binding_constants_match_header():
+    """Every option key and status code the binding names has the value the
+    header gives it (ctypes passes them as plain ints)."""
+    from paper_2310_20103_amd import binding as B
+    keys = _header_enum("GWL_KEY_")
+    bound = {n[len("KEY_"):]: v for n, v in vars(B).items()
+             if n.startswith("KEY_") and isinstance(v, int)}
+    assert bound, "no option keys in the binding"
+    for name, value in bound.items():
+        assert keys.get(name) == value, name
+    for name, (ms, cnt, vec) in {"GEMM1": B.KEY_PROF["gemm1"], "GEMM2": B.KEY_PROF["gemm2"],
+                                 "FFT": B.KEY_PROF["fft"]}.items():
+        assert (keys["PROF_MS_" + name], keys["PROF_N_" + name], keys["PROF_VEC_" + name]) == \
+            (ms, cnt, vec)
+    codes = _header_enum("GWL_E")
+    for name in ("INVAL", "NOMEM", "DEVICE", "NUMERIC", "STATE", "UNSUPPORTED"):
+        assert getattr(B, "GWL_E" + name) == codes[name], name
+    assert B.GWL_OK == 0
+    prec = _header_enum("GWL_")
+    assert (B.FP64, B.MIXED_BF16) == (prec["FP64"], prec["MIXED_BF16"])
+    assert B.REORTH == {"none": prec["REORTH_NONE"], "local": prec["REORTH_LOCAL"],
+                        "full": prec["REORTH_FULL"]}
