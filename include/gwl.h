@@ -67,12 +67,17 @@ typedef enum {
  * Chebyshev combination, reorthogonalisation and the continued fraction are
  * FP64 in every mode. */
 typedef enum {
-  GWL_FP64 = 0,       /* GEMMs and FFT in FP64 */
-  GWL_MIXED_BF16 = 1  /* mixed: first GEMM on FP16 operands (pair vectors and orbitals
-                         scaled by powers of two into FP16's range), second GEMM on
-                         BF16 operands, both with FP32 accumulation; FFT FP32;
-                         recurrence, Chebyshev combination and continued fraction
-                         FP64 */
+  GWL_FP64 = 0,            /* GEMMs and FFT in FP64 */
+  GWL_MIXED_F16_BF16 = 1,  /* first GEMM on FP16 operands (pair vectors and orbitals
+                              scaled by powers of two into FP16's range), second GEMM
+                              on BF16 operands (phi_v V needs BF16's exponent range),
+                              both with FP32 accumulation; FFT in FP32 */
+  GWL_MIXED_BF16X3 = 2,    /* three-term BF16 split of each operand: not built
+                              (GWL_EUNSUPPORTED); the 16-bit path already meets the
+                              1 meV bar on the smooth stress inputs */
+  GWL_MIXED_FP32 = 3       /* FP32 operands: not built (GWL_EUNSUPPORTED); FP32
+                              matrix throughput is twice FP64's, too little to
+                              pay for the separate kernels */
 } gwl_precision;
 
 /* Reorthogonalisation of the Lanczos vectors (the paper does not prescribe
@@ -129,7 +134,16 @@ gwl_status gwl_setup(const void* orbitals, int orb_dtype, int orb_on_device,
  *   sigma_out   host [n_qp][n_omega][2] (re, im), eV.
  * The n-sum runs over all n_orb orbitals, n = m included.  Each (m, n) run
  * ends early if b_{k+1} <= 1e-12 max_j |a_j| (exact invariant subspace).
- * Errors: GWL_EINVAL, GWL_ENUMERIC (non-finite coefficients), GWL_EDEVICE. */
+ * Interval check: p_g approximates the square root only on [lo, hi] (the
+ * paragraph after Eq. 12) and extrapolates wildly outside it.  After the
+ * recurrence every run's tridiagonal T is tested by Sturm counts: an
+ * eigenvalue of T above max p_g or below min p_g on [lo, hi] by more than
+ * 0.5 % of max p_g means C has spectrum outside [lo, hi] that the start
+ * vector sees (about 1 % beyond hi), and the call fails with GWL_ENUMERIC
+ * instead of returning a corrupted Sigma (Tamm-Dancoff and quadrature runs
+ * use no polynomial and are not tested).
+ * Errors: GWL_EINVAL, GWL_ENUMERIC (non-finite coefficients, spectrum outside
+ * the Chebyshev interval), GWL_EDEVICE. */
 gwl_status gwl_sigma_c(gwl_ctx* ctx, const int* qp_states, int n_qp,
                        const double* omega_ev, int n_omega, double eta_ev,
                        int n_lanczos, double* sigma_out);
@@ -207,7 +221,7 @@ gwl_status gwl_sigma_c_vjp(gwl_ctx* ctx, const int* qp_states, int n_qp,
 
 /* Hartree potential V = FFT^-1[kernel_scale 4 pi/|G|^2 FFT[rho]] of n_fields
  * real densities.  rho, v: device [n_fields][nx*ny*nz] in float64 if
- * precision == GWL_FP64, float32 if GWL_MIXED_BF16. */
+ * precision == GWL_FP64, float32 if GWL_MIXED_F16_BF16. */
 gwl_status gwl_poisson(gwl_ctx* ctx, const void* rho, void* v, int n_fields,
                        int precision);
 
@@ -362,8 +376,12 @@ enum {
                                    device memory can be allocated; 0 = always recompute
                                    them from checkpoints.  Both give bitwise the same
                                    results. */
-  GWL_KEY_ADJOINT_STORED = 33   /* query: 1 if the last gwl_sigma_c_vjp call kept the
+  GWL_KEY_ADJOINT_STORED = 33,  /* query: 1 if the last gwl_sigma_c_vjp call kept the
                                    iterates, 0 if it recomputed them, -1 before a call */
+  GWL_KEY_HI_RESIDUAL = 34      /* query: residual bound |b_40 u_40| of the largest Ritz
+                                   value in the last estimate of the interval's upper end
+                                   (hartree^2; 0 when no estimate ran or the recurrence
+                                   ended in an invariant subspace) */
 };
 
 /* Device-memory cap for the iterates kept by gwl_sigma_c_vjp: per Lanczos step

@@ -77,6 +77,36 @@ cfrac_kernel(const double* __restrict__ ca, const double* __restrict__ cb,
   }
 }
 
+// ---------------------------------------------------------------- interval check
+// Number of eigenvalues of the L x L tridiagonal T below tau: the negative
+// pivots of T - tau I = L D L^T (Sylvester's law of inertia).  A zero pivot
+// is replaced by a tiny negative one, as in bisection codes.
+__device__ inline int sturm_below(const double* __restrict__ a, const double* __restrict__ b,
+                                  int L, double tau) {
+  int cnt = 0;
+  double d = 1.0;
+  for (int i = 0; i < L; ++i) {
+    d = (a[i] - tau) - (i > 0 ? b[i - 1] * b[i - 1] / d : 0.0);
+    if (fabs(d) < 1e-280) d = -1e-280;
+    cnt += d < 0.0;
+  }
+  return cnt;
+}
+
+__global__ void __launch_bounds__(256)
+interval_check_kernel(int npairs, const double* __restrict__ ca, const double* __restrict__ cb,
+                      const int* __restrict__ lens, int ld, double t_lo, double t_hi,
+                      int* __restrict__ bad) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npairs) return;
+  const int L = lens[p];
+  const double* a = ca + (long)p * ld;
+  const double* b = cb + (long)p * ld;
+  int out = 0;
+  if (L > 0) out = sturm_below(a, b, L, t_lo) > 0 || sturm_below(a, b, L, t_hi) < L;
+  bad[p] = out;
+}
+
 // ---------------------------------------------------------------- quadrature
 // Lanczos on C + Gauss quadrature: the eigenvalues theta_k of each pair's
 // tridiagonal T and the first components u_k(0) of its eigenvectors, by the
@@ -252,6 +282,14 @@ void sum_groups(const double* sig, int ngroups, int per, int nomega, double* out
 void sum_polar(const double* sig, int nn, int nomega, double* out, hipStream_t st) {
   if (nn <= 0 || nomega <= 0) return;
   sum_polar_kernel<<<ceil_div(2 * nomega, 256), 256, 0, st>>>(sig, nn, nomega, out);
+  GWL_HIP(hipGetLastError());
+}
+
+void lz_interval_check(int npairs, const double* coef_a, const double* coef_b, const int* lens,
+                       int ld, double t_lo, double t_hi, int* bad, hipStream_t st) {
+  if (npairs <= 0) return;
+  interval_check_kernel<<<(npairs + 255) / 256, 256, 0, st>>>(npairs, coef_a, coef_b, lens, ld,
+                                                              t_lo, t_hi, bad);
   GWL_HIP(hipGetLastError());
 }
 

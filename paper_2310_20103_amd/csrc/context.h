@@ -140,6 +140,8 @@ struct gwl_ctx {
   int adjoint_store = 1;     // 1: the adjoint keeps the forward's iterates when they fit
   int adjoint_stored = -1;   // what the last adjoint call did (-1: no call yet)
   bool poly_hi_auto = false;  // the interval's upper end is estimated (re-done for ISDF)
+  double hi_resid = 0.0;      // residual bound of the last estimate's largest Ritz value
+  DevBuf<int> ivbad;          // per-run flags of the interval check
 
   // ISDF of the pair densities: the K product runs on N_mu interpolation
   // points with the Coulomb matrix M / dV in place of the FFT Poisson solve
@@ -651,7 +653,7 @@ struct gwl_ctx {
   Tune autotune(int prec, int bmax) {
     Tune best = tuned[prec];
     if (best.B > 0) return best;
-    const bool pick_tile = prec == GWL_MIXED_BF16 && fp64_kernel && !tile_fixed;
+    const bool pick_tile = prec == GWL_MIXED_F16_BF16 && fp64_kernel && !tile_fixed;
     if (tune_cache_read(prec, best)) {
       if (pick_tile) set_tile(best.tile);
       best.tile = bf16_tile;
@@ -860,6 +862,7 @@ struct gwl_ctx {
     }
     GWL_HIP(hipStreamSynchronize(stream));
     prof_flush();
+    if (!on_c && !tda) check_interval(P, ld);
   }
 
   int auto_block(int P, int L) const {
@@ -873,9 +876,15 @@ struct gwl_ctx {
   }
 
   // Upper end of the spectrum of C: Lanczos on C from a fixed pseudo-random
-  // start, largest Ritz value plus its residual bound, 1% margin.
+  // start, largest Ritz value theta of the steps x steps tridiagonal plus its
+  // residual bound |b_steps u_last| (one more step supplies b_steps; the
+  // residual is 0 when the recurrence ends in an invariant subspace), 1 %
+  // margin.  A Ritz residual locates an eigenvalue near theta, it does not
+  // bound the spectrum; the Sturm check after every Lanczos run on p_g(C)
+  // catches an estimate that fell short.
   double estimate_hi() {
     const int steps = (int)std::min<long>(40, nvc);
+    const int len = steps < nvc ? steps + 1 : steps;
     std::vector<double> x0(nvc);
     uint64_t st = 0x9E3779B97F4A7C15ull;
     for (long i = 0; i < nvc; ++i) {
@@ -893,18 +902,20 @@ struct gwl_ctx {
     block = 1;
     precision = GWL_FP64;
     tda = 0;
-    int m0 = 0, n0 = 0, len = steps;
-    run_pairs(1, &m0, &n0, &len, steps, true, start.p);
+    int m0 = 0, n0 = 0, lreq = len;
+    run_pairs(1, &m0, &n0, &lreq, len, true, start.p);
     reorth = saved_reorth;
     block = saved_block;
     precision = saved_prec;
     tda = saved_tda;
-    std::vector<double> a(steps), b(steps);
-    int L = 0;
-    GWL_HIP(hipMemcpy(a.data(), coef_a.p, steps * sizeof(double), hipMemcpyDeviceToHost));
-    GWL_HIP(hipMemcpy(b.data(), coef_b.p, steps * sizeof(double), hipMemcpyDeviceToHost));
-    GWL_HIP(hipMemcpy(&L, out_len.p, sizeof(int), hipMemcpyDeviceToHost));
-    GWL_CHECK(L >= 1 && finite_all(a.data(), L), GWL_ENUMERIC, "spectrum estimate failed");
+    std::vector<double> a(len), b(len);
+    int lout = 0;
+    GWL_HIP(hipMemcpy(a.data(), coef_a.p, len * sizeof(double), hipMemcpyDeviceToHost));
+    GWL_HIP(hipMemcpy(b.data(), coef_b.p, len * sizeof(double), hipMemcpyDeviceToHost));
+    GWL_HIP(hipMemcpy(&lout, out_len.p, sizeof(int), hipMemcpyDeviceToHost));
+    GWL_CHECK(lout >= 1 && finite_all(a.data(), lout) && finite_all(b.data(), lout),
+              GWL_ENUMERIC, "spectrum estimate failed");
+    const int L = std::min(lout, steps);
     std::vector<double> t((size_t)L * L, 0.0), vec;
     for (int i = 0; i < L; ++i) {
       t[(size_t)i * L + i] = a[i];
@@ -915,7 +926,50 @@ struct gwl_ctx {
     for (int i = 1; i < L; ++i)
       if (t[(size_t)i * L + i] > t[(size_t)imax * L + imax]) imax = i;
     const double theta = t[(size_t)imax * L + imax];
-    const double resid = (L < steps) ? 0.0 : std::fabs(b[L - 1] * vec[(size_t)(L - 1) * L + imax]);
-    return (theta + resid) * 1.01;
+    hi_resid = (lout > steps) ? std::fabs(b[steps - 1] * vec[(size_t)(L - 1) * L + imax]) : 0.0;
+    return (theta + hi_resid) * 1.01;
+  }
+
+  // Range [pmin, pmax] of p_g over [lo, hi]: the polynomial sampled at 8193
+  // points x = cos(theta), theta uniform (dense near both ends), by Clenshaw.
+  void poly_range(double& pmin, double& pmax) const {
+    const int ns = 8193;
+    pmin = 1e300;
+    pmax = -1e300;
+    for (int i = 0; i < ns; ++i) {
+      const double x = std::cos(kPi * i / (ns - 1));
+      double b1 = 0.0, b2 = 0.0;
+      for (int j = (int)cheb.size() - 1; j >= 1; --j) {
+        const double b0 = cheb[j] + 2.0 * x * b1 - b2;
+        b2 = b1;
+        b1 = b0;
+      }
+      const double p = cheb[0] + x * b1 - b2;
+      pmin = std::min(pmin, p);
+      pmax = std::max(pmax, p);
+    }
+  }
+
+  // After Lanczos runs on p_g(C) (coefficients of P pairs in coef_a/coef_b,
+  // lengths out_len, leading dimension ld): fail with GWL_ENUMERIC when some
+  // run's tridiagonal has an eigenvalue outside [pmin - tol, pmax + tol],
+  // tol = 0.5 % of max |p_g| -- the spectrum of C left [lo, hi] and p_g
+  // extrapolated there.
+  void check_interval(int P, int ld) {
+    double pmin, pmax;
+    poly_range(pmin, pmax);
+    const double tol = 5e-3 * std::max(std::fabs(pmin), std::fabs(pmax));
+    ivbad.ensure(P);
+    lz_interval_check(P, coef_a.p, coef_b.p, out_len.p, ld, pmin - tol, pmax + tol, ivbad.p,
+                      stream);
+    std::vector<int> bad(P);
+    GWL_HIP(hipMemcpyAsync(bad.data(), ivbad.p, P * sizeof(int), hipMemcpyDeviceToHost, stream));
+    GWL_HIP(hipStreamSynchronize(stream));
+    int nbad = 0;
+    for (int v : bad) nbad += v != 0;
+    GWL_CHECK(nbad == 0, GWL_ENUMERIC,
+              "the spectrum of C leaves the Chebyshev interval [" + std::to_string(poly_lo) +
+                  ", " + std::to_string(poly_hi) + "] hartree^2 (" + std::to_string(nbad) +
+                  " of " + std::to_string(P) + " runs): p_g(C) is no square root there");
   }
 };

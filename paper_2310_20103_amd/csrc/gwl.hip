@@ -73,6 +73,14 @@ void upload_tables(int n, double len, DevBuf<cplx<T>>& tw, DevBuf<T>& g2) {
 
 void check_ctx(gwl_ctx* c) { GWL_CHECK(c != nullptr, GWL_EINVAL, "null context"); }
 
+// The two built precisions; the split-BF16 and FP32 members of gwl_precision
+// are named by the ABI but not built.
+void check_precision(int p) {
+  GWL_CHECK(p != GWL_MIXED_BF16X3 && p != GWL_MIXED_FP32, GWL_EUNSUPPORTED,
+            "precision not built: use GWL_FP64 or GWL_MIXED_F16_BF16");
+  GWL_CHECK(p == GWL_FP64 || p == GWL_MIXED_F16_BF16, GWL_EINVAL, "unknown precision");
+}
+
 }  // namespace
 
 namespace {
@@ -130,8 +138,7 @@ gwl_status gwl_setup(const void* orbitals, int orb_dtype, int orb_on_device, int
     gwl_options o;
     gwl_default_options(&o);
     if (opts) o = *opts;
-    GWL_CHECK(o.precision == GWL_FP64 || o.precision == GWL_MIXED_BF16, GWL_EINVAL,
-              "unknown precision");
+    check_precision(o.precision);
     GWL_CHECK(o.poly_degree >= 1 && o.poly_degree <= 30, GWL_EINVAL,
               "poly_degree must be in [1, 30]");
     GWL_CHECK(o.reorth >= 0 && o.reorth <= 2, GWL_EINVAL, "unknown reorth mode");
@@ -335,7 +342,8 @@ gwl_status gwl_set_option(gwl_ctx* ctx, int key, double value) {
     check_ctx(ctx);
     switch (key) {
       case GWL_KEY_PRECISION:
-        GWL_CHECK(value == GWL_FP64 || value == GWL_MIXED_BF16, GWL_EINVAL, "bad precision");
+        check_precision((int)value);
+        GWL_CHECK(value == (int)value, GWL_EINVAL, "bad precision");
         ctx->precision = (int)value;
         break;
       case GWL_KEY_REORTH:
@@ -375,7 +383,7 @@ gwl_status gwl_set_option(gwl_ctx* ctx, int key, double value) {
         if (ctx->bf16_tile != (int)value || !ctx->tile_fixed) {
           ctx->bf16_tile = (int)value;
           ctx->tile_fixed = true;
-          ctx->tuned[GWL_MIXED_BF16] = gwl_ctx::Tune{};
+          ctx->tuned[GWL_MIXED_F16_BF16] = gwl_ctx::Tune{};
           ctx->drop_graph();
         }
         break;
@@ -415,6 +423,7 @@ gwl_status gwl_query(gwl_ctx* ctx, int key, double* out) {
       case GWL_KEY_QUADRATURE: *out = ctx->quadrature; break;
       case GWL_KEY_ADJOINT_STORE: *out = ctx->adjoint_store; break;
       case GWL_KEY_ADJOINT_STORED: *out = ctx->adjoint_stored; break;
+      case GWL_KEY_HI_RESIDUAL: *out = ctx->hi_resid; break;
       case GWL_KEY_ISDF: *out = ctx->isdf_on; break;
       case GWL_KEY_ISDF_NMU: *out = ctx->isdf_ready ? ctx->n_mu : 0; break;
       case GWL_KEY_PROFILE: *out = ctx->profile; break;
@@ -442,8 +451,7 @@ gwl_status gwl_poisson(gwl_ctx* ctx, const void* rho, void* v, int n_fields, int
     GWL_CHECK(n_fields >= 0, GWL_EINVAL, "n_fields < 0");
     if (n_fields == 0) return;
     GWL_CHECK(rho && v, GWL_EINVAL, "null pointer");
-    GWL_CHECK(precision == GWL_FP64 || precision == GWL_MIXED_BF16, GWL_EINVAL,
-              "bad precision");
+    check_precision(precision);
     const int chunk = std::max(2, std::min(n_fields + (n_fields & 1), 64));
     ctx->ensure_work(chunk, 1, false);
     for (int f0 = 0; f0 < n_fields; f0 += chunk) {
@@ -469,8 +477,7 @@ gwl_status gwl_apply_c(gwl_ctx* ctx, const double* x, double* y, int n_vec, int 
     GWL_CHECK(n_vec >= 0, GWL_EINVAL, "n_vec < 0");
     if (n_vec == 0) return;
     GWL_CHECK(x && y, GWL_EINVAL, "null pointer");
-    GWL_CHECK(precision == GWL_FP64 || precision == GWL_MIXED_BF16, GWL_EINVAL,
-              "bad precision");
+    check_precision(precision);
     ctx->prof_reset();
     const int chunk = std::min(n_vec, 64);
     ctx->ensure_work(chunk, 1, false);
@@ -490,8 +497,7 @@ gwl_status gwl_apply_d(gwl_ctx* ctx, const double* x, double* y, int n_vec, int 
     GWL_CHECK(n_vec >= 0, GWL_EINVAL, "n_vec < 0");
     if (n_vec == 0) return;
     GWL_CHECK(x && y, GWL_EINVAL, "null pointer");
-    GWL_CHECK(precision == GWL_FP64 || precision == GWL_MIXED_BF16, GWL_EINVAL,
-              "bad precision");
+    check_precision(precision);
     ctx->prof_reset();
     const int chunk = std::min(n_vec, 64);
     ctx->ensure_work(chunk, 1, false);

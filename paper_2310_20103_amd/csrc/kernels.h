@@ -186,6 +186,12 @@ void lz_reorth(const SlotState& s, int nb, int kmax, int mode, const double* bas
 void lz_beta(const SlotState& s, int nb, double* q, double* qprev, double* w, double* basis,
              long basis_slot_stride, int store_basis, long nvc, hipStream_t st);
 
+// Sturm counts of each run's tridiagonal T (a_0..a_{L-1}, b_1..b_{L-1} in
+// [npairs][ld], L = lens[p]): bad[p] = 1 when T has an eigenvalue below t_lo
+// or above t_hi, else 0.  One thread per run.
+void lz_interval_check(int npairs, const double* coef_a, const double* coef_b, const int* lens,
+                       int ld, double t_lo, double t_hi, int* bad, hipStream_t st);
+
 // ---------------------------------------------------------------- continued fraction
 // sig[p][w] (complex, eV) for pairs p, Eq. 12 with Eq. 14.
 void cfrac_sigma(int npairs, const double* coef_a, const double* coef_b, const int* lens,

@@ -5,6 +5,12 @@
   energies and in the orbital grid values: <= 1e-6 relative;
 * against central finite differences of the oracle forward (same algorithm):
   <= 1e-5 relative;
+* the energy gradient element by element against the oracle's closed form
+  (Daleckii-Krein divided differences through the eigendecomposition of C)
+  at L >= N_vc, where the recurrence is exhausted and Sigma_L equals the
+  exact p_g(C) resolvent: <= 1e-6 of the largest element;
+* 64 sampled orbital-gradient entries (8 per orbital) against central
+  differences of the oracle forward in that one grid value: <= 1e-5;
 * the forward Sigma returned with the gradient equals gwl_sigma_c;
 * two runs agree bitwise.
 """
@@ -132,3 +138,50 @@ def test_vjp_stored_iterates_match_checkpoints(tiny, n_lanczos):
     for a, b in zip(out[1], out[0]):
         assert np.all(np.isfinite(a))
         assert np.array_equal(a, b)
+
+
+def test_vjp_energy_gradient_elementwise(tiny):
+    s, wl, lo, hi, om, G = tiny
+    qp = s.qp_states
+    L = 20  # > N_vc = 15: every recurrence ends at an invariant subspace
+    _say("vjp energy gradient element by element vs closed form, L", L)
+    with _ctx(s.phi, s.energies_ev, wl, lo, hi) as c:
+        sig, ge, _ = c.sigma_c_vjp(qp, om, wl.eta, L, G)
+    sdg = A.sigma_dg_states(s.phi, s.energies_ev, wl.n_occ, wl.grid, wl.h, qp, om, wl.eta, lo,
+                            hi, wl.poly_degree)
+    assert np.max(np.abs(sig - sdg)) <= 1e-9 * np.max(np.abs(sdg))
+    ref = A.dk_energy_gradient(s.phi, s.energies_ev, wl.n_occ, wl.grid, wl.h, qp, om, wl.eta,
+                               lo, hi, wl.poly_degree, G)
+    err = np.max(np.abs(ge - ref)) / np.max(np.abs(ref))
+    _say(f"  max |grad| {np.max(np.abs(ref)):.3e}, rel err {err:.2e}")
+    assert err <= 1e-6
+
+
+def test_vjp_orbital_gradient_sampled_entries(tiny):
+    s, wl, lo, hi, om, G = tiny
+    qp = s.qp_states
+    _say("vjp orbital gradient, 64 sampled entries vs oracle central differences")
+    with _ctx(s.phi, s.energies_ev, wl, lo, hi) as c:
+        _, _, go = c.sigma_c_vjp(qp, om, wl.eta, wl.n_lanczos, G)
+        go = go.cpu().numpy()
+
+    def loss_at(phi):
+        return A.loss(A.sigma_states(phi, s.energies_ev, wl.n_occ, wl.grid, wl.h, qp, om,
+                                     wl.eta, wl.n_lanczos, lo, hi, wl.poly_degree), G)
+
+    rng = np.random.default_rng(8)
+    step = 1e-4 * np.mean(np.abs(s.phi))
+    worst = 0.0
+    scale = np.max(np.abs(go))
+    for a in range(wl.n_orb):
+        for r in rng.choice(wl.n_r, size=8, replace=False):
+            ph = s.phi.copy()
+            ph[a, r] += step
+            lp = loss_at(ph)
+            ph[a, r] -= 2 * step
+            lm = loss_at(ph)
+            fd = (lp - lm) / (2 * step)
+            dev = abs(fd - go[a, r])
+            worst = max(worst, dev / scale)
+            assert dev <= 1e-5 * scale + 1e-5 * abs(fd), (a, r, fd, go[a, r])
+    _say(f"  max |dl/dphi| {scale:.3e}, worst deviation {worst:.2e} of it")
