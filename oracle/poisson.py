@@ -46,7 +46,9 @@ def poisson(rho: np.ndarray, shape, h: float, scale: float = 1.0) -> np.ndarray:
     axes = (-3, -2, -1)
     v = coulomb_kernel(shape, h, scale)
     out = np.fft.ifftn(v * np.fft.fftn(r3, axes=axes), axes=axes)
-    return out.real.reshape(rho.shape)
+    # a contiguous copy: the real part is a strided view, which numpy's
+    # matrix product would not hand to BLAS
+    return np.ascontiguousarray(out.real).reshape(rho.shape)
 
 
 def dft_matrix(n: int) -> np.ndarray:
