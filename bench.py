@@ -156,27 +156,32 @@ def run_adjoint(args):
     import torch
     import gw_inputs as gi
     import paper_2310_20103_amd as G
-    wl = gi.workload("grid48_v64c256")
+    wl = gi.workload(args.adjoint_workload)
+    L = args.adjoint_lanczos or wl.n_lanczos
     phi = gi.make_orbitals(wl)
     eps = gi.make_energies(wl)
     qp = gi.frontier_states(eps, wl.n_occ, wl.n_qp_occ, wl.n_qp_emp)
     omega = gi.omega_grid(wl)
+    if args.adjoint_omega:
+        omega = np.linspace(omega[0], omega[-1], args.adjoint_omega)
     box = tuple(k * wl.h for k in wl.grid)
     m = [int(qp[0])]
+    n_end = args.adjoint_vectors or wl.n_orb
     rng = np.random.default_rng([wl.seed, 9])
-    cot = rng.standard_normal((1, wl.n_omega)) + 1j * rng.standard_normal((1, wl.n_omega))
+    cot = rng.standard_normal((1, len(omega))) + 1j * rng.standard_normal((1, len(omega)))
+    log(f"adjoint: {wl.name}, {n_end} start vectors, L = {L}, {len(omega)} frequencies")
     ctx = G.Context(phi, eps, wl.n_occ, wl.grid, box, precision="fp64",
                     poly_degree=wl.poly_degree, reorth="none", block=args.block)
     ctx.lanczos_pairs([m[0]] * 2, [0, 1], [1, 1])
-    if args.adjoint_checkpoints:
-        ctx.set_option(G.KEY_ADJOINT_STORE, 0)
+    if args.adjoint_store:
+        ctx.set_option(G.KEY_ADJOINT_STORE, 1)
     torch.cuda.synchronize()
     t = time.perf_counter()
-    sig = ctx.sigma_c(m, omega, wl.eta, wl.n_lanczos)
+    sig = ctx.sigma_c_range(m, 0, n_end, omega, wl.eta, L)
     t_fwd = time.perf_counter() - t
     log(f"adjoint: forward {t_fwd:.1f}s")
     t = time.perf_counter()
-    sig2, ge, go = ctx.sigma_c_vjp(m, omega, wl.eta, wl.n_lanczos, cot)
+    sig2, ge, go = ctx.sigma_c_vjp(m, omega, wl.eta, L, cot, n_range=(0, n_end))
     torch.cuda.synchronize()
     t_vjp = time.perf_counter() - t
     iterates = "stored" if ctx.query(G.KEY_ADJOINT_STORED) == 1 else "recomputed"
@@ -184,7 +189,7 @@ def run_adjoint(args):
     same = float(np.max(np.abs(sig2 - sig)) / max(np.max(np.abs(sig)), 1e-300))
     ctx.set_reorth("full")
     t = time.perf_counter()
-    ctx.sigma_c(m, omega, wl.eta, wl.n_lanczos)
+    ctx.sigma_c_range(m, 0, n_end, omega, wl.eta, L)
     t_full = time.perf_counter() - t
     lo, hi = ctx.interval
     ctx.close()
@@ -196,7 +201,8 @@ def run_adjoint(args):
         with G.Context(p, e, wl.n_occ, wl.grid, box, precision="fp64",
                        poly_degree=wl.poly_degree, poly_lo=lo, poly_hi=hi, reorth="none",
                        block=args.block) as c:
-            return float(np.sum((np.conj(cot) * c.sigma_c(m, omega, wl.eta, wl.n_lanczos)).real))
+            return float(np.sum((np.conj(cot) * c.sigma_c_range(m, 0, n_end, omega, wl.eta,
+                                                                L)).real))
 
     de = rng.standard_normal(wl.n_orb)
     dp = rng.standard_normal(phi.shape) * float(np.mean(np.abs(phi)))
@@ -210,8 +216,8 @@ def run_adjoint(args):
         "metric": "Sigma_c vector-Jacobian product time / forward time, FP64", "unit": "ratio",
         "value": round(t_vjp / t_fwd, 3), "n_gpus": 1, "higher_is_better": False,
         "dtype": "f64", "data": "synthetic",
-        "config": {"workload": wl.name, "qp_states": 1, "start_vectors": wl.n_orb,
-                   "n_lanczos": wl.n_lanczos, "n_omega": wl.n_omega, "block": args.block,
+        "config": {"workload": wl.name, "qp_states": 1, "start_vectors": n_end,
+                   "n_lanczos": L, "n_omega": len(omega), "block": args.block,
                    "iterates": iterates},
         "forward_s": round(t_fwd, 3), "vjp_s_incl_forward": round(t_vjp, 3),
         "forward_full_reorth_s": round(t_full, 3),
@@ -497,8 +503,15 @@ def main():
                                        "large"),
                     default="headline")
     ap.add_argument("--pairs", type=int, default=256, help="uneven mode: pairs measured")
-    ap.add_argument("--adjoint-checkpoints", action="store_true",
-                    help="adjoint mode: recompute the iterates from checkpoints")
+    ap.add_argument("--adjoint-store", action="store_true",
+                    help="adjoint mode: keep the whole forward run instead of recomputing "
+                         "it from checkpoints (when it fits)")
+    ap.add_argument("--adjoint-workload", default="grid48_v64c256")
+    ap.add_argument("--adjoint-lanczos", type=int, default=0, help="adjoint mode: L (0 = the workload's)")
+    ap.add_argument("--adjoint-vectors", type=int, default=0,
+                    help="adjoint mode: start vectors n in [0, this) (0 = all orbitals)")
+    ap.add_argument("--adjoint-omega", type=int, default=0,
+                    help="adjoint mode: frequencies (0 = the workload's)")
     ap.add_argument("--large-splits", default="",
                     help="large mode: comma-separated second-GEMM splits to time first")
     ap.add_argument("--uneven-blocks", default="",

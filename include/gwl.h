@@ -197,25 +197,41 @@ gwl_status gwl_sigma_from_coeffs(gwl_ctx* ctx, const int* n_idx, int n_pairs,
  *   grad_sigma  host [n_qp][n_omega][2]: G (re, im), per eV of Sigma,
  * returns
  *   grad_energies  host [n_orb]: dl/de_a (per eV of energy),
- *   grad_orbitals  device float64 [n_orb][nx*ny*nz]: dl/dphi_a(r),
+ *   grad_orbitals  device [n_orb][nx*ny*nz] in the orbitals' type (float64,
+ *                  or float32 when gwl_setup was given FP32 orbitals):
+ *                  dl/dphi_a(r), accumulated in FP64,
  *   sigma_out      host [n_qp][n_omega][2] or NULL: the forward Sigma (eV).
  * The forward is the path of gwl_sigma_c in FP64 with the three-term
  * recurrence only (no reorthogonalisation, so the Lanczos vectors can be
  * recomputed exactly); the derivative is exact for that forward.  The
- * backward needs, per step k, q_k, p_g(C) q_k and the Chebyshev iterates of
- * that product: kept from the forward when they fit (GWL_KEY_ADJOINT_STORE,
- * GWL_ADJOINT_STORE_MAX), otherwise recomputed from checkpoints of
- * (q_{k-1}, q_k) every ceil(sqrt(L)) steps, which costs two more p_g(C)
- * products per step.  Orbitals are free
- * variables (no orthonormality constraint), occupations and the Chebyshev
- * interval [lo, hi] are held fixed.  Holds a dense N_vc x N_vc coupling
- * cotangent and the N_vc pair potentials (GWL_EUNSUPPORTED when too large);
- * n_lanczos <= 1024.  The paper defines the forward (Eqs. 7-14); the adjoint
- * is this library's. */
+ * backward needs, per step k, q_k, p_g(C) q_k, the Chebyshev iterates of that
+ * product and the Hartree potentials formed inside it.  By default the
+ * forward keeps only (q_{k-1}, q_k) every ceil(sqrt(L)) steps and the
+ * backward recomputes one such segment at a time (one more p_g(C) product
+ * per step); with GWL_KEY_ADJOINT_STORE = 1 the forward keeps the whole run
+ * when it fits in GWL_ADJOINT_STORE_MAX.  The orbital gradient is contracted
+ * step by step from the outer products of the reverse sweep with the FP64
+ * matrix-core kernel (no N_vc x N_vc matrix is formed); device memory
+ * beyond the context's is about
+ *   ceil(sqrt(L)) [(2g + 2) B N_vc + g B N_r] + g B (N_r + 2 N_v N_c)
+ *   + (N_v + N_c + N_v N_c / 64) N_r  doubles  (B = block, default 64).
+ * Orbitals are free variables (no orthonormality constraint), occupations
+ * and the Chebyshev interval [lo, hi] are held fixed.  n_lanczos <= 1024.
+ * The paper defines the forward (Eqs. 7-14); the adjoint is this library's. */
 gwl_status gwl_sigma_c_vjp(gwl_ctx* ctx, const int* qp_states, int n_qp,
                            const double* omega_ev, int n_omega, double eta_ev, int n_lanczos,
                            const double* grad_sigma, double* sigma_out,
-                           double* grad_energies, double* grad_orbitals);
+                           double* grad_energies, void* grad_orbitals);
+
+/* The same derivative for the partial sum over n in [n_begin, n_end) that
+ * gwl_sigma_c_range returns (gwl_sigma_c_vjp is the range [0, n_orb)):
+ * l = sum_{q,w} Re(conj(G_qw) sum_{n_begin <= n < n_end} Sigma_qq(w, n)).
+ * Arguments, outputs and errors as gwl_sigma_c_vjp, plus GWL_EINVAL unless
+ * 0 <= n_begin < n_end <= n_orb. */
+gwl_status gwl_sigma_c_range_vjp(gwl_ctx* ctx, const int* qp_states, int n_qp, int n_begin,
+                                 int n_end, const double* omega_ev, int n_omega, double eta_ev,
+                                 int n_lanczos, const double* grad_sigma, double* sigma_out,
+                                 double* grad_energies, void* grad_orbitals);
 
 /* ---- component entry points (the steps of the path, for parity checks) ---- */
 
@@ -370,11 +386,12 @@ enum {
   GWL_KEY_TUNED_TILE = 31,      /* query: second-GEMM block tile (128 or 256) chosen by the
                                    autotuner with GWL_KEY_TUNED_BLOCK (the mixed product
                                    picks it unless GWL_KEY_BF16_TILE was set), 0 before */
-  GWL_KEY_ADJOINT_STORE = 32,   /* set/query: 1 (default) = gwl_sigma_c_vjp keeps every
-                                   Lanczos step's Chebyshev iterates from its forward when
-                                   they fit in GWL_ADJOINT_STORE_MAX bytes and that much
-                                   device memory can be allocated; 0 = always recompute
-                                   them from checkpoints.  Both give bitwise the same
+  GWL_KEY_ADJOINT_STORE = 32,   /* set/query: 0 (default) = gwl_sigma_c_vjp recomputes the
+                                   Lanczos vectors from checkpoints every ceil(sqrt(L))
+                                   steps; 1 = it keeps every step's iterates and potentials
+                                   from its forward when they fit in GWL_ADJOINT_STORE_MAX
+                                   bytes and that much device memory can be allocated
+                                   (else it recomputes).  Both give bitwise the same
                                    results. */
   GWL_KEY_ADJOINT_STORED = 33,  /* query: 1 if the last gwl_sigma_c_vjp call kept the
                                    iterates, 0 if it recomputed them, -1 before a call */
@@ -384,9 +401,10 @@ enum {
                                    ended in an invariant subspace) */
 };
 
-/* Device-memory cap for the iterates kept by gwl_sigma_c_vjp: per Lanczos step
- * 2g + 2 vectors of B x N_vc doubles (the iterates t_0..t_g, their coupling
- * parts K Delta^1/2 t_j for j < g, and p_g(C) q_k). */
+/* Device-memory cap for the run kept by gwl_sigma_c_vjp with
+ * GWL_KEY_ADJOINT_STORE: per Lanczos step 2g + 2 vectors of B x N_vc doubles
+ * (the iterates t_0..t_g, their coupling parts K Delta^1/2 t_j for j < g, and
+ * p_g(C) q_k) and g x B Hartree potentials on the grid. */
 #define GWL_ADJOINT_STORE_MAX (32ull << 30)
 /* The autotuner runs on the first gwl_sigma_c / gwl_sigma_c_range /
  * gwl_lanczos_pairs call with block = 0: it times one C-product for

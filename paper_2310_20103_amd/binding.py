@@ -63,6 +63,7 @@ _SIGS = {
     "gwl_lanczos_pairs": (_I, [_P, _P, _P, _P, _I, _P, _P, _P, _P, _I]),
     "gwl_sigma_from_coeffs": (_I, [_P, _P, _I, _P, _P, _P, _P, _I, _P, _I, _D, _P]),
     "gwl_sigma_c_vjp": (_I, [_P, _P, _I, _P, _I, _D, _I, _P, _P, _P, _P]),
+    "gwl_sigma_c_range_vjp": (_I, [_P, _P, _I, _I, _I, _P, _I, _D, _I, _P, _P, _P, _P]),
     "gwl_poisson": (_I, [_P, _P, _P, _I, _I]),
     "gwl_apply_c": (_I, [_P, _P, _P, _I, _I]),
     "gwl_apply_d": (_I, [_P, _P, _P, _I, _I]),
@@ -188,6 +189,7 @@ class Context:
                            ct.byref(op), ct.byref(self._h)))
         del keep
         self.n_orb, self.n_occ = int(n_orb), int(n_occ)
+        self.orb_itemsize = int(dt)
         self.n_emp = self.n_orb - self.n_occ
         self.n_vc = self.n_occ * self.n_emp
         self.grid = (nx, ny, nz)
@@ -296,10 +298,12 @@ class Context:
         return out[..., 0] + 1j * out[..., 1]
 
     def sigma_c_vjp(self, qp_states, omega_ev, eta_ev: float, n_lanczos: int, grad_sigma,
-                    device="cuda"):
+                    device="cuda", n_range=None):
         """Reverse-mode derivative of l = sum Re(conj(G) Sigma): returns
         (Sigma [n_qp, n_omega] complex eV, dl/d energies [n_orb] per eV,
-        dl/d orbitals torch float64 [n_orb, N_r] on the device)."""
+        dl/d orbitals [n_orb, N_r] on the device, in the orbitals' dtype).
+        n_range = (n_begin, n_end) differentiates the partial n-sum of
+        sigma_c_range instead."""
         import torch
         q = _i32(qp_states)
         om = _f64(omega_ev)
@@ -307,11 +311,18 @@ class Context:
         g2 = np.ascontiguousarray(np.stack([G.real, G.imag], axis=-1))
         sig = np.zeros((len(q), len(om), 2))
         ge = np.zeros(self.n_orb)
-        go = torch.empty((self.n_orb, self.n_r), dtype=torch.float64, device=device)
+        gdt = torch.float64 if self.orb_itemsize == 8 else torch.float32
+        go = torch.empty((self.n_orb, self.n_r), dtype=gdt, device=device)
         _sync_torch()
-        _check(lib().gwl_sigma_c_vjp(self._h, _ptr(q), len(q), _ptr(om), len(om), float(eta_ev),
-                                     int(n_lanczos), _ptr(g2), _ptr(sig), _ptr(ge),
-                                     _dev(go, torch.float64)))
+        if n_range is None:
+            _check(lib().gwl_sigma_c_vjp(self._h, _ptr(q), len(q), _ptr(om), len(om),
+                                         float(eta_ev), int(n_lanczos), _ptr(g2), _ptr(sig),
+                                         _ptr(ge), _dev(go, gdt)))
+        else:
+            _check(lib().gwl_sigma_c_range_vjp(self._h, _ptr(q), len(q), int(n_range[0]),
+                                               int(n_range[1]), _ptr(om), len(om),
+                                               float(eta_ev), int(n_lanczos), _ptr(g2),
+                                               _ptr(sig), _ptr(ge), _dev(go, gdt)))
         return sig[..., 0] + 1j * sig[..., 1], ge, go
 
     def lanczos_pairs(self, m_idx, n_idx, lengths, ld: Optional[int] = None):

@@ -237,7 +237,8 @@ lzb_step_kernel(int k, const int* __restrict__ pair_of_slot, const int* __restri
 
 // Start vector: q_0 = P/|P|, N = |P|^2; P = (nm|vc) Delta^1/2.
 // P_bar = (q_bar_0 - q_0 (q_0 . q_bar_0)) / |P| + 2 N_bar P;
-// Delta_bar += P_bar P / (2 Delta);  k_bar = P_bar Delta^1/2 (row of the pair).
+// Delta_bar += P_bar P / (2 Delta);  k_bar = P_bar Delta^1/2 (row of the slot;
+// zero for an empty slot or a zero start vector).
 __global__ void __launch_bounds__(NT)
 lzb_start_kernel(const int* __restrict__ pair_of_slot, const double* __restrict__ norm2,
                  const double* __restrict__ nbar, const double* __restrict__ P,
@@ -247,11 +248,10 @@ lzb_start_kernel(const int* __restrict__ pair_of_slot, const double* __restrict_
   __shared__ double sh[NT / 64];
   const int b = blockIdx.x;
   const int p = pair_of_slot[b];
-  if (p < 0) return;
   const long o = (long)b * nvc;
-  const double N = norm2[p];
+  const double N = p >= 0 ? norm2[p] : 0.0;
   if (!(N > 0.0)) {
-    for (long i = threadIdx.x; i < nvc; i += NT) kbar[(long)p * nvc + i] = 0.0;
+    for (long i = threadIdx.x; i < nvc; i += NT) kbar[o + i] = 0.0;
     return;
   }
   const double s = sqrt(N), is = 1.0 / s;
@@ -263,7 +263,7 @@ lzb_start_kernel(const int* __restrict__ pair_of_slot, const double* __restrict_
     const double pi = P[o + i];
     const double pbar = (qb0[o + i] - pi * is * d) * is + nb2 * pi;
     dbar[o + i] += pbar * pi / (2.0 * sdelta[i] * sdelta[i]);
-    kbar[(long)p * nvc + i] = pbar * sdelta[i];
+    kbar[o + i] = pbar * sdelta[i];
   }
 }
 
@@ -296,24 +296,6 @@ __global__ void combine_adj_kernel(PairGeom g, int nb, int splitk, const double*
   }
 }
 
-// Per Chebyshev term j: Delta_bar += alpha [2 Delta s t + (s K~t + t K~s)/Delta^1/2]
-// and the rows U = kappa Delta^1/2 s, V = Delta^1/2 t of the K_bar update.
-__global__ void dbar_uv_kernel(PairGeom g, int nb, const double* __restrict__ s,
-                               const double* __restrict__ ks, const double* __restrict__ t,
-                               const double* __restrict__ kt, double alpha, double kappa,
-                               double* __restrict__ dbar, double* __restrict__ U,
-                               double* __restrict__ V) {
-  const int b = blockIdx.y;
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < g.nvc; i += (long)gridDim.x * blockDim.x) {
-    const long o = (long)b * g.nvc + i;
-    const double sd = g.sdelta[i];
-    const double si = s[o], ti = t[o];
-    dbar[o] += alpha * (2.0 * sd * sd * si * ti + (si * kt[o] + ti * ks[o]) / sd);
-    U[o] = kappa * sd * si;
-    V[o] = sd * ti;
-  }
-}
-
 __global__ void scale_copy_kernel(double* __restrict__ dst, const double* __restrict__ src,
                                   double c, long n) {
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
@@ -337,46 +319,6 @@ __global__ void sum_rows_kernel(double* __restrict__ dst, const double* __restri
 }
 
 // S = A + A^T for an n x n matrix
-__global__ void symmetrize_kernel(double* __restrict__ S, const double* __restrict__ A, long n) {
-  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n * n; e += (long)gridDim.x * blockDim.x) {
-    const long i = e / n, j = e - i * n;
-    S[e] = A[e] + A[j * n + i];
-  }
-}
-
-// Pair densities phi_v phi_c for pairs q0 .. q0 + cnt - 1
-__global__ void pair_density_kernel(const double* __restrict__ psi_t, long ld, int nv, int nc,
-                                    int nvp, long q0, double* __restrict__ rho) {
-  const int i = blockIdx.y;
-  const long q = q0 + i;
-  const int v = (int)(q / nc), c = (int)(q - (long)v * nc);
-  const double* a = psi_t + (long)v * ld;
-  const double* bb = psi_t + (long)(nvp + c) * ld;
-  double* o = rho + (long)i * ld;
-  for (long r = blockIdx.x * (long)blockDim.x + threadIdx.x; r < ld; r += (long)gridDim.x * blockDim.x)
-    o[r] = a[r] * bb[r];
-}
-
-// grad_v(r) = dV sum_c phi_c(r) W[(v,c)][r];  grad_c(r) = dV sum_v phi_v(r) W[(v,c)][r]
-__global__ void orb_grad_vc_kernel(const double* __restrict__ psi_t, const double* __restrict__ W,
-                                   long ld, int nr, int nv, int nc, int nvp, double dv,
-                                   double* __restrict__ grad) {
-  const int a = blockIdx.y;  // orbital (0..nv-1 occupied, nv.. empty)
-  for (long r = blockIdx.x * (long)blockDim.x + threadIdx.x; r < nr; r += (long)gridDim.x * blockDim.x) {
-    double s = 0.0;
-    if (a < nv) {
-      for (int c = 0; c < nc; ++c)
-        s += psi_t[(long)(nvp + c) * ld + r] * W[((long)a * nc + c) * ld + r];
-      grad[(long)a * ld + r] += dv * s;
-    } else {
-      const int c = a - nv;
-      for (int v = 0; v < nv; ++v)
-        s += psi_t[(long)v * ld + r] * W[((long)v * nc + c) * ld + r];
-      grad[(long)(nvp + c) * ld + r] += dv * s;
-    }
-  }
-}
-
 // grad_n += dV phi_m Vk_p, grad_m += dV phi_n Vk_p for every pair p, in pair order
 __global__ void orb_grad_nm_kernel(const double* __restrict__ psi_t, const double* __restrict__ Vk,
                                    long ld, int nr, const int* __restrict__ mrow,
@@ -392,13 +334,15 @@ __global__ void orb_grad_nm_kernel(const double* __restrict__ psi_t, const doubl
   }
 }
 
-// user layout [n_orb][nr] from the internal padded [nvp + ncp][ld]
+// user layout [n_orb][nr] from the internal padded [nvp + ncp][ld], in the
+// orbitals' own type
+template <typename T>
 __global__ void gather_orbitals_kernel(const double* __restrict__ src, long ld, int nr, int nv,
-                                       int nvp, double* __restrict__ dst) {
+                                       int nvp, T* __restrict__ dst) {
   const int a = blockIdx.y;
   const long row = a < nv ? a : nvp + (a - nv);
   for (long r = blockIdx.x * (long)blockDim.x + threadIdx.x; r < nr; r += (long)gridDim.x * blockDim.x)
-    dst[(long)a * nr + r] = src[row * ld + r];
+    dst[(long)a * nr + r] = (T)src[row * ld + r];
 }
 
 inline int gelems(long n) {
@@ -448,14 +392,6 @@ void adj_combine(const PairGeom& g, int nb, int splitk, const double* ypart, con
   GWL_HIP(hipGetLastError());
 }
 
-void adj_dbar_uv(const PairGeom& g, int nb, const double* s, const double* ks, const double* t,
-                 const double* kt, double alpha, double kappa, double* dbar, double* U,
-                 double* V, hipStream_t st) {
-  dim3 grid(gelems(g.nvc), nb);
-  dbar_uv_kernel<<<grid, NT, 0, st>>>(g, nb, s, ks, t, kt, alpha, kappa, dbar, U, V);
-  GWL_HIP(hipGetLastError());
-}
-
 void adj_scale_copy(double* dst, const double* src, double c, long n, hipStream_t st) {
   scale_copy_kernel<<<gelems(n), NT, 0, st>>>(dst, src, c, n);
   GWL_HIP(hipGetLastError());
@@ -471,25 +407,6 @@ void adj_sum_rows(double* dst, const double* src, int nrows, long n, hipStream_t
   GWL_HIP(hipGetLastError());
 }
 
-void adj_symmetrize(double* S, const double* A, long n, hipStream_t st) {
-  symmetrize_kernel<<<gelems(n * n), NT, 0, st>>>(S, A, n);
-  GWL_HIP(hipGetLastError());
-}
-
-void adj_pair_density(const double* psi_t, long ld, int nv, int nc, int nvp, long q0, int cnt,
-                      double* rho, hipStream_t st) {
-  if (cnt <= 0) return;
-  pair_density_kernel<<<dim3(gelems(ld), cnt), NT, 0, st>>>(psi_t, ld, nv, nc, nvp, q0, rho);
-  GWL_HIP(hipGetLastError());
-}
-
-void adj_orb_grad_vc(const double* psi_t, const double* W, long ld, int nr, int nv, int nc,
-                     int nvp, double dv, double* grad, hipStream_t st) {
-  orb_grad_vc_kernel<<<dim3(gelems(nr), nv + nc), NT, 0, st>>>(psi_t, W, ld, nr, nv, nc, nvp, dv,
-                                                               grad);
-  GWL_HIP(hipGetLastError());
-}
-
 void adj_orb_grad_nm(const double* psi_t, const double* Vk, long ld, int nr, const int* mrow,
                      const int* nrow, int npairs, double dv, double* grad, hipStream_t st) {
   orb_grad_nm_kernel<<<gelems(nr), NT, 0, st>>>(psi_t, Vk, ld, nr, mrow, nrow, npairs, dv, grad);
@@ -497,8 +414,14 @@ void adj_orb_grad_nm(const double* psi_t, const double* Vk, long ld, int nr, con
 }
 
 void adj_gather_orbitals(const double* src, long ld, int nr, int nv, int nvp, int norb,
-                         double* dst, hipStream_t st) {
-  gather_orbitals_kernel<<<dim3(gelems(nr), norb), NT, 0, st>>>(src, ld, nr, nv, nvp, dst);
+                         void* dst, bool f32, hipStream_t st) {
+  const dim3 grid(gelems(nr), norb);
+  if (f32)
+    gather_orbitals_kernel<float><<<grid, NT, 0, st>>>(src, ld, nr, nv, nvp,
+                                                       static_cast<float*>(dst));
+  else
+    gather_orbitals_kernel<double><<<grid, NT, 0, st>>>(src, ld, nr, nv, nvp,
+                                                        static_cast<double*>(dst));
   GWL_HIP(hipGetLastError());
 }
 

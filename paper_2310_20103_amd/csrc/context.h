@@ -137,7 +137,8 @@ struct gwl_ctx {
   bool tile_fixed = false;  // set by the caller: the autotuner keeps it
   int tda = 0;          // 1: Tamm-Dancoff (Lanczos on A = Delta + K from (nm|vc))
   int quadrature = 0;   // 1: Lanczos on C + Gauss quadrature (no polynomial)
-  int adjoint_store = 1;     // 1: the adjoint keeps the forward's iterates when they fit
+  int adjoint_store = 0;     // 1: the adjoint keeps the forward's iterates when they fit
+  int orb_dtype = 8;         // 8 = FP64 orbitals were given, 4 = FP32
   int adjoint_stored = -1;   // what the last adjoint call did (-1: no call yet)
   bool poly_hi_auto = false;  // the interval's upper end is estimated (re-done for ISDF)
   double hi_resid = 0.0;      // residual bound of the last estimate's largest Ritz value
@@ -381,7 +382,9 @@ struct gwl_ctx {
   void middle_step(int nb, int prec, int nvt, const void* rho_in, void* v_out);
 
   // ypart <- second GEMM of K applied to u (u already cast for nb vectors).
-  void k_product(int nb, int prec, int S) {
+  // FP64: the Hartree potentials of the nb densities go to vout64 [nb][N_rp]
+  // when given (kept by the adjoint), else to vpot64.
+  void k_product(int nb, int prec, int S, double* vout64 = nullptr) {
     hipStream_t st = stream;
     const bool is = isdf_on;
     // On N_mu points the 16-bit operand rounding of the second GEMM averages
@@ -392,7 +395,7 @@ struct gwl_ctx {
     if (prec == GWL_FP64) {
       const double* uu = u64.p;
       double* rp = reinterpret_cast<double*>(rho.p);
-      double* vp = vpot64.p;
+      double* vp = vout64 ? vout64 : vpot64.p;
       double* yp = reinterpret_cast<double*>(ypart.p);
       const double* crc = is ? ipsi_c_rc64.p : psi_c_rc64.p;
       const double* vrv = is ? ipsi_v_rv64.p : psi_v_rv64.p;
@@ -457,6 +460,24 @@ struct gwl_ctx {
         gemm2_bf16s(d, nb, S, pv, pc, vp, yp, st);
       prof_end(1, nb);
     }
+  }
+
+  // vout [nb][N_rp] <- Hartree potentials of the densities rho_b(r) =
+  // sum_vc phi_v(r) phi_c(r) u_b[v][c] of the FP64 operands already in u64
+  // (the first half of the K product, on the grid).
+  void potential64(int nb, double* vout) {
+    const GemmDims& d = gd;
+    double* rp = reinterpret_cast<double*>(rho.p);
+    int nvt;
+    if (fp64_kernel) {
+      gemm1_f64m(d, nb, psi_c_rc64.p, psi_v_rv64.p, u64.p, rp, stream);
+      nvt = gemm1_f64m_vtiles(d);
+    } else {
+      gemm1_f64(d, nb, psi_c_rc64.p, psi_v_rv64.p, u64.p, rp, stream);
+      nvt = gemm1_f64_vtiles(d);
+    }
+    poisson_launch<double>(pg64, rp, d.nrp, (long)nb * d.nrp, nvt, vout, d.nrp, nb,
+                           reinterpret_cast<cplx<double>*>(fftx.p), stream);
   }
 
   void cast(int nb, const double* x, int prec, bool a_op = false) {

@@ -169,6 +169,7 @@ gwl_status gwl_setup(const void* orbitals, int orb_dtype, int orb_on_device, int
     c.lz = grid->lz;
     c.nr = (long)c.nx * c.ny * c.nz;
     c.n_orb = n_orb;
+    c.orb_dtype = orb_dtype;
     c.nv = n_occ;
     c.nc = n_orb - n_occ;
     c.nvc = (long)c.nv * c.nc;

@@ -231,20 +231,35 @@ void adj_start(int nb, const int* pair_of_slot, const double* norm2, const doubl
 void adj_combine(const PairGeom& g, int nb, int splitk, const double* ypart, const double* sj,
                  const double* sj1, const double* seed, double cprev, double sigma, double lo,
                  double hi, double* out, double* ks, double* u, hipStream_t st);
-void adj_dbar_uv(const PairGeom& g, int nb, const double* s, const double* ks, const double* t,
-                 const double* kt, double alpha, double kappa, double* dbar, double* U,
-                 double* V, hipStream_t st);
 void adj_scale_copy(double* dst, const double* src, double c, long n, hipStream_t st);
 void adj_axpy(double* dst, const double* src, double a, long n, hipStream_t st);
 void adj_sum_rows(double* dst, const double* src, int nrows, long n, hipStream_t st);
-void adj_symmetrize(double* S, const double* A, long n, hipStream_t st);
-void adj_pair_density(const double* psi_t, long ld, int nv, int nc, int nvp, long q0, int cnt,
-                      double* rho, hipStream_t st);
-void adj_orb_grad_vc(const double* psi_t, const double* W, long ld, int nr, int nv, int nc,
-                     int nvp, double dv, double* grad, hipStream_t st);
 void adj_orb_grad_nm(const double* psi_t, const double* Vk, long ld, int nr, const int* mrow,
                      const int* nrow, int npairs, double dv, double* grad, hipStream_t st);
+// user layout [n_orb][nr] (FP32 if f32, else FP64) from the padded [nvp + ncp][ld]
 void adj_gather_orbitals(const double* src, long ld, int nr, int nv, int nvp, int norb,
-                         double* dst, hipStream_t st);
+                         void* dst, bool f32, hipStream_t st);
+
+// Factored orbital gradient of pair-vector outer products (adj_zgemm.hip).
+// A segment pairs k potentials vf [k][N_rp] with k padded pair vectors
+// u [k][N_vp][N_cp]; with Z(r, v, c) = sum over both segments of vf(r) u(v, c):
+//   grad_c[c][r] += dv sum_v phi_v(r) Z(r, v, c)          (rows [N_cp][N_rp])
+//   gvpart[ct][v][r] += dv sum_{c in tile ct} phi_c(r) Z   (ct = c / 64)
+struct ZSeg {
+  const double* vf;
+  const double* u;
+  int k;
+};
+void adj_zgemm(const GemmDims& d, int nv, const ZSeg& s0, const ZSeg& s1, const double* psi_c_rc,
+               const double* psi_v_rv, double dv, double* grad_c, double* gvpart,
+               hipStream_t st);
+// grad_v[v][r] += sum over the nct c tiles, in order, of gvpart[ct][v][r]
+void adj_gv_reduce(const double* gvpart, int nct, int nv, long nrp, double* grad_v,
+                   hipStream_t st);
+// Per Chebyshev term: Delta_bar += alpha [2 Delta s t + (s K~t + t K~s)/Delta^1/2]
+// and the padded operands us = kappa Delta^1/2 s, ut = kappa Delta^1/2 t.
+void adj_dbar_zops(const PairGeom& g, int nb, const double* s, const double* ks, const double* t,
+                   const double* kt, double alpha, double kappa, double* dbar, double* us,
+                   double* ut, hipStream_t st);
 
 }  // namespace gwl

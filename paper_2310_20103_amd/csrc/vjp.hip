@@ -1,54 +1,40 @@
 // Vector-Jacobian product of Sigma_c (gwl_sigma_c_vjp).
 //
 // Forward: the same path as gwl_sigma_c in FP64 without reorthogonalisation
-// (so the recurrence can be recomputed exactly).  When they fit in
-// GWL_ADJOINT_STORE_MAX, every step's Chebyshev iterates t_j (t_0 = q_k),
-// coupling parts K Delta^1/2 t_j and w_k = p_g(C) q_k are kept from the
-// forward; otherwise the forward checkpoints (q_{k-1}, q_k) and the slot state
-// every ceil(sqrt(L)) steps, and the backward recomputes, segment by segment
-// (last first), the Lanczos vectors from the checkpoint and then, per step,
-// the product with its iterates (two more p_g(C) products per step; the same
-// kernels in the same order, so both routes agree bitwise).  Backward, per
-// block of start vectors: continued-fraction adjoint; then for each step k
-// (last first) the reverse Lanczos step gives w_bar_k, and the reverse
-// Chebyshev recurrence
-// applied to w_bar_k gives D w_bar_k (added to q_bar_k) together with the
-// outer products s_j t_{j-1}^T that make up C_bar.  C_bar is pushed into
-// Delta_bar directly and into a dense K_bar; the coupling vectors' adjoint
-// gives Delta_bar and k_bar.  At the end K_bar and k_bar are contracted with
-// the pair potentials V[phi_v phi_c] (plain rocBLAS GEMMs) into the orbital
-// gradient, and Delta_bar into the energy gradient.
-#include <rocblas/rocblas.h>
-
+// (so the recurrence can be recomputed exactly), in segments of S_L steps.
+// By default S_L = ceil(sqrt(L)): the forward keeps only (q_{k-1}, q_k) and the
+// slot state at each segment start, and the backward recomputes one segment
+// at a time (last first), keeping for each of its steps the Chebyshev
+// iterates t_0..t_g of p_g(C) q_k, their coupling parts K Delta^1/2 t_j, the
+// product w_k and the Hartree potentials V[rho(Delta^1/2 t_j)] that the FFT
+// Poisson solve forms inside each C-product.  With GWL_KEY_ADJOINT_STORE the
+// whole run is one segment kept by the forward itself when it fits.
+//
+// Backward, per block of start vectors: continued-fraction adjoint; then for
+// each step k (last first) the reverse Lanczos step gives w_bar_k, and the
+// reverse Chebyshev recurrence applied to w_bar_k gives D w_bar_k (added to
+// q_bar_k) together with the outer products s_j t_{j-1}^T that make up C_bar.
+// C_bar goes into Delta_bar at once; its coupling part goes into the orbital
+// gradient at once through the factored contraction of adj_zgemm, which pairs
+// each pair vector with the potential of its partner (no N_vc x N_vc
+// cotangent, no per-pair potentials on the grid).  The start vectors'
+// adjoint gives Delta_bar and k_bar, whose orbital terms go the same way
+// (k_bar with V[phi_n phi_m], and V[rho(k_bar)] with phi_m and phi_n).
 #include "context.h"
+
+using namespace gwl;
 
 namespace {
 
-#define GWL_BLAS(call)                                                           \
-  do {                                                                           \
-    rocblas_status s_ = (call);                                                  \
-    if (s_ != rocblas_status_success)                                            \
-      throw ::gwl::Error{GWL_EDEVICE, std::string(#call) + ": rocblas status " + \
-                                          std::to_string((int)s_)};              \
-  } while (0)
-
-struct Blas {
-  rocblas_handle h = nullptr;
-  ~Blas() {
-    if (h) (void)rocblas_destroy_handle(h);
-  }
-};
-
-}  // namespace
-
-extern "C" gwl_status gwl_sigma_c_vjp(gwl_ctx* ctx, const int* qp_states, int n_qp,
-                                      const double* omega_ev, int n_omega, double eta_ev,
-                                      int n_lanczos, const double* grad_sigma,
-                                      double* sigma_out, double* grad_energies,
-                                      double* grad_orbitals) {
+gwl_status vjp_range(gwl_ctx* ctx, const int* qp_states, int n_qp, int n_begin, int n_end,
+                     const double* omega_ev, int n_omega, double eta_ev, int n_lanczos,
+                     const double* grad_sigma, double* sigma_out, double* grad_energies,
+                     void* grad_orbitals) {
   try {
     GWL_CHECK(ctx != nullptr, GWL_EINVAL, "null context");
     gwl_ctx& c = *ctx;
+    GWL_CHECK(0 <= n_begin && n_begin < n_end && n_end <= c.n_orb, GWL_EINVAL,
+              "need 0 <= n_begin < n_end <= n_orb");
     GWL_CHECK(!c.tda && !c.quadrature && !c.isdf_on, GWL_EUNSUPPORTED,
               "the adjoint covers the polynomial method on the grid only (not Tamm-Dancoff, "
               "quadrature or ISDF)");
@@ -66,9 +52,8 @@ extern "C" gwl_status gwl_sigma_c_vjp(gwl_ctx* ctx, const int* qp_states, int n_
     const long nvc = c.nvc;
     const int g = c.poly_degree;
     const int L = n_lanczos;
-    const int P = n_qp * c.n_orb;
-    GWL_CHECK((double)nvc * nvc * 8 < 64e9, GWL_EUNSUPPORTED,
-              "adjoint holds the dense coupling cotangent: N_vc too large");
+    const int nn = n_end - n_begin;
+    const int P = n_qp * nn;
     hipStream_t st = c.stream;
     const int saved_prec = c.precision, saved_reorth = c.reorth;
     c.precision = GWL_FP64;
@@ -85,19 +70,21 @@ extern "C" gwl_status gwl_sigma_c_vjp(gwl_ctx* ctx, const int* qp_states, int n_
     const int B = std::max(1, std::min(P, c.block > 0 ? c.block : 64));
     c.ensure_work(B, L, false);
     const int S = c.auto_splitk(B, GWL_FP64);
-    const int seg = std::max(1, (int)std::ceil(std::sqrt((double)L)));
-    const int nseg = (L + seg - 1) / seg;
     PairGeom pg = c.pair_geom();
+    const GemmDims& d = c.kd();
     const double lo = c.poly_lo, hi = c.poly_hi;
     const size_t vec = (size_t)B * nvc;
+    const size_t fld = (size_t)B * d.nrp;             // B potentials on the padded grid
+    const size_t uvp = (size_t)B * d.nvp * d.ncp;     // B padded pair vectors
+    const int nct = d.ncp / 64;
 
     // pair list (m, n), qp index per pair
-    std::vector<int> m(P), n(P), q(P), len(P, L);
+    std::vector<int> m(P), n(P), q(P);
     for (int a = 0; a < n_qp; ++a)
-      for (int j = 0; j < c.n_orb; ++j) {
-        const int p = a * c.n_orb + j;
+      for (int j = 0; j < nn; ++j) {
+        const int p = a * nn + j;
         m[p] = qp_states[a];
-        n[p] = j;
+        n[p] = n_begin + j;
         q[p] = a;
       }
     std::vector<double> en(P), et(P), om(n_omega);
@@ -107,46 +94,51 @@ extern "C" gwl_status gwl_sigma_c_vjp(gwl_ctx* ctx, const int* qp_states, int n_
     }
     for (int i = 0; i < n_omega; ++i) om[i] = omega_ev[i] / kHartreeEv;
 
-    // buffers
-    DevBuf<double> Pb, ckq, ckqp, segq, T, KT, Sv, KS, U, V, wk, wbar, qb0, qb1, qb2, pend, dbar,
-        dbar_tot, Kbar, kbar, abar, bbar, nbar, ebar, sig, Gd, e_d, eta_d, om_d, grad_int;
-    DevBuf<int> ck_state, qidx_d, slot_pair, mrow_d, nrow_d, flen;
-    DevBuf<double> ck_amax, ck_bprev;
-    DevBuf<unsigned char> tscr;
-    Pb.ensure(vec);
-    // kept iterates per step k: t_0..t_g, K~t_0..K~t_{g-1}, w_k; then q_L and q_{-1}
-    const size_t per_step = (size_t)(2 * g + 2) * vec;
-    bool store = c.adjoint_store &&
-                 ((size_t)L * per_step + 2 * vec) * sizeof(double) <= GWL_ADJOINT_STORE_MAX;
-    DevBuf<double> It;
-    if (store) {
+    // ---- segment store: per step t_0..t_g, K~t_0..K~t_{g-1}, w_k, V[t_0..t_{g-1}]
+    const size_t per_step = (size_t)(2 * g + 2) * vec + (size_t)g * fld;
+    int seg = std::max(1, (int)std::ceil(std::sqrt((double)L)));
+    DevBuf<double> store;
+    bool whole = false;
+    if (c.adjoint_store && seg < L &&
+        ((size_t)L * per_step + 2 * vec) * sizeof(double) <= GWL_ADJOINT_STORE_MAX) {
       try {
-        It.ensure((size_t)L * per_step + 2 * vec);
+        store.ensure((size_t)L * per_step + 2 * vec);
+        whole = true;
+        seg = L;
       } catch (const Error& e) {
         // not enough free device memory: recompute from checkpoints instead
         if (e.code != GWL_ENOMEM) throw;
         (void)hipGetLastError();
-        store = false;
       }
     }
-    c.adjoint_stored = store ? 1 : 0;
-    if (!store) {
+    if (seg >= L) whole = true, seg = L;
+    if (!store.p) store.ensure((size_t)seg * per_step + 2 * vec);
+    c.adjoint_stored = whole ? 1 : 0;
+    const int nseg = (L + seg - 1) / seg;
+    double* const sq_end = store.p + (size_t)seg * per_step;  // q after the segment's last step
+    double* const sq_prev0 = sq_end + vec;                     // q_{k0-1} of the segment
+    auto step_ptr = [&](int kk) { return store.p + (size_t)kk * per_step; };
+
+    // buffers
+    DevBuf<double> Pb, Vnm, ckq, ckqp, Sv, KS, VS, US, UT, wbar, qb0, qb1, qb2, pend, dbar,
+        dbar_tot, kbar, abar, bbar, nbar, ebar, sig, Gd, e_d, eta_d, om_d, grad_int, gvpart;
+    DevBuf<int> ck_state, qidx_d, slot_pair, mrow_d, nrow_d, flen;
+    DevBuf<double> ck_amax, ck_bprev;
+    DevBuf<unsigned char> tscr;
+    Pb.ensure(vec);
+    Vnm.ensure(fld);
+    if (nseg > 1) {
       ckq.ensure((size_t)nseg * vec);
       ckqp.ensure((size_t)nseg * vec);
       ck_state.ensure((size_t)nseg * 2 * B);
       ck_amax.ensure((size_t)nseg * B);
       ck_bprev.ensure((size_t)nseg * B);
-      segq.ensure((size_t)(seg + 1) * vec);
-      T.ensure((size_t)(g + 1) * vec);
-      KT.ensure((size_t)g * vec);
-      wk.ensure(vec);
     }
-    double* const q_last = store ? It.p + (size_t)L * per_step : nullptr;
-    double* const q_m1 = store ? q_last + vec : nullptr;
     Sv.ensure((size_t)(g + 1) * vec);
     KS.ensure((size_t)(g + 1) * vec);
-    U.ensure((size_t)g * vec);
-    V.ensure((size_t)g * vec);
+    VS.ensure((size_t)g * fld);
+    US.ensure((size_t)g * uvp);
+    UT.ensure((size_t)g * uvp);
     wbar.ensure(vec);
     qb0.ensure(vec);
     qb1.ensure(vec);
@@ -154,8 +146,7 @@ extern "C" gwl_status gwl_sigma_c_vjp(gwl_ctx* ctx, const int* qp_states, int n_
     pend.ensure(B);
     dbar.ensure(vec);
     dbar_tot.ensure(nvc);
-    Kbar.ensure((size_t)nvc * nvc);
-    kbar.ensure((size_t)P * nvc);
+    kbar.ensure(vec);
     abar.ensure((size_t)P * L);
     bbar.ensure((size_t)P * L);
     nbar.ensure(P);
@@ -168,18 +159,23 @@ extern "C" gwl_status gwl_sigma_c_vjp(gwl_ctx* ctx, const int* qp_states, int n_
     qidx_d.ensure(P);
     flen.ensure(P);
     slot_pair.ensure(B);
+    mrow_d.ensure(P);
+    nrow_d.ensure(P);
     tscr.ensure((size_t)B * L * n_omega * 16);
-    grad_int.ensure((size_t)(c.gd.nvp + c.gd.ncp) * c.gd.nrp);
+    grad_int.ensure((size_t)(d.nvp + d.ncp) * d.nrp);
+    gvpart.ensure((size_t)nct * c.nv * d.nrp);
+    std::vector<int> mr(P), nr_(P);
+    for (int p = 0; p < P; ++p) {
+      mr[p] = c.orb_row(m[p]);
+      nr_[p] = c.orb_row(n[p]);
+    }
     GWL_HIP(hipMemcpy(Gd.p, grad_sigma, sizeof(double) * n_qp * n_omega * 2, hipMemcpyHostToDevice));
     GWL_HIP(hipMemcpy(e_d.p, en.data(), sizeof(double) * P, hipMemcpyHostToDevice));
     GWL_HIP(hipMemcpy(eta_d.p, et.data(), sizeof(double) * P, hipMemcpyHostToDevice));
     GWL_HIP(hipMemcpy(om_d.p, om.data(), sizeof(double) * n_omega, hipMemcpyHostToDevice));
     GWL_HIP(hipMemcpy(qidx_d.p, q.data(), sizeof(int) * P, hipMemcpyHostToDevice));
-
-    Blas blas;
-    GWL_BLAS(rocblas_create_handle(&blas.h));
-    GWL_BLAS(rocblas_set_stream(blas.h, st));
-    const double one = 1.0, zero = 0.0;
+    GWL_HIP(hipMemcpy(mrow_d.p, mr.data(), sizeof(int) * P, hipMemcpyHostToDevice));
+    GWL_HIP(hipMemcpy(nrow_d.p, nr_.data(), sizeof(int) * P, hipMemcpyHostToDevice));
 
     c.coef_a.ensure((size_t)P * L);
     c.coef_b.ensure((size_t)P * L);
@@ -207,12 +203,13 @@ extern "C" gwl_status gwl_sigma_c_vjp(gwl_ctx* ctx, const int* qp_states, int n_
       lz_beta(ss, B, c.q.p, c.qprev.p, c.w.p, nullptr, 0, 0, nvc, st);
     };
     // w = p_g(C) t_0 for the vectors t_0 = Ti[0], keeping the iterates
-    // t_1..t_g in Ti[1..g] and K~t_j = K Delta^1/2 t_j in KTi[0..g-1]
-    // (the same launches as Context::apply_d_batch, plus the K~t_j output)
-    auto cheb_iterates = [&](double* Ti, double* KTi, double* w) {
+    // t_1..t_g in Ti[1..g], K~t_j = K Delta^1/2 t_j in KTi[0..g-1] and the
+    // potentials V[rho(Delta^1/2 t_j)] in VTi[j] (the same launches as
+    // Context::apply_d_batch, plus those two outputs)
+    auto cheb_iterates = [&](double* Ti, double* KTi, double* w, double* VTi) {
       c.cast(B, Ti, GWL_FP64);
       for (int j = 0; j < g; ++j) {
-        c.k_product(B, GWL_FP64, S);
+        c.k_product(B, GWL_FP64, S, VTi + (size_t)j * fld);
         combine<double, double>(pg, B, S, reinterpret_cast<const double*>(c.ypart.p),
                                 Ti + (size_t)j * vec, j > 0 ? Ti + (size_t)(j - 1) * vec : nullptr,
                                 Ti + (size_t)(j + 1) * vec, w, j == 0 ? 1 : 2, lo, hi,
@@ -220,16 +217,21 @@ extern "C" gwl_status gwl_sigma_c_vjp(gwl_ctx* ctx, const int* qp_states, int n_
                                 KTi + (size_t)j * vec);
       }
     };
-    // one forward step that keeps its iterates (store route)
-    auto fwd_step_store = [&](int k) {
-      double* Ti = It.p + (size_t)k * per_step;
-      double* KTi = Ti + (size_t)(g + 1) * vec;
-      double* Wi = Ti + (size_t)(2 * g + 1) * vec;
-      GWL_HIP(hipMemcpyAsync(Ti, c.q.p, vec * 8, hipMemcpyDeviceToDevice, st));
-      cheb_iterates(Ti, KTi, Wi);
-      GWL_HIP(hipMemcpyAsync(c.w.p, Wi, vec * 8, hipMemcpyDeviceToDevice, st));
-      lz_alpha(ss, B, c.q.p, c.qprev.p, c.w.p, nvc, st);
-      lz_beta(ss, B, c.q.p, c.qprev.p, c.w.p, nullptr, 0, 0, nvc, st);
+    // steps k0..k1-1 from (qprev, q), keeping each step's iterates in the store
+    auto fwd_segment_store = [&](int k0, int k1) {
+      GWL_HIP(hipMemcpyAsync(sq_prev0, c.qprev.p, vec * 8, hipMemcpyDeviceToDevice, st));
+      for (int k = k0; k < k1; ++k) {
+        double* Ti = step_ptr(k - k0);
+        double* KTi = Ti + (size_t)(g + 1) * vec;
+        double* Wi = Ti + (size_t)(2 * g + 1) * vec;
+        double* VTi = Ti + (size_t)(2 * g + 2) * vec;
+        GWL_HIP(hipMemcpyAsync(Ti, c.q.p, vec * 8, hipMemcpyDeviceToDevice, st));
+        cheb_iterates(Ti, KTi, Wi, VTi);
+        GWL_HIP(hipMemcpyAsync(c.w.p, Wi, vec * 8, hipMemcpyDeviceToDevice, st));
+        lz_alpha(ss, B, c.q.p, c.qprev.p, c.w.p, nvc, st);
+        lz_beta(ss, B, c.q.p, c.qprev.p, c.w.p, nullptr, 0, 0, nvc, st);
+      }
+      GWL_HIP(hipMemcpyAsync(sq_end, c.q.p, vec * 8, hipMemcpyDeviceToDevice, st));
     };
     auto save_state = [&](int sgi) {
       GWL_HIP(hipMemcpyAsync(ckq.p + (size_t)sgi * vec, c.q.p, vec * 8, hipMemcpyDeviceToDevice, st));
@@ -247,6 +249,9 @@ extern "C" gwl_status gwl_sigma_c_vjp(gwl_ctx* ctx, const int* qp_states, int n_
       GWL_HIP(hipMemcpyAsync(c.s_amax.p, ck_amax.p + (size_t)sgi * B, B * 8, hipMemcpyDeviceToDevice, st));
       GWL_HIP(hipMemcpyAsync(c.s_bprev.p, ck_bprev.p + (size_t)sgi * B, B * 8, hipMemcpyDeviceToDevice, st));
     };
+    const double* psi_c_rc = c.psi_c_rc64.p;
+    const double* psi_v_rv = c.psi_v_rv64.p;
+    double* grad_c = grad_int.p + (size_t)d.nvp * d.nrp;
 
     for (int p0 = 0; p0 < P; p0 += B) {
       const int nbk = std::min(B, P - p0);
@@ -265,12 +270,12 @@ extern "C" gwl_status gwl_sigma_c_vjp(gwl_ctx* ctx, const int* qp_states, int n_
       GWL_HIP(hipMemsetAsync(c.q.p, 0, vec * 8, st));
       // ---- forward
       c.coupling_batch(nbk, m.data() + p0, n.data() + p0, c.q.p, nvc);
+      // the coupling build leaves V[phi_n phi_m] of the block in vpot64
+      GWL_HIP(hipMemcpyAsync(Vnm.p, c.vpot64.p, (size_t)nbk * d.nrp * 8, hipMemcpyDeviceToDevice, st));
       GWL_HIP(hipMemcpyAsync(Pb.p, c.q.p, vec * 8, hipMemcpyDeviceToDevice, st));
       lz_start(ss, B, c.s_slots.p, nbk, c.q.p, c.qprev.p, nullptr, 0, nvc, st);
-      if (store) {
-        GWL_HIP(hipMemcpyAsync(q_m1, c.qprev.p, vec * 8, hipMemcpyDeviceToDevice, st));
-        for (int k = 0; k < L; ++k) fwd_step_store(k);
-        GWL_HIP(hipMemcpyAsync(q_last, c.q.p, vec * 8, hipMemcpyDeviceToDevice, st));
+      if (nseg == 1) {
+        fwd_segment_store(0, L);
       } else {
         for (int k = 0; k < L; ++k) {
           if (k % seg == 0) save_state(k / seg);
@@ -294,36 +299,37 @@ extern "C" gwl_status gwl_sigma_c_vjp(gwl_ctx* ctx, const int* qp_states, int n_
       GWL_HIP(hipMemsetAsync(qbp, 0, vec * 8, st));
       GWL_HIP(hipMemsetAsync(pend.p, 0, B * 8, st));
       GWL_HIP(hipMemsetAsync(dbar.p, 0, vec * 8, st));
-      // backward step k from q_{k+1}, q_k, q_{k-1}, w_k and the iterates of p_g(C) q_k
+      // backward step k from q_{k+1}, q_k, q_{k-1} and the kept iterates of p_g(C) q_k
       auto reverse_step = [&](int k, const double* qn, const double* qk, const double* qpv,
-                              const double* Ti, const double* KTi, const double* Wi) {
+                              const double* Ti, const double* KTi, const double* Wi,
+                              const double* VTi) {
         // reverse Lanczos step k
         adj_lanczos_step(k, B, slot_pair.p, flen.p, L, c.coef_a.p, c.coef_b.p, abar.p,
                          bbar.p, qn, qk, qpv, Wi, qbn, qbc, qbp, wbar.p, pend.p, nvc, st);
-        // reverse Chebyshev recurrence on x = w_bar_k
+        // reverse Chebyshev recurrence on x = w_bar_k; the product on s_j leaves
+        // V[rho(Delta^1/2 s_j)] in VS[j - 1]
         adj_scale_copy(Sv.p + (size_t)g * vec, wbar.p, c.cheb[g], (long)vec, st);
         c.cast(B, Sv.p + (size_t)g * vec, GWL_FP64);
         for (int j = g; j >= 1; --j) {
-          c.k_product(B, GWL_FP64, S);
+          c.k_product(B, GWL_FP64, S, VS.p + (size_t)(j - 1) * fld);
           adj_combine(pg, B, S, reinterpret_cast<const double*>(c.ypart.p),
                       Sv.p + (size_t)j * vec, j < g ? Sv.p + (size_t)(j + 1) * vec : nullptr,
                       wbar.p, c.cheb[j - 1], j >= 2 ? 2.0 : 1.0, lo, hi,
                       Sv.p + (size_t)(j - 1) * vec, KS.p + (size_t)j * vec,
                       j - 1 >= 1 ? c.u64.p : nullptr, st);
         }
-        // C_bar = (2/(hi-lo)) [sum_{j>=2} 2 s_j t_{j-1}^T + s_1 t_0^T]
+        // C_bar = (2/(hi-lo)) [sum_{j>=2} 2 s_j t_{j-1}^T + s_1 t_0^T]: its Delta part
+        // now, its coupling part as the pair-vector operands of the contraction
         for (int j = 1; j <= g; ++j) {
           const double alpha = (2.0 / (hi - lo)) * (j >= 2 ? 2.0 : 1.0);
-          adj_dbar_uv(pg, B, Sv.p + (size_t)j * vec, KS.p + (size_t)j * vec,
-                      Ti + (size_t)(j - 1) * vec, KTi + (size_t)(j - 1) * vec, alpha,
-                      2.0 * alpha, dbar.p, U.p + (size_t)(j - 1) * vec,
-                      V.p + (size_t)(j - 1) * vec, st);
+          adj_dbar_zops(pg, B, Sv.p + (size_t)j * vec, KS.p + (size_t)j * vec,
+                        Ti + (size_t)(j - 1) * vec, KTi + (size_t)(j - 1) * vec, alpha,
+                        2.0 * alpha, dbar.p, US.p + (size_t)(j - 1) * uvp,
+                        UT.p + (size_t)(j - 1) * uvp, st);
         }
-        // K_bar += sum_rows U^T V  (column-major view: Kbar += V_cm U_cm^T)
-        GWL_BLAS(rocblas_dgemm(blas.h, rocblas_operation_none, rocblas_operation_transpose,
-                               (rocblas_int)nvc, (rocblas_int)nvc, (rocblas_int)(g * B), &one,
-                               V.p, (rocblas_int)nvc, U.p, (rocblas_int)nvc, &one, Kbar.p,
-                               (rocblas_int)nvc));
+        // orbital gradient of this step's coupling part
+        adj_zgemm(d, c.nv, ZSeg{VTi, US.p, g * B}, ZSeg{VS.p, UT.p, g * B}, psi_c_rc, psi_v_rv,
+                  c.dv, grad_c, gvpart.p, st);
         // q_bar_k += D w_bar_k
         adj_axpy(qbc, Sv.p, 1.0, (long)vec, st);
         // rotate: q_bar_{k+1} <- q_bar_k <- q_bar_{k-1} <- 0
@@ -333,110 +339,58 @@ extern "C" gwl_status gwl_sigma_c_vjp(gwl_ctx* ctx, const int* qp_states, int n_
         qbp = t;
         GWL_HIP(hipMemsetAsync(qbp, 0, vec * 8, st));
       };
-      if (store) {
-        for (int k = L - 1; k >= 0; --k) {
-          const double* Ti = It.p + (size_t)k * per_step;
-          const double* qn = k + 1 < L ? Ti + per_step : q_last;
-          const double* qpv = k > 0 ? Ti - per_step : q_m1;
-          reverse_step(k, qn, Ti, qpv, Ti, Ti + (size_t)(g + 1) * vec,
-                       Ti + (size_t)(2 * g + 1) * vec);
-        }
-      } else {
-        for (int sgi = nseg - 1; sgi >= 0; --sgi) {
-          const int k0 = sgi * seg, k1 = std::min(L, k0 + seg);
+      for (int sgi = nseg - 1; sgi >= 0; --sgi) {
+        const int k0 = sgi * seg, k1 = std::min(L, k0 + seg);
+        if (nseg > 1) {
           load_state(sgi);
-          GWL_HIP(hipMemcpyAsync(segq.p, c.q.p, vec * 8, hipMemcpyDeviceToDevice, st));
-          for (int k = k0; k < k1; ++k) {
-            fwd_step();
-            GWL_HIP(hipMemcpyAsync(segq.p + (size_t)(k - k0 + 1) * vec, c.q.p, vec * 8,
-                                   hipMemcpyDeviceToDevice, st));
-          }
-          const double* qprev0 = ckqp.p + (size_t)sgi * vec;
-          for (int k = k1 - 1; k >= k0; --k) {
-            const double* qk = segq.p + (size_t)(k - k0) * vec;
-            const double* qn = segq.p + (size_t)(k - k0 + 1) * vec;
-            const double* qpv = k > k0 ? segq.p + (size_t)(k - k0 - 1) * vec : qprev0;
-            // recompute w_k = p_g(C) q_k keeping t_0..t_{g-1} and K Delta^1/2 t_j
-            GWL_HIP(hipMemcpyAsync(T.p, qk, vec * 8, hipMemcpyDeviceToDevice, st));
-            cheb_iterates(T.p, KT.p, wk.p);
-            reverse_step(k, qn, qk, qpv, T.p, KT.p, wk.p);
-          }
+          fwd_segment_store(k0, k1);
+        }
+        for (int k = k1 - 1; k >= k0; --k) {
+          const double* Ti = step_ptr(k - k0);
+          const double* qn = k + 1 < k1 ? step_ptr(k + 1 - k0) : sq_end;
+          const double* qpv = k > k0 ? step_ptr(k - 1 - k0) : sq_prev0;
+          reverse_step(k, qn, Ti, qpv, Ti, Ti + (size_t)(g + 1) * vec,
+                       Ti + (size_t)(2 * g + 1) * vec, Ti + (size_t)(2 * g + 2) * vec);
         }
       }
-      // start vector adjoint: q_bar_0 is now in qbn
+      // start vector adjoint: q_bar_0 is now in qbn; k_bar per slot
       adj_start(B, slot_pair.p, c.norm2.p, nbar.p, Pb.p, qbn, c.sdelta.p, dbar.p, kbar.p, nvc,
                 st);
       adj_sum_rows(dbar_tot.p, dbar.p, B, nvc, st);
+      // orbital terms of the coupling integrals (nm|vc) = dV sum_r rho_vc V[phi_n phi_m]:
+      // k_bar with V[phi_n phi_m] through the contraction, and the potential of
+      // rho(k_bar) with phi_m (for phi_n) and phi_n (for phi_m)
+      c.cast(B, kbar.p, GWL_FP64, true);
+      adj_zgemm(d, c.nv, ZSeg{Vnm.p, c.u64.p, nbk}, ZSeg{nullptr, nullptr, 0}, psi_c_rc,
+                psi_v_rv, c.dv, grad_c, gvpart.p, st);
+      c.potential64(nbk, c.vpot64.p);
+      adj_orb_grad_nm(c.psi_t.p, c.vpot64.p, d.nrp, (int)c.nr, mrow_d.p + p0, nrow_d.p + p0, nbk,
+                      c.dv, grad_int.p, st);
     }
+    adj_gv_reduce(gvpart.p, nct, c.nv, d.nrp, grad_int.p, st);
 
     // ---- energies: Delta_bar -> e_bar, plus the explicit z_n terms
     std::vector<double> dtot(nvc), eb(P);
     GWL_HIP(hipStreamSynchronize(st));
-    It.release();  // the kept iterates are done with; the orbital stage needs the room
     GWL_HIP(hipMemcpy(dtot.data(), dbar_tot.p, nvc * 8, hipMemcpyDeviceToHost));
     GWL_HIP(hipMemcpy(eb.data(), ebar.p, P * 8, hipMemcpyDeviceToHost));
     std::vector<double> ge(c.n_orb, 0.0);
     for (int v = 0; v < c.nv; ++v)
       for (int cc = 0; cc < c.nc; ++cc) {
-        const double d = dtot[(size_t)v * c.nc + cc];
-        ge[v] -= d;
-        ge[c.nv + cc] += d;
+        const double dd = dtot[(size_t)v * c.nc + cc];
+        ge[v] -= dd;
+        ge[c.nv + cc] += dd;
       }
     for (int p = 0; p < P; ++p) ge[n[p]] += eb[p];
     for (int a = 0; a < c.n_orb; ++a) grad_energies[a] = ge[a] / kHartreeEv;
 
-    // ---- orbitals
-    const long ld = c.gd.nrp;
-    DevBuf<double> VB, W, Sym, Vnm, Vk;
-    VB.ensure((size_t)nvc * ld);
-    W.ensure((size_t)nvc * ld);
-    Sym.ensure((size_t)nvc * nvc);
-    Vnm.ensure((size_t)P * ld);
-    Vk.ensure((size_t)P * ld);
-    const int chunk = std::min<long>(B, nvc);
-    double* rho = reinterpret_cast<double*>(c.rho.p);
-    double* fx = reinterpret_cast<double*>(c.fftx.p);
-    for (long q0 = 0; q0 < nvc; q0 += chunk) {
-      const int cnt = (int)std::min<long>(chunk, nvc - q0);
-      adj_pair_density(c.psi_t.p, ld, c.nv, c.nc, c.gd.nvp, q0, cnt, rho, st);
-      poisson_launch<double>(c.pg64, rho, ld, 0, 1, VB.p + (size_t)q0 * ld, ld, cnt,
-                             reinterpret_cast<cplx<double>*>(fx), st);
-    }
-    std::vector<int> mr(P), nr_(P);
-    for (int p = 0; p < P; ++p) {
-      mr[p] = c.orb_row(m[p]);
-      nr_[p] = c.orb_row(n[p]);
-    }
-    mrow_d.ensure(P);
-    nrow_d.ensure(P);
-    GWL_HIP(hipMemcpy(mrow_d.p, mr.data(), P * 4, hipMemcpyHostToDevice));
-    GWL_HIP(hipMemcpy(nrow_d.p, nr_.data(), P * 4, hipMemcpyHostToDevice));
-    for (int p0 = 0; p0 < P; p0 += B) {
-      const int cnt = std::min(B, P - p0);
-      pair_product(c.psi_t.p, ld, (int)c.nr, mrow_d.p + p0, nrow_d.p + p0, cnt, rho, st);
-      poisson_launch<double>(c.pg64, rho, ld, 0, 1, Vnm.p + (size_t)p0 * ld, ld, cnt,
-                             reinterpret_cast<cplx<double>*>(fx), st);
-    }
-    adj_symmetrize(Sym.p, Kbar.p, nvc, st);
-    // W[(vc)][r] = sum_q Sym[(vc)][q] VB[q][r] + sum_p kbar[p][(vc)] Vnm[p][r]
-    GWL_BLAS(rocblas_dgemm(blas.h, rocblas_operation_none, rocblas_operation_none,
-                           (rocblas_int)ld, (rocblas_int)nvc, (rocblas_int)nvc, &one, VB.p,
-                           (rocblas_int)ld, Sym.p, (rocblas_int)nvc, &zero, W.p, (rocblas_int)ld));
-    GWL_BLAS(rocblas_dgemm(blas.h, rocblas_operation_none, rocblas_operation_transpose,
-                           (rocblas_int)ld, (rocblas_int)nvc, (rocblas_int)P, &one, Vnm.p,
-                           (rocblas_int)ld, kbar.p, (rocblas_int)nvc, &one, W.p, (rocblas_int)ld));
-    // Vk[p][r] = sum_q kbar[p][q] VB[q][r]
-    GWL_BLAS(rocblas_dgemm(blas.h, rocblas_operation_none, rocblas_operation_none,
-                           (rocblas_int)ld, (rocblas_int)P, (rocblas_int)nvc, &one, VB.p,
-                           (rocblas_int)ld, kbar.p, (rocblas_int)nvc, &zero, Vk.p, (rocblas_int)ld));
-    GWL_HIP(hipMemsetAsync(grad_int.p, 0, grad_int.n * 8, st));
-    adj_orb_grad_vc(c.psi_t.p, W.p, ld, (int)c.nr, c.nv, c.nc, c.gd.nvp, c.dv, grad_int.p, st);
-    adj_orb_grad_nm(c.psi_t.p, Vk.p, ld, (int)c.nr, mrow_d.p, nrow_d.p, P, c.dv, grad_int.p, st);
-    adj_gather_orbitals(grad_int.p, ld, (int)c.nr, c.nv, c.gd.nvp, c.n_orb, grad_orbitals, st);
+    // ---- orbitals, in the orbitals' own type
+    adj_gather_orbitals(grad_int.p, d.nrp, (int)c.nr, c.nv, d.nvp, c.n_orb, grad_orbitals,
+                        c.orb_dtype == 4, st);
 
     if (sigma_out) {
       c.sig_sum.ensure((size_t)n_qp * n_omega * 2);
-      sum_groups(sig.p, n_qp, c.n_orb, n_omega, c.sig_sum.p, st);
+      sum_groups(sig.p, n_qp, nn, n_omega, c.sig_sum.p, st);
       GWL_HIP(hipMemcpyAsync(sigma_out, c.sig_sum.p, sizeof(double) * n_qp * n_omega * 2,
                              hipMemcpyDeviceToHost, st));
     }
@@ -450,4 +404,28 @@ extern "C" gwl_status gwl_sigma_c_vjp(gwl_ctx* ctx, const int* qp_states, int n_
     set_error(e.what());
     return GWL_EDEVICE;
   }
+}
+
+}  // namespace
+
+extern "C" gwl_status gwl_sigma_c_vjp(gwl_ctx* ctx, const int* qp_states, int n_qp,
+                                      const double* omega_ev, int n_omega, double eta_ev,
+                                      int n_lanczos, const double* grad_sigma,
+                                      double* sigma_out, double* grad_energies,
+                                      void* grad_orbitals) {
+  if (!ctx) {
+    set_error("null context");
+    return GWL_EINVAL;
+  }
+  return vjp_range(ctx, qp_states, n_qp, 0, ctx->n_orb, omega_ev, n_omega, eta_ev, n_lanczos,
+                   grad_sigma, sigma_out, grad_energies, grad_orbitals);
+}
+
+extern "C" gwl_status gwl_sigma_c_range_vjp(gwl_ctx* ctx, const int* qp_states, int n_qp,
+                                            int n_begin, int n_end, const double* omega_ev,
+                                            int n_omega, double eta_ev, int n_lanczos,
+                                            const double* grad_sigma, double* sigma_out,
+                                            double* grad_energies, void* grad_orbitals) {
+  return vjp_range(ctx, qp_states, n_qp, n_begin, n_end, omega_ev, n_omega, eta_ev, n_lanczos,
+                   grad_sigma, sigma_out, grad_energies, grad_orbitals);
 }
