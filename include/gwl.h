@@ -68,10 +68,11 @@ typedef enum {
  * FP64 in every mode. */
 typedef enum {
   GWL_FP64 = 0,            /* GEMMs and FFT in FP64 */
-  GWL_MIXED_F16_BF16 = 1,  /* first GEMM on FP16 operands (pair vectors and orbitals
-                              scaled by powers of two into FP16's range), second GEMM
-                              on BF16 operands (phi_v V needs BF16's exponent range),
-                              both with FP32 accumulation; FFT in FP32 */
+  GWL_MIXED_F16 = 1,       /* both GEMMs on FP16 operands with FP32 accumulation; each
+                              operand carries a power of two that puts it inside FP16's
+                              range (pair vectors per batch, orbitals once, phi_v V_b
+                              per pair vector from the maximum of its potential, which
+                              the Poisson solve records); FFT in FP32 */
   GWL_MIXED_BF16X3 = 2,    /* three-term BF16 split of each operand: not built
                               (GWL_EUNSUPPORTED); the 16-bit path already meets the
                               1 meV bar on the smooth stress inputs */
@@ -237,7 +238,7 @@ gwl_status gwl_sigma_c_range_vjp(gwl_ctx* ctx, const int* qp_states, int n_qp, i
 
 /* Hartree potential V = FFT^-1[kernel_scale 4 pi/|G|^2 FFT[rho]] of n_fields
  * real densities.  rho, v: device [n_fields][nx*ny*nz] in float64 if
- * precision == GWL_FP64, float32 if GWL_MIXED_F16_BF16. */
+ * precision == GWL_FP64, float32 if GWL_MIXED_F16. */
 gwl_status gwl_poisson(gwl_ctx* ctx, const void* rho, void* v, int n_fields,
                        int precision);
 

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libgwl.so")
 
 GWL_OK, GWL_EINVAL, GWL_ENOMEM, GWL_EDEVICE, GWL_ENUMERIC, GWL_ESTATE, GWL_EUNSUPPORTED = (
     0, -1, -2, -3, -4, -5, -6)
-FP64, MIXED_F16_BF16, MIXED_BF16X3, MIXED_FP32 = 0, 1, 2, 3
+FP64, MIXED_F16, MIXED_BF16X3, MIXED_FP32 = 0, 1, 2, 3
 REORTH = {"none": 0, "local": 1, "full": 2}
 KEY_PRECISION, KEY_REORTH, KEY_BLOCK, KEY_POLY_LO, KEY_POLY_HI, KEY_POLY_DEGREE = 1, 2, 3, 4, 5, 6
 KEY_N_VC, KEY_LAST_MS_TOTAL, KEY_LAST_C_MATVECS, KEY_GEMM_SPLITK, KEY_KERNELS = 7, 9, 10, 11, 12
@@ -29,7 +29,7 @@ KEY_ADJOINT_STORE, KEY_ADJOINT_STORED, KEY_HI_RESIDUAL = 32, 33, 34
 KEY_PROF = {"gemm1": (14, 15, 16), "gemm2": (17, 18, 19), "fft": (20, 21, 22)}
 # "mixed" is the built 16-bit path; the last two are named by the ABI and
 # refused by the library (GWL_EUNSUPPORTED)
-PRECISIONS = {"fp64": FP64, "mixed": MIXED_F16_BF16, "bf16x3": MIXED_BF16X3, "fp32": MIXED_FP32}
+PRECISIONS = {"fp64": FP64, "mixed": MIXED_F16, "bf16x3": MIXED_BF16X3, "fp32": MIXED_FP32}
 
 
 class GwlError(RuntimeError):

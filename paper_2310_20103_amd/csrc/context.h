@@ -149,7 +149,7 @@ struct gwl_ctx {
   int isdf_on = 0, isdf_ready = 0, n_mu = 0;
   GemmDims gdi{};                     // dims with the grid replaced by the points
   DevBuf<double> ipsi_t, ipsi_c_rc64, ipsi_v_rv64, mmat64;  // mmat: [NRp_i][NRp_i]
-  DevBuf<bf16_t> ipsi_t16;
+  DevBuf<f16_t> ipsi_t16;
   DevBuf<f16_t> ipsi_c_rc16, ipsi_v_rv16;
   DevBuf<float> ipsi_v_rv32, mmat32;
   DevBuf<int> ipoints;
@@ -178,7 +178,9 @@ struct gwl_ctx {
   DevBuf<double> psi_t;       // [NVp + NCp][NRp]
   DevBuf<double> psi_c_rc64;  // [NRp][NCp]
   DevBuf<double> psi_v_rv64;  // [NRp][NVp]
-  DevBuf<bf16_t> psi_t16;     // [NVp + NCp][NRp]
+  DevBuf<f16_t> psi_t16;      // [NVp + NCp][NRp] FP16, scaled by orb16_scale
+  int pv16_exp = 0;           // frexp exponent of max |phi_v| in psi_t16
+  DevBuf<unsigned> vmax32;    // [cap] max |V_b| of the mixed product's potentials
   DevBuf<f16_t> psi_c_rc16;   // [NRp][NCp] FP16, scaled by orb16_scale
   DevBuf<float> psi_v_rv32;   // [NRp][NVp] FP32, scaled (other mixed epilogues)
   DevBuf<f16_t> psi_v_rv16;   // [NRp][NVp] FP16, scaled (MFMA epilogue, N_vp <= 128)
@@ -330,7 +332,7 @@ struct gwl_ctx {
     else if (prec == GWL_FP64)
       blocks = gemm2_f64m_blocks(d, nb);
     else
-      blocks = gemm2_bf16_blocks(d, nb, bf16_tile);
+      blocks = gemm2_f16_blocks(d, nb, bf16_tile);
     int s = 1;
     while (blocks * s < 1024 && s < 32 && (long)d.nrp / (s * 2) >= 2048) s *= 2;
     return s;
@@ -350,6 +352,7 @@ struct gwl_ctx {
       rho.ensure((size_t)nvt_max() * nb * gd.nrp * 8);
       vpot64.ensure((size_t)nb * gd.nrp);
       vpot32.ensure((size_t)alloc_rows_v(nb, gd.nvp) * gd.nrp);
+      vmax32.ensure((size_t)alloc_rows_v(nb, gd.nvp));
       fftx.ensure((size_t)((nb + 1) / 2) * nr * 16);
       ypart.ensure((size_t)32 * nb * nvpc * 8);
       s_pair.ensure(nb);
@@ -433,7 +436,7 @@ struct gwl_ctx {
       const f16_t* crc = is ? ipsi_c_rc16.p : psi_c_rc16.p;
       const f16_t* vrv16 = is ? ipsi_v_rv16.p : psi_v_rv16.p;
       const float* vrv32 = is ? ipsi_v_rv32.p : psi_v_rv32.p;
-      const bf16_t* pt = is ? ipsi_t16.p : psi_t16.p;
+      const f16_t* pt = is ? ipsi_t16.p : psi_t16.p;
       int nvt;
       prof_begin();
       if (fp64_kernel) {
@@ -449,15 +452,15 @@ struct gwl_ctx {
         middle_step(nb, prec, nvt, rp, vp);
       else
         poisson_launch<float>(pg32, rp, d.nrp, (long)nb * d.nrp, nvt, vp, d.nrp, nb,
-                              reinterpret_cast<cplx<float>*>(fftx.p), st);
+                              reinterpret_cast<cplx<float>*>(fftx.p), st, vmax32.p);
       prof_end(2, nb);
-      const bf16_t* pv = pt;
-      const bf16_t* pc = pt + (size_t)d.nvp * d.nrp;
+      const f16_t* pv = pt;
+      const f16_t* pc = pt + (size_t)d.nvp * d.nrp;
       prof_begin();
       if (fp64_kernel)
-        gemm2_bf16(d, nb, bf16_tile, S, pv, pc, vp, yp, st);
+        gemm2_f16(d, nb, bf16_tile, S, pv, pc, vp, vmax32.p, pv16_exp, yp, st);
       else
-        gemm2_bf16s(d, nb, S, pv, pc, vp, yp, st);
+        gemm2_f16s(d, nb, S, pv, pc, vp, vmax32.p, pv16_exp, yp, st);
       prof_end(1, nb);
     }
   }
@@ -499,7 +502,11 @@ struct gwl_ctx {
                               write_u ? u64.p : nullptr, stream);
     else {
       g.uscale = u_scale;
-      g.yscale = 1.0 / (u_scale * orb16_scale * orb16_scale);
+      // first GEMM: u and both orbital factors scaled; second GEMM: phi_v and
+      // phi_c scaled again, and s_b per row (g.vmax)
+      g.yscale = 1.0 / (u_scale * orb16_scale * orb16_scale * orb16_scale * orb16_scale);
+      g.vmax = vmax32.p;
+      g.pexp = pv16_exp;
       combine<float, f16_t>(g, nb, S, reinterpret_cast<const float*>(ypart.p), x, tp, out,
                             acc, mode, poly_lo, poly_hi, c0, cj,
                             write_u ? u16.p : nullptr, stream);
@@ -674,7 +681,7 @@ struct gwl_ctx {
   Tune autotune(int prec, int bmax) {
     Tune best = tuned[prec];
     if (best.B > 0) return best;
-    const bool pick_tile = prec == GWL_MIXED_F16_BF16 && fp64_kernel && !tile_fixed;
+    const bool pick_tile = prec == GWL_MIXED_F16 && fp64_kernel && !tile_fixed;
     if (tune_cache_read(prec, best)) {
       if (pick_tile) set_tile(best.tile);
       best.tile = bf16_tile;

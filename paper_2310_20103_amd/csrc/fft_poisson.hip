@@ -136,11 +136,15 @@ __device__ cplx<T>* fft_lines(cplx<T>* buf0, cplx<T>* buf1, int nl, int n, int l
 // Pass along z (contiguous lines).  Forward: builds the complex field from the
 // real fields 2p and 2p+1, summing nparts GEMM partial densities.  Inverse:
 // writes the real part to field 2p and the imaginary part to field 2p+1.
+// vmax (optional, [nf]): the forward pass clears it, the inverse pass leaves
+// max_r |V_f(r)| of each output field in it (float bits; the maximum of
+// non-negative floats is order-independent, so the value is deterministic).
 template <typename T, bool INVERSE>
 __global__ void __launch_bounds__(256)
 fft_pass_z(cplx<T>* __restrict__ X, const T* __restrict__ rin, T* __restrict__ rout,
            int nf, long ld_real, long part_stride, int nparts, int nlines, int nz,
-           long nr, int lpb, FftPlan plan, const cplx<T>* __restrict__ tw) {
+           long nr, int lpb, FftPlan plan, const cplx<T>* __restrict__ tw,
+           unsigned* __restrict__ vmax) {
   extern __shared__ unsigned char smem_raw[];
   cplx<T>* buf0 = reinterpret_cast<cplx<T>*>(smem_raw);
   const int ls = nz + 1;
@@ -172,6 +176,7 @@ fft_pass_z(cplx<T>* __restrict__ X, const T* __restrict__ rin, T* __restrict__ r
   }
   __syncthreads();
   cplx<T>* res = fft_lines<T>(buf0, buf1, nl, nz, ls, plan, tw);
+  T m0 = 0, m1 = 0;
   for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
     const int l = e / nz, p = e - l * nz;
     cplx<T> v = res[l * ls + p];
@@ -180,6 +185,39 @@ fft_pass_z(cplx<T>* __restrict__ X, const T* __restrict__ rin, T* __restrict__ r
     } else {
       rout[(long)f0 * ld_real + base + e] = v.x;
       if (f1 < nf) rout[(long)f1 * ld_real + base + e] = -v.y;
+      m0 = fmax(m0, fabs(v.x));
+      m1 = fmax(m1, fabs(v.y));
+    }
+  }
+  if (vmax) {
+    if (!INVERSE) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        vmax[f0] = 0u;
+        if (f1 < nf) vmax[f1] = 0u;
+      }
+    } else {
+      // block maximum, then one atomic per field
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        m0 = fmax(m0, __shfl_xor(m0, off, 64));
+        m1 = fmax(m1, __shfl_xor(m1, off, 64));
+      }
+      __shared__ float wm[2][4];
+      const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+      if (lane == 0) {
+        wm[0][wid] = (float)m0;
+        wm[1][wid] = (float)m1;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        float a = 0.0f, b = 0.0f;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+          a = fmaxf(a, wm[0][i]);
+          b = fmaxf(b, wm[1][i]);
+        }
+        atomicMax(&vmax[f0], __float_as_uint(a));
+        if (f1 < nf) atomicMax(&vmax[f1], __float_as_uint(b));
+      }
     }
   }
 }
@@ -262,7 +300,7 @@ FftPlan make_plan(int n) {
 template <typename T>
 void poisson_launch(const PoissonGeom<T>& g, const T* rin, long ld_in, long part_stride,
                     int nparts, T* rout, long ld_out, int nf, cplx<T>* scratch,
-                    hipStream_t st) {
+                    hipStream_t st, unsigned* vmax) {
   if (nf <= 0) return;
   const int npairs = (nf + 1) / 2;
   const long nr = (long)g.nx * g.ny * g.nz;
@@ -274,7 +312,7 @@ void poisson_launch(const PoissonGeom<T>& g, const T* rin, long ld_in, long part
     size_t sm = 2 * (size_t)lpb * (g.nz + 1) * sizeof(cplx<T>);
     fft_pass_z<T, false><<<grid, 256, sm, st>>>(scratch, rin, nullptr, nf, ld_in,
                                                 part_stride, nparts, nlines, g.nz, nr,
-                                                lpb, g.pz, g.twz);
+                                                lpb, g.pz, g.twz, vmax);
   }
   const int nmax = g.nx > g.ny ? g.nx : g.ny;
   int lpb = 1024 / nmax;
@@ -313,14 +351,15 @@ void poisson_launch(const PoissonGeom<T>& g, const T* rin, long ld_in, long part
     dim3 grid(ceil_div(nlines, lpbz), npairs);
     size_t sm = 2 * (size_t)lpbz * (g.nz + 1) * sizeof(cplx<T>);
     fft_pass_z<T, true><<<grid, 256, sm, st>>>(scratch, nullptr, rout, nf, ld_out, 0, 1,
-                                               nlines, g.nz, nr, lpbz, g.pz, g.twz);
+                                               nlines, g.nz, nr, lpbz, g.pz, g.twz, vmax);
   }
   GWL_HIP(hipGetLastError());
 }
 
 template void poisson_launch<float>(const PoissonGeom<float>&, const float*, long, long, int,
-                                    float*, long, int, cplx<float>*, hipStream_t);
+                                    float*, long, int, cplx<float>*, hipStream_t, unsigned*);
 template void poisson_launch<double>(const PoissonGeom<double>&, const double*, long, long,
-                                     int, double*, long, int, cplx<double>*, hipStream_t);
+                                     int, double*, long, int, cplx<double>*, hipStream_t,
+                                     unsigned*);
 
 }  // namespace gwl

@@ -13,11 +13,12 @@
 // into LDS, so the per-vector operand never exists in HBM either.
 //
 // FP64: v_mfma_f64_16x16x4f64, block tile 128 x 128 x 16, 4 waves of 64 x 64.
-// Mixed path: the first GEMM on FP16 operands (v_mfma_f32_32x32x16_f16; the
-// pair vector is scaled by a power of two into FP16's range), the second on
-// BF16 operands (v_mfma_f32_32x32x16_bf16, whose range holds phi_v V without
-// scaling), both with FP32 accumulation; block tiles 256 x 128 x 32 (4 waves
-// of 128 x 64) and, for the second GEMM, 256 x 256 x 32.
+// Mixed path: both GEMMs on FP16 operands (v_mfma_f32_32x32x16_f16) with FP32
+// accumulation; every operand carries a power-of-two scale that puts it
+// inside FP16's range (the pair vector per batch, the orbitals once, and
+// phi_v V_b per pair vector from the maximum of its potential), undone
+// exactly in FP64 by the combine; block tiles 256 x 128 x 32 (4 waves of
+// 128 x 64) and, for the second GEMM, 256 x 256 x 32.
 // Tiles are staged through LDS with the K steps prefetched into registers
 // (two XOR-swizzled LDS stages, one barrier per K step, two register stages:
 // the loads of the step after next in flight during the current step's MFMAs).
@@ -309,31 +310,56 @@ struct LoadU16 {  // plain [M][K] rows
   __device__ u4 finish(const Raw& r, int q) const { return r.c[q]; }
 };
 
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+// two floats -> packed FP16 pair, round to nearest even (v_cvt_pk_f16_f32)
+__device__ inline unsigned pack_f16(float a, float b) {
+  const h2 v = {(_Float16)a, (_Float16)b};
+  return __builtin_bit_cast(unsigned, v);
+}
+
 __device__ inline u4 scale8(u4 pv, f4v v0, f4v v1) {
   u4 out;
-  out[0] = pack_bf16(lo_bf16(pv[0]) * v0[0], hi_bf16(pv[0]) * v0[1]);
-  out[1] = pack_bf16(lo_bf16(pv[1]) * v0[2], hi_bf16(pv[1]) * v0[3]);
-  out[2] = pack_bf16(lo_bf16(pv[2]) * v1[0], hi_bf16(pv[2]) * v1[1]);
-  out[3] = pack_bf16(lo_bf16(pv[3]) * v1[2], hi_bf16(pv[3]) * v1[3]);
+  out[0] = pack_f16(lo_f16(pv[0]) * v0[0], hi_f16(pv[0]) * v0[1]);
+  out[1] = pack_f16(lo_f16(pv[1]) * v0[2], hi_f16(pv[1]) * v0[3]);
+  out[2] = pack_f16(lo_f16(pv[2]) * v1[0], hi_f16(pv[2]) * v1[1]);
+  out[3] = pack_f16(lo_f16(pv[3]) * v1[2], hi_f16(pv[3]) * v1[3]);
   return out;
 }
 
-// A[(b,v)][r] = bf16(phi_v(r) V_b(r)).  NVP = padded N_v when it is 64 or
-// 128 (a thread's four rows then share one or two phi_v rows and use four or
-// two potentials), 256 when it is a multiple of 256 (a tile lies inside one
-// pair vector: four phi_v rows, one potential), 0 otherwise.
+// A[(b,v)][r] = f16(phi_v(r) V_b(r) s_b), phi_v in FP16 (scaled) and s_b the
+// power of two that keeps the pair vector's products inside FP16's range
+// (f16_operand_exp of max_r |V_b| and the orbitals' maximum), applied to the
+// potential as it is loaded.  NVP = padded N_v when it is 64 or 128 (a
+// thread's four rows then share one or two phi_v rows and use four or two
+// potentials), 256 when it is a multiple of 256 (a tile lies inside one pair
+// vector: four phi_v rows, one potential), 0 otherwise.
 template <int NVP>
 struct LoadPsiV16 {
-  const bf16_t* psi_v_t;
+  const f16_t* psi_v_t;
   const float* vpot;
   long nrp;
   int nvp;
   static constexpr int NPV = NVP == 64 ? 1 : (NVP == 128 ? 2 : 4);
   static constexpr int NB = NVP == 128 ? 2 : (NVP == 256 ? 1 : 4);
+  float sc[NB];  // s_b of the potentials this thread loads
   struct Raw {
     u4 pv[NPV];
     f4v v[NB][2];
   };
+  __device__ LoadPsiV16(const f16_t* pv, const float* vp, long nrp_, int nvp_, int m0, int t,
+                        const unsigned* __restrict__ vmax, int pexp)
+      : psi_v_t(pv), vpot(vp), nrp(nrp_), nvp(nvp_) {
+    const int r0 = t >> 2;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      int b;
+      if constexpr (NVP == 64) b = m0 / 64 + i;
+      else if constexpr (NVP == 128) b = m0 / 128 + i;
+      else if constexpr (NVP == 256) b = m0 / nvp;
+      else b = (m0 + r0 + 64 * i) / nvp;
+      sc[i] = ldexpf(1.0f, f16_operand_exp(__uint_as_float(vmax[b]), pexp));
+    }
+  }
   __device__ void load(int m0, int t, int k0, Raw& r) const {
     const int k = k0 + (t & 3) * 8;
     const int r0 = t >> 2;
@@ -342,8 +368,8 @@ struct LoadPsiV16 {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const float* vp = vpot + (long)(m0 / 64 + q) * nrp + k;
-        r.v[q][0] = *reinterpret_cast<const f4v*>(vp);
-        r.v[q][1] = *reinterpret_cast<const f4v*>(vp + 4);
+        r.v[q][0] = *reinterpret_cast<const f4v*>(vp) * sc[q];
+        r.v[q][1] = *reinterpret_cast<const f4v*>(vp + 4) * sc[q];
       }
     } else if constexpr (NVP == 128) {
       r.pv[0] = *reinterpret_cast<const u4*>(psi_v_t + (long)r0 * nrp + k);
@@ -351,8 +377,8 @@ struct LoadPsiV16 {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const float* vp = vpot + (long)(m0 / 128 + h) * nrp + k;
-        r.v[h][0] = *reinterpret_cast<const f4v*>(vp);
-        r.v[h][1] = *reinterpret_cast<const f4v*>(vp + 4);
+        r.v[h][0] = *reinterpret_cast<const f4v*>(vp) * sc[h];
+        r.v[h][1] = *reinterpret_cast<const f4v*>(vp + 4) * sc[h];
       }
     } else if constexpr (NVP == 256) {
       const int b = m0 / nvp, v0 = m0 - b * nvp + r0;
@@ -360,8 +386,8 @@ struct LoadPsiV16 {
       for (int q = 0; q < 4; ++q)
         r.pv[q] = *reinterpret_cast<const u4*>(psi_v_t + (long)(v0 + 64 * q) * nrp + k);
       const float* vp = vpot + (long)b * nrp + k;
-      r.v[0][0] = *reinterpret_cast<const f4v*>(vp);
-      r.v[0][1] = *reinterpret_cast<const f4v*>(vp + 4);
+      r.v[0][0] = *reinterpret_cast<const f4v*>(vp) * sc[0];
+      r.v[0][1] = *reinterpret_cast<const f4v*>(vp + 4) * sc[0];
     } else {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -369,8 +395,8 @@ struct LoadPsiV16 {
         const int b = m / nvp, vv = m - b * nvp;
         r.pv[q] = *reinterpret_cast<const u4*>(psi_v_t + (long)vv * nrp + k);
         const float* vp = vpot + (long)b * nrp + k;
-        r.v[q][0] = *reinterpret_cast<const f4v*>(vp);
-        r.v[q][1] = *reinterpret_cast<const f4v*>(vp + 4);
+        r.v[q][0] = *reinterpret_cast<const f4v*>(vp) * sc[q];
+        r.v[q][1] = *reinterpret_cast<const f4v*>(vp + 4) * sc[q];
       }
     }
   }
@@ -688,11 +714,13 @@ __device__ inline void g2_sched() {
 // the A operand of the next step scaled by the potential and stored after the
 // current step's MFMAs.
 template <int BN, int NVP>
-__device__ inline void gemm2_bf16_body(const GemmDims& d, int M, int splitk, int kchunk,
-                                       const bf16_t* __restrict__ psi_v_t,
-                                       const bf16_t* __restrict__ psi_c_t,
-                                       const float* __restrict__ vpot,
-                                       float* __restrict__ ypart) {
+__device__ inline void gemm2_f16_body(const GemmDims& d, int M, int splitk, int kchunk,
+                                      const f16_t* __restrict__ psi_v_t,
+                                      const f16_t* __restrict__ psi_c_t16,
+                                      const float* __restrict__ vpot,
+                                      const unsigned* __restrict__ vmax, int pexp,
+                                      float* __restrict__ ypart) {
+  const bf16_t* psi_c_t = reinterpret_cast<const bf16_t*>(psi_c_t16);  // raw 16-bit rows
   constexpr int WN = BfCfg<BN>::WN;
   __shared__ BfSmem<BN> sm;
   const int mt = (M + HM - 1) / HM, nt = (d.ncp + BN - 1) / BN;
@@ -708,7 +736,7 @@ __device__ inline void gemm2_bf16_body(const GemmDims& d, int M, int splitk, int
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < WN; ++j) acc[i][j] = f16v{};
-  LoadPsiV16<NVP> la{psi_v_t, vpot, d.nrp, d.nvp};
+  LoadPsiV16<NVP> la(psi_v_t, vpot, d.nrp, d.nvp, m0, threadIdx.x, vmax, pexp);
   // Two register stages: the loads of step i + 2 are in flight while step i
   // computes and step i + 1 is scaled into the other LDS buffer.  The last
   // steps reload the final slab instead of branching.
@@ -721,12 +749,12 @@ __device__ inline void gemm2_bf16_body(const GemmDims& d, int M, int splitk, int
   __syncthreads();
   for (int i = 0; i < nsteps; i += 2) {
     bf_gload(la, psi_c_t, d.nrp, m0, n0, kb + min(i + 2, nsteps - 1) * HK, x0);
-    bf_compute(sm, 0, acc);
+    bf_compute<BN, OpF16>(sm, 0, acc);
     bf_lstore(la, sm, 1, x1);
     if constexpr (BN == 256) g2_sched<0>();
     __syncthreads();
     bf_gload(la, psi_c_t, d.nrp, m0, n0, kb + min(i + 3, nsteps - 1) * HK, x1);
-    bf_compute(sm, 1, acc);
+    bf_compute<BN, OpF16>(sm, 1, acc);
     bf_lstore(la, sm, 0, x0);
     if constexpr (BN == 256) g2_sched<0>();
     __syncthreads();
@@ -750,17 +778,19 @@ __device__ inline void gemm2_bf16_body(const GemmDims& d, int M, int splitk, int
 
 template <int NVP>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
-gemm2_bf16_n128_kernel(GemmDims d, int M, int splitk, int kchunk,
-                       const bf16_t* __restrict__ psi_v_t, const bf16_t* __restrict__ psi_c_t,
-                       const float* __restrict__ vpot, float* __restrict__ ypart) {
-  gemm2_bf16_body<128, NVP>(d, M, splitk, kchunk, psi_v_t, psi_c_t, vpot, ypart);
+gemm2_f16_n128_kernel(GemmDims d, int M, int splitk, int kchunk,
+                      const f16_t* __restrict__ psi_v_t, const f16_t* __restrict__ psi_c_t,
+                      const float* __restrict__ vpot, const unsigned* __restrict__ vmax,
+                      int pexp, float* __restrict__ ypart) {
+  gemm2_f16_body<128, NVP>(d, M, splitk, kchunk, psi_v_t, psi_c_t, vpot, vmax, pexp, ypart);
 }
 template <int NVP>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
-gemm2_bf16_n256_kernel(GemmDims d, int M, int splitk, int kchunk,
-                       const bf16_t* __restrict__ psi_v_t, const bf16_t* __restrict__ psi_c_t,
-                       const float* __restrict__ vpot, float* __restrict__ ypart) {
-  gemm2_bf16_body<256, NVP>(d, M, splitk, kchunk, psi_v_t, psi_c_t, vpot, ypart);
+gemm2_f16_n256_kernel(GemmDims d, int M, int splitk, int kchunk,
+                      const f16_t* __restrict__ psi_v_t, const f16_t* __restrict__ psi_c_t,
+                      const float* __restrict__ vpot, const unsigned* __restrict__ vmax,
+                      int pexp, float* __restrict__ ypart) {
+  gemm2_f16_body<256, NVP>(d, M, splitk, kchunk, psi_v_t, psi_c_t, vpot, vmax, pexp, ypart);
 }
 
 }  // namespace
@@ -803,19 +833,20 @@ void gemm1_f16(const GemmDims& d, int nb, const f16_t* psi_c_rc, const float* ps
   GWL_HIP(hipGetLastError());
 }
 
-int gemm2_bf16_blocks(const GemmDims& d, int nb, int bn) {
+int gemm2_f16_blocks(const GemmDims& d, int nb, int bn) {
   return ceil_div(nb * d.nvp, HM) * ceil_div(d.ncp, bn);
 }
 
-void gemm2_bf16(const GemmDims& d, int nb, int bn, int splitk, const bf16_t* psi_v_t,
-                const bf16_t* psi_c_t, const float* vpot, float* ypart, hipStream_t st) {
+void gemm2_f16(const GemmDims& d, int nb, int bn, int splitk, const f16_t* psi_v_t,
+               const f16_t* psi_c_t, const float* vpot, const unsigned* vmax, int pexp,
+               float* ypart, hipStream_t st) {
   if (nb <= 0) return;
   const int M = nb * d.nvp;
   const int kchunk = (int)round_up(ceil_div(d.nrp, splitk), 2 * HK);
-  const int blocks = gemm2_bf16_blocks(d, nb, bn) * splitk;
-#define GWL_G2(BNV, NVPV)                                                                   \
-  gemm2_bf16_n##BNV##_kernel<NVPV><<<blocks, 256, 0, st>>>(d, M, splitk, kchunk, psi_v_t, \
-                                                            psi_c_t, vpot, ypart)
+  const int blocks = gemm2_f16_blocks(d, nb, bn) * splitk;
+#define GWL_G2(BNV, NVPV)                                                                  \
+  gemm2_f16_n##BNV##_kernel<NVPV><<<blocks, 256, 0, st>>>(d, M, splitk, kchunk, psi_v_t, \
+                                                           psi_c_t, vpot, vmax, pexp, ypart)
   if (bn == 256) {
     if (d.nvp == 64) GWL_G2(256, 64);
     else if (d.nvp == 128) GWL_G2(256, 128);

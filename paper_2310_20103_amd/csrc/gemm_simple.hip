@@ -1,5 +1,5 @@
 // Factored pair-space product, plain LDS-tiled FMA version (FP64, and the
-// mixed path's FP16 / BF16 operands with FP32 accumulation).  The MFMA kernels
+// mixed path's FP16 operands with FP32 accumulation).  The MFMA kernels
 // are checked against it.
 //
 // First GEMM with fused row-dot (the density of a pair vector u = Delta^1/2 x):
@@ -78,7 +78,8 @@ template <typename A, typename TO>
 __global__ void __launch_bounds__(256)
 gemm2_simple_kernel(GemmDims d, const TO* __restrict__ psi_v_t,
                  const TO* __restrict__ psi_c_t, const A* __restrict__ vpot,
-                 A* __restrict__ ypart, int nb, int splitk, int kchunk) {
+                 A* __restrict__ ypart, int nb, int splitk, int kchunk,
+                 const unsigned* __restrict__ vmax, int pexp) {
   __shared__ A As[TK][LDT];
   __shared__ A Bs[TK][LDT];
   const int tid = threadIdx.x;
@@ -88,11 +89,15 @@ gemm2_simple_kernel(GemmDims d, const TO* __restrict__ psi_v_t,
   const int rbeg = s * kchunk;
   const int rend = min(d.nrp, rbeg + kchunk);
   const A* vb = vpot + (long)b * d.nrp;
+  // mixed path: the operand phi_v V_b s_b is rounded to FP16 as in the MFMA kernel
+  const A sb = vmax ? (A)ldexpf(1.0f, f16_operand_exp(__uint_as_float(vmax[b]), pexp)) : (A)1;
   A acc[4][4] = {};
   for (int r = rbeg; r < rend; r += TK) {
     for (int e = tid; e < TK * TM; e += 256) {
       const int kk = e & (TK - 1), i = e >> 4;
-      As[kk][i] = (A)ldx(psi_v_t, (long)(v0 + i) * d.nrp + r + kk) * vb[r + kk];
+      A av = (A)ldx(psi_v_t, (long)(v0 + i) * d.nrp + r + kk) * (vb[r + kk] * sb);
+      if (vmax) av = (A)(float)(_Float16)(float)av;
+      As[kk][i] = av;
       Bs[kk][i] = ldx(psi_c_t, (long)(c0 + i) * d.nrp + r + kk);
     }
     __syncthreads();
@@ -143,13 +148,14 @@ void gemm1_f16s(const GemmDims& d, int nb, const f16_t* psi_c_rc, const float* p
   GWL_HIP(hipGetLastError());
 }
 
-void gemm2_bf16s(const GemmDims& d, int nb, int splitk, const bf16_t* psi_v_t,
-                 const bf16_t* psi_c_t, const float* vpot, float* ypart, hipStream_t st) {
+void gemm2_f16s(const GemmDims& d, int nb, int splitk, const f16_t* psi_v_t,
+                const f16_t* psi_c_t, const float* vpot, const unsigned* vmax, int pexp,
+                float* ypart, hipStream_t st) {
   if (nb <= 0) return;
   const int kchunk = (int)round_up(ceil_div(d.nrp, splitk), TK);
   dim3 grid(d.ncp / TN, d.nvp / TM, nb * splitk);
-  gemm2_simple_kernel<float, bf16_t><<<grid, 256, 0, st>>>(d, psi_v_t, psi_c_t, vpot, ypart,
-                                                           nb, splitk, kchunk);
+  gemm2_simple_kernel<float, f16_t><<<grid, 256, 0, st>>>(d, psi_v_t, psi_c_t, vpot, ypart,
+                                                          nb, splitk, kchunk, vmax, pexp);
   GWL_HIP(hipGetLastError());
 }
 
@@ -159,7 +165,7 @@ void gemm2_f64(const GemmDims& d, int nb, int splitk, const double* psi_v_t,
   const int kchunk = (int)round_up(ceil_div(d.nrp, splitk), TK);
   dim3 grid(d.ncp / TN, d.nvp / TM, nb * splitk);
   gemm2_simple_kernel<double, double><<<grid, 256, 0, st>>>(d, psi_v_t, psi_c_t, vpot, ypart,
-                                                             nb, splitk, kchunk);
+                                                             nb, splitk, kchunk, nullptr, 0);
   GWL_HIP(hipGetLastError());
 }
 

@@ -77,8 +77,8 @@ void check_ctx(gwl_ctx* c) { GWL_CHECK(c != nullptr, GWL_EINVAL, "null context")
 // are named by the ABI but not built.
 void check_precision(int p) {
   GWL_CHECK(p != GWL_MIXED_BF16X3 && p != GWL_MIXED_FP32, GWL_EUNSUPPORTED,
-            "precision not built: use GWL_FP64 or GWL_MIXED_F16_BF16");
-  GWL_CHECK(p == GWL_FP64 || p == GWL_MIXED_F16_BF16, GWL_EINVAL, "unknown precision");
+            "precision not built: use GWL_FP64 or GWL_MIXED_F16");
+  GWL_CHECK(p == GWL_FP64 || p == GWL_MIXED_F16, GWL_EINVAL, "unknown precision");
 }
 
 }  // namespace
@@ -254,9 +254,9 @@ gwl_status gwl_setup(const void* orbitals, int orb_dtype, int orb_on_device, int
       c.psi_v_rv64.ensure(vrv.size());
       GWL_HIP(hipMemcpy(c.psi_c_rc64.p, crc.data(), crc.size() * 8, hipMemcpyHostToDevice));
       GWL_HIP(hipMemcpy(c.psi_v_rv64.p, vrv.data(), vrv.size() * 8, hipMemcpyHostToDevice));
-      // mixed-precision copies: BF16 for the second GEMM; FP16 for the first
-      // GEMM's orbital operand and row-dot weights, scaled by a power of two
-      // that puts the largest orbital value near 2^11
+      // mixed-precision copies in FP16 (both GEMMs' orbital operands and the
+      // first GEMM's row-dot weights), scaled by a power of two that puts the
+      // largest orbital value near 2^11
       double omax = 0.0;
       for (double v : host) omax = std::max(omax, std::fabs(v));
       {
@@ -265,9 +265,15 @@ gwl_status gwl_setup(const void* orbitals, int orb_dtype, int orb_on_device, int
         c.orb16_scale = std::ldexp(1.0, e);
       }
       const double os = c.orb16_scale;
-      std::vector<bf16_t> t16((size_t)(nvp + alloc_rows_c(ncp)) * nrp, 0);
+      std::vector<f16_t> t16((size_t)(nvp + alloc_rows_c(ncp)) * nrp, f16_t{0});
       std::vector<f16_t> c16(crc.size());
-      for (size_t i = 0; i < host.size(); ++i) t16[i] = f32_to_bf16((float)host[i]);
+      float pvmax = 0.0f;
+      for (size_t i = 0; i < host.size(); ++i) {
+        t16[i] = f32_to_f16((float)(os * host[i]));
+        if (i < (size_t)nvp * nrp) pvmax = std::max(pvmax, std::fabs(f16_to_f32(t16[i])));
+      }
+      c.pv16_exp = 0;
+      if (pvmax > 0.0f) (void)std::frexp(pvmax, &c.pv16_exp);
       for (size_t i = 0; i < crc.size(); ++i) c16[i] = f32_to_f16((float)(os * crc[i]));
       std::vector<float> v32(vrv.size());
       std::vector<f16_t> v16(vrv.size());
@@ -384,7 +390,7 @@ gwl_status gwl_set_option(gwl_ctx* ctx, int key, double value) {
         if (ctx->bf16_tile != (int)value || !ctx->tile_fixed) {
           ctx->bf16_tile = (int)value;
           ctx->tile_fixed = true;
-          ctx->tuned[GWL_MIXED_F16_BF16] = gwl_ctx::Tune{};
+          ctx->tuned[GWL_MIXED_F16] = gwl_ctx::Tune{};
           ctx->drop_graph();
         }
         break;

@@ -27,11 +27,12 @@ struct PoissonGeom {
 };
 
 // rin: [nparts][nf][ld_in] partial densities (summed); rout: [nf][ld_out].
-// scratch: [(nf+1)/2][N_r] complex.
+// scratch: [(nf+1)/2][N_r] complex.  vmax (optional, [nf]): receives
+// max_r |rout_f(r)| as float bits.
 template <typename T>
 void poisson_launch(const PoissonGeom<T>& g, const T* rin, long ld_in, long part_stride,
                     int nparts, T* rout, long ld_out, int nf, cplx<T>* scratch,
-                    hipStream_t st);
+                    hipStream_t st, unsigned* vmax = nullptr);
 
 // ---------------------------------------------------------------- GEMMs
 // Padded operand layouts (NRp, NVp, NCp multiples of the tile sizes):
@@ -66,12 +67,14 @@ void gemm1_f64(const GemmDims& d, int nb, const double* psi_c_rc, const double* 
 void gemm2_f64(const GemmDims& d, int nb, int splitk, const double* psi_v_t,
                const double* psi_c_t, const double* vpot, double* ypart, hipStream_t st);
 
-// BF16 operands, FP32 accumulation, plain FMA tiles (checks the MFMA kernels).
+// FP16 operands, FP32 accumulation, plain FMA tiles (checks the MFMA kernels;
+// the second GEMM's operand phi_v V_b s_b is rounded to FP16 as there).
 int gemm1_f16s_vtiles(const GemmDims& d);
 void gemm1_f16s(const GemmDims& d, int nb, const f16_t* psi_c_rc, const float* psi_v_rv,
                 const f16_t* u, float* rho_part, hipStream_t st);
-void gemm2_bf16s(const GemmDims& d, int nb, int splitk, const bf16_t* psi_v_t,
-                 const bf16_t* psi_c_t, const float* vpot, float* ypart, hipStream_t st);
+void gemm2_f16s(const GemmDims& d, int nb, int splitk, const f16_t* psi_v_t,
+                const f16_t* psi_c_t, const float* vpot, const unsigned* vmax, int pexp,
+                float* ypart, hipStream_t st);
 
 // FP64 on MFMA (v_mfma_f64_16x16x4).
 int gemm1_f64m_vtiles(const GemmDims& d);
@@ -80,18 +83,23 @@ void gemm1_f64m(const GemmDims& d, int nb, const double* psi_c_rc, const double*
 void gemm2_f64m(const GemmDims& d, int nb, int splitk, const double* psi_v_t,
                 const double* psi_c_t, const double* vpot, double* ypart, hipStream_t st);
 
-// BF16 operands, FP32 accumulation, on MFMA.
+// FP16 operands, FP32 accumulation, on MFMA.
 int gemm1_f16_vtiles(const GemmDims& d);
 // First GEMM of the mixed path: FP16 operands (u scaled by a power of two),
 // FP32 accumulation.  psi_v_rv: FP32 [N_rp][N_vp] epilogue weights;
 // psi_v_rv16: the same in FP16 (used when N_vp is 64 or 128)
 void gemm1_f16(const GemmDims& d, int nb, const f16_t* psi_c_rc, const float* psi_v_rv,
                const f16_t* psi_v_rv16, const f16_t* u, float* rho_part, hipStream_t st);
-// bn = block tile width of the second GEMM (128 or 256)
-int gemm2_bf16_blocks(const GemmDims& d, int nb, int bn);  // blocks per split of the K range
+// Second GEMM of the mixed path: A = f16(phi_v V_b s_b) formed while staging
+// (psi_v_t, psi_c_t: FP16 orbitals scaled by the orbital scale; vmax [nb]:
+// max_r |V_b| as float bits from the Poisson solve; pexp: frexp exponent of
+// the largest scaled orbital value; s_b = 2^f16_operand_exp(vmax_b, pexp)).
+// bn = block tile width (128 or 256).
+int gemm2_f16_blocks(const GemmDims& d, int nb, int bn);  // blocks per split of the K range
 int gemm2_f64m_blocks(const GemmDims& d, int nb);
-void gemm2_bf16(const GemmDims& d, int nb, int bn, int splitk, const bf16_t* psi_v_t,
-                const bf16_t* psi_c_t, const float* vpot, float* ypart, hipStream_t st);
+void gemm2_f16(const GemmDims& d, int nb, int bn, int splitk, const f16_t* psi_v_t,
+               const f16_t* psi_c_t, const float* vpot, const unsigned* vmax, int pexp,
+               float* ypart, hipStream_t st);
 
 // ---------------------------------------------------------------- pair-space ops
 struct PairGeom {
@@ -110,6 +118,10 @@ struct PairGeom {
   // cast_u / combine only: GEMM operand row b belongs to pair-vector slot
   // rows[b] (device, nb entries); nullptr = row b is slot b
   const int* rows = nullptr;
+  // mixed second GEMM: row b of its sum also carries s_b =
+  // 2^f16_operand_exp(vmax[b], pexp), divided out next to yscale
+  const unsigned* vmax = nullptr;
+  int pexp = 0;
 };
 
 // Elementwise orbital products rho_i = phi_{n_i} phi_{m_i} (FP64), [cnt][NRp].

@@ -76,12 +76,15 @@ __global__ void combine_kernel(PairGeom g, int nb, int splitk, const Y* __restri
   const Y* yb = ypart + (long)b * g.nvp * g.ncp;
   const double* xb = x + (long)slot * g.nvc;
   const double inv = 1.0 / (hi - lo);
+  // the mixed second GEMM's row scale s_b is divided out with the operand scales
+  const double ysc =
+      g.vmax ? ldexp(g.yscale, -f16_operand_exp(__uint_as_float(g.vmax[b]), g.pexp)) : g.yscale;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < g.nvc; i += (long)gridDim.x * blockDim.x) {
     const int v = (int)(i / g.nc), c = (int)(i - (long)v * g.nc);
     const long off = (long)v * g.ncp + c;
     double y = 0.0;
     for (int s = 0; s < splitk; ++s) y += (double)yb[s * stride_s + off];
-    y *= g.yscale;
+    y *= ysc;
     const double xi = xb[i];
     const long o = (long)slot * g.nvc + i;
     if (mode == 3) {  // A x = Delta x + K x

@@ -73,7 +73,7 @@ def test_binding_constants_match_header():
         assert getattr(B, "GWL_E" + name) == codes[name], name
     assert B.GWL_OK == 0
     prec = _header_enum("GWL_")
-    assert (B.FP64, B.MIXED_F16_BF16, B.MIXED_BF16X3, B.MIXED_FP32) == (
-        prec["FP64"], prec["MIXED_F16_BF16"], prec["MIXED_BF16X3"], prec["MIXED_FP32"])
+    assert (B.FP64, B.MIXED_F16, B.MIXED_BF16X3, B.MIXED_FP32) == (
+        prec["FP64"], prec["MIXED_F16"], prec["MIXED_BF16X3"], prec["MIXED_FP32"])
     assert B.REORTH == {"none": prec["REORTH_NONE"], "local": prec["REORTH_LOCAL"],
                         "full": prec["REORTH_FULL"]}
