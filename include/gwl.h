@@ -396,10 +396,19 @@ enum {
                                    results. */
   GWL_KEY_ADJOINT_STORED = 33,  /* query: 1 if the last gwl_sigma_c_vjp call kept the
                                    iterates, 0 if it recomputed them, -1 before a call */
-  GWL_KEY_HI_RESIDUAL = 34      /* query: residual bound |b_40 u_40| of the largest Ritz
+  GWL_KEY_HI_RESIDUAL = 34,     /* query: residual bound |b_40 u_40| of the largest Ritz
                                    value in the last estimate of the interval's upper end
                                    (hartree^2; 0 when no estimate ran or the recurrence
                                    ended in an invariant subspace) */
+  GWL_KEY_SCHEDULER = 35        /* set/query: 1 (default) = the batched Lanczos runs play the
+                                   whole refill schedule out on the host first (a slot runs
+                                   its start vector for exactly its length), upload it once
+                                   and then only queue work: no host synchronisation inside
+                                   the loop, and steps without a refill or a change of the
+                                   busy slots replay one graph of the whole step (product,
+                                   a_k, reorthogonalisation, b_{k+1}); 0 = the host-driven
+                                   loop (a synchronisation and host copies per refill, the
+                                   vector kernels launched eagerly).  Same coefficients. */
 };
 
 /* Device-memory cap for the run kept by gwl_sigma_c_vjp with

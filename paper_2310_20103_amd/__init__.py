@@ -9,7 +9,7 @@ from .binding import (Context, GwlError, lib, qp_solve, FP64, MIXED_F16, REORTH,
                       KEY_POLY_DEGREE, KEY_N_VC, KEY_LAST_MS_TOTAL, KEY_LAST_C_MATVECS,
                       KEY_GEMM_SPLITK, KEY_KERNELS, KEY_PROFILE, KEY_PROF, KEY_GRAPHS, KEY_TUNED_BLOCK,
                       KEY_TUNED_SPLITK, KEY_BF16_TILE, KEY_TDA, KEY_QUADRATURE, KEY_ISDF, KEY_ISDF_NMU,
-                      KEY_TUNED_TILE, KEY_ADJOINT_STORE, KEY_ADJOINT_STORED,
+                      KEY_TUNED_TILE, KEY_ADJOINT_STORE, KEY_ADJOINT_STORED, KEY_HI_RESIDUAL, KEY_SCHEDULER,
                       LIB_PATH)
 
 __all__ = ["Context", "GwlError", "lib", "LIB_PATH"]

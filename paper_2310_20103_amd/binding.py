@@ -25,7 +25,7 @@ KEY_N_VC, KEY_LAST_MS_TOTAL, KEY_LAST_C_MATVECS, KEY_GEMM_SPLITK, KEY_KERNELS = 
 KEY_PROFILE = 13
 KEY_GRAPHS, KEY_TUNED_BLOCK, KEY_TUNED_SPLITK, KEY_BF16_TILE, KEY_TDA = 23, 24, 25, 26, 27
 KEY_QUADRATURE, KEY_ISDF, KEY_ISDF_NMU, KEY_TUNED_TILE = 28, 29, 30, 31
-KEY_ADJOINT_STORE, KEY_ADJOINT_STORED, KEY_HI_RESIDUAL = 32, 33, 34
+KEY_ADJOINT_STORE, KEY_ADJOINT_STORED, KEY_HI_RESIDUAL, KEY_SCHEDULER = 32, 33, 34, 35
 KEY_PROF = {"gemm1": (14, 15, 16), "gemm2": (17, 18, 19), "fft": (20, 21, 22)}
 # "mixed" is the built 16-bit path; the last two are named by the ABI and
 # refused by the library (GWL_EUNSUPPORTED)

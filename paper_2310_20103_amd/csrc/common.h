@@ -74,10 +74,10 @@ __host__ __device__ inline float f16_to_f32(f16_t v) {
 }
 
 // Power-of-two scale of the second GEMM's FP16 operand phi_v(r) V_b(r) for
-// one pair vector b: with vmax = max_r |V_b(r)| and pmax = max |phi_v| (both
+// one pair vector b: with vmax >= max_r |V_b(r)| and pmax = max |phi_v| (both
 // as stored, i.e. with their own scales), vmax = m_v 2^ev and pmax = m_p 2^ep
 // (m in [0.5, 1)), the scale 2^(14 - ev - ep) keeps every product below 2^14,
-// inside FP16's range.  Exact and the same wherever it is evaluated.
+// inside FP16's range.  Returns the exponent.
 __host__ __device__ inline int f16_operand_exp(float vmax, int ep) {
   int ev = 0;
   if (vmax > 0.0f && vmax <= 3.0e38f) (void)frexpf(vmax, &ev);

@@ -180,7 +180,8 @@ struct gwl_ctx {
   DevBuf<double> psi_v_rv64;  // [NRp][NVp]
   DevBuf<f16_t> psi_t16;      // [NVp + NCp][NRp] FP16, scaled by orb16_scale
   int pv16_exp = 0;           // frexp exponent of max |phi_v| in psi_t16
-  DevBuf<unsigned> vmax32;    // [cap] max |V_b| of the mixed product's potentials
+  DevBuf<unsigned> xmax32;    // mixed Poisson solve: bound scratch per field pair
+  DevBuf<int> vexp32;         // [cap] scale exponent of each mixed potential
   DevBuf<f16_t> psi_c_rc16;   // [NRp][NCp] FP16, scaled by orb16_scale
   DevBuf<float> psi_v_rv32;   // [NRp][NVp] FP32, scaled (other mixed epilogues)
   DevBuf<f16_t> psi_v_rv16;   // [NRp][NVp] FP16, scaled (MFMA epilogue, N_vp <= 128)
@@ -227,6 +228,12 @@ struct gwl_ctx {
 
   // captured graph of one p_g(C) product over the Lanczos slots (q -> w)
   int use_graphs = 1;
+  // 1: run_pairs uploads its whole refill schedule once and replays a graph
+  // of the whole Lanczos step; 0: the host-driven loop (synchronous refills)
+  int sched_tables = 1;
+  hipGraphExec_t sgraph = nullptr;  // whole Lanczos step (product + alpha/reorth/beta)
+  std::vector<unsigned char> sg_key;
+  DevBuf<int> sched_tab;            // refill schedule of the current run_pairs call
   hipGraphExec_t dgraph = nullptr;
   int dg_nb = -1, dg_prec = -1, dg_S = -1, dg_kern = -1, dg_deg = -1;
   double dg_lo = 0, dg_hi = 0, dg_uscale = 0;
@@ -352,7 +359,8 @@ struct gwl_ctx {
       rho.ensure((size_t)nvt_max() * nb * gd.nrp * 8);
       vpot64.ensure((size_t)nb * gd.nrp);
       vpot32.ensure((size_t)alloc_rows_v(nb, gd.nvp) * gd.nrp);
-      vmax32.ensure((size_t)alloc_rows_v(nb, gd.nvp));
+      xmax32.ensure((size_t)alloc_rows_v(nb, gd.nvp));
+      vexp32.ensure((size_t)alloc_rows_v(nb, gd.nvp));
       fftx.ensure((size_t)((nb + 1) / 2) * nr * 16);
       ypart.ensure((size_t)32 * nb * nvpc * 8);
       s_pair.ensure(nb);
@@ -452,15 +460,16 @@ struct gwl_ctx {
         middle_step(nb, prec, nvt, rp, vp);
       else
         poisson_launch<float>(pg32, rp, d.nrp, (long)nb * d.nrp, nvt, vp, d.nrp, nb,
-                              reinterpret_cast<cplx<float>*>(fftx.p), st, vmax32.p);
+                              reinterpret_cast<cplx<float>*>(fftx.p), st, xmax32.p,
+                              vexp32.p, pv16_exp);
       prof_end(2, nb);
       const f16_t* pv = pt;
       const f16_t* pc = pt + (size_t)d.nvp * d.nrp;
       prof_begin();
       if (fp64_kernel)
-        gemm2_f16(d, nb, bf16_tile, S, pv, pc, vp, vmax32.p, pv16_exp, yp, st);
+        gemm2_f16(d, nb, bf16_tile, S, pv, pc, vp, yp, st);
       else
-        gemm2_f16s(d, nb, S, pv, pc, vp, vmax32.p, pv16_exp, yp, st);
+        gemm2_f16s(d, nb, S, pv, pc, vp, yp, st);
       prof_end(1, nb);
     }
   }
@@ -505,8 +514,7 @@ struct gwl_ctx {
       // first GEMM: u and both orbital factors scaled; second GEMM: phi_v and
       // phi_c scaled again, and s_b per row (g.vmax)
       g.yscale = 1.0 / (u_scale * orb16_scale * orb16_scale * orb16_scale * orb16_scale);
-      g.vmax = vmax32.p;
-      g.pexp = pv16_exp;
+      g.vexp = vexp32.p;
       combine<float, f16_t>(g, nb, S, reinterpret_cast<const float*>(ypart.p), x, tp, out,
                             acc, mode, poly_lo, poly_hi, c0, cj,
                             write_u ? u16.p : nullptr, stream);
@@ -564,10 +572,16 @@ struct gwl_ctx {
     GWL_HIP(hipStreamSynchronize(stream));
     GWL_HIP(hipMemcpy(s_m.p, mr.data(), cnt * sizeof(int), hipMemcpyHostToDevice));
     GWL_HIP(hipMemcpy(s_n.p, nrw.data(), cnt * sizeof(int), hipMemcpyHostToDevice));
+    coupling_rows(cnt, s_m.p, s_n.p, dst, ldp);
+  }
+
+  // Coupling vectors from orbital rows already on the device (mrow, nrow:
+  // [cnt] rows of psi_t); queued on the stream, no host synchronisation.
+  void coupling_rows(int cnt, const int* mrow, const int* nrow, double* dst, long ldp) {
     double* rp = reinterpret_cast<double*>(rho.p);
     double* vp = vpot64.p;
     double* yp = reinterpret_cast<double*>(ypart.p);
-    pair_product(psi_t.p, gd.nrp, (int)nr, s_m.p, s_n.p, cnt, rp, stream);
+    pair_product(psi_t.p, gd.nrp, (int)nr, mrow, nrow, cnt, rp, stream);
     poisson_launch<double>(pg64, rp, gd.nrp, 0, 1, vp, gd.nrp, cnt,
                            reinterpret_cast<cplx<double>*>(fftx.p), stream);
     const int S = auto_splitk(cnt, GWL_FP64);
@@ -630,6 +644,9 @@ struct gwl_ctx {
   void drop_graph() {
     if (dgraph) (void)hipGraphExecDestroy(dgraph);
     dgraph = nullptr;
+    if (sgraph) (void)hipGraphExecDestroy(sgraph);
+    sgraph = nullptr;
+    sg_key.clear();
   }
 
   // ---------------------------------------------------------------- autotuner
@@ -755,6 +772,15 @@ struct gwl_ctx {
   // ([P][ld]), norm2 [P], out_len [P] on the device.
   void run_pairs(int P, const int* m_host, const int* n_host, const int* len_host, int ld,
                  bool on_c = false, const double* start_dev = nullptr) {
+    if (sched_tables)
+      run_pairs_tables(P, m_host, n_host, len_host, ld, on_c, start_dev);
+    else
+      run_pairs_host(P, m_host, n_host, len_host, ld, on_c, start_dev);
+    if (!on_c && !tda) check_interval(P, ld);
+  }
+
+  // Slots B, buffers and the zeroed coefficient arrays of a run_pairs call.
+  int prepare_pairs(int P, int ld, bool full) {
     const int prec = precision;
     set_u_bound(1.0);  // Lanczos vectors have unit norm
     int B;
@@ -765,7 +791,6 @@ struct gwl_ctx {
       B = std::min(autotune(prec, bmem).B, bmem);
     }
     B = std::max(1, std::min(B, P));
-    const bool full = (reorth == GWL_REORTH_FULL);
     ensure_work(B, ld, full);
     coef_a.ensure((size_t)P * ld);
     coef_b.ensure((size_t)P * ld);
@@ -773,6 +798,10 @@ struct gwl_ctx {
     out_len.ensure(P);
     GWL_HIP(hipMemsetAsync(coef_a.p, 0, sizeof(double) * (size_t)P * ld, stream));
     GWL_HIP(hipMemsetAsync(coef_b.p, 0, sizeof(double) * (size_t)P * ld, stream));
+    return B;
+  }
+
+  SlotState slot_state(int ld) {
     SlotState ss;
     ss.pair = s_pair.p;
     ss.k = s_k.p;
@@ -785,6 +814,275 @@ struct gwl_ctx {
     ss.out_len = out_len.p;
     ss.norm2 = norm2.p;
     ss.ld = ld;
+    return ss;
+  }
+
+  // The product of one Lanczos step over nb slot rows (q -> w).
+  void step_product(int nb, int prec, bool on_c, bool eager) {
+    if (on_c)
+      apply_c_batch(nb, q.p, w.p, prec);
+    else if (tda)
+      apply_a_batch(nb, q.p, w.p, prec);
+    else if (eager) {
+      last_c_matvecs += (long)nb * poly_degree;
+      apply_d_batch(nb, q.p, w.p, prec, false);
+    } else
+      apply_d_step(nb, prec);
+  }
+
+  // One whole Lanczos step over all B slots -- the product, a_k, the
+  // reorthogonalisation against every stored row a slot has (rows beyond a
+  // slot's k return at once, so the launch shapes do not change from step
+  // to step) and b_{k+1} -- replayed from a captured graph while the shapes
+  // and buffers stay the same.
+  void lanczos_step_graph(int B, int ld, bool on_c, const SlotState& ss, bool full) {
+    const int prec = precision;
+    const long bstride = (long)ld * nvc;
+    auto body = [&]() {
+      step_product(B, prec, on_c, true);
+      lz_alpha(ss, B, q.p, qprev.p, w.p, nvc, stream);
+      lz_reorth(ss, B, ld - 1, reorth, full ? basis.p : nullptr, bstride, q.p, qprev.p, w.p,
+                hbuf.p, ReorthScratch{rw_n0.p, rw_part.p, rw_skip.p}, nvc, stream);
+      lz_beta(ss, B, q.p, qprev.p, w.p, full ? basis.p : nullptr, bstride, full ? 1 : 0, nvc,
+              stream);
+    };
+    const long cm = (long)B * (on_c || tda ? 1 : poly_degree);
+    if (!use_graphs || profile || isdf_on) {
+      body();  // (the ISDF product calls rocBLAS)
+      return;
+    }
+    // everything the captured launches depend on
+    struct Key {
+      int B, ld, on_c, tda, prec, S, kern, deg, reorth, tile;
+      long gen;
+      double lo, hi, us;
+      const void* p[8];
+      SlotState ss;
+    } key;
+    std::memset(&key, 0, sizeof(key));
+    key.B = B;
+    key.ld = ld;
+    key.on_c = on_c;
+    key.tda = tda;
+    key.prec = prec;
+    key.S = auto_splitk(B, prec);
+    key.kern = fp64_kernel;
+    key.deg = poly_degree;
+    key.reorth = reorth;
+    key.tile = bf16_tile;
+    key.gen = work_gen;
+    key.lo = poly_lo;
+    key.hi = poly_hi;
+    key.us = u_scale;
+    key.p[0] = basis.p;
+    key.p[1] = hbuf.p;
+    key.p[2] = rw_part.p;
+    key.p[3] = coef_a.p;
+    key.p[4] = coef_b.p;
+    key.p[5] = norm2.p;
+    key.p[6] = out_len.p;
+    key.p[7] = vexp32.p;
+    key.ss = ss;
+    const unsigned char* kb = reinterpret_cast<const unsigned char*>(&key);
+    std::vector<unsigned char> kv(kb, kb + sizeof(key));
+    if (!sgraph || kv != sg_key) {
+      if (sgraph) (void)hipGraphExecDestroy(sgraph);
+      sgraph = nullptr;
+      sg_key.clear();
+      hipGraph_t g = nullptr;
+      const long saved = last_c_matvecs;
+      GWL_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+      try {
+        body();
+      } catch (...) {
+        (void)hipStreamEndCapture(stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      GWL_HIP(hipStreamEndCapture(stream, &g));
+      last_c_matvecs = saved;
+      const hipError_t e = hipGraphInstantiate(&sgraph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) {
+        sgraph = nullptr;
+        throw Error{GWL_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e)};
+      }
+      sg_key = kv;
+    }
+    GWL_HIP(hipGraphLaunch(sgraph, stream));
+    last_c_matvecs += cm;
+  }
+
+  // Scheduler with the whole refill schedule on the device.  The order of
+  // refills is fixed by the lengths (a slot runs its start vector for exactly
+  // its length; a breakdown only freezes its coefficients), so the host
+  // plays the schedule out first, uploads it once (per refill event: the
+  // refilled slots, their orbital rows and the slot table after the event;
+  // per change of the busy set: its slot list) and then only queues work:
+  // no synchronisation or host-to-device copy inside the loop.  Steps with
+  // neither a refill nor a change of the busy set replay one graph of the
+  // whole step.
+  void run_pairs_tables(int P, const int* m_host, const int* n_host, const int* len_host,
+                        int ld, bool on_c, const double* start_dev) {
+    const int prec = precision;
+    const bool full = (reorth == GWL_REORTH_FULL);
+    const int B = prepare_pairs(P, ld, full);
+    const SlotState ss = slot_state(ld);
+    const long bstride = (long)ld * nvc;
+    // ---- play the schedule out on the host
+    struct Ev {
+      long step;
+      int cnt;
+      bool contiguous;
+      long o_slots, o_m, o_n, o_pair, o_len;  // offsets into tab
+    };
+    struct Act {
+      long step;
+      int nact;
+      long o_rows;  // -1: all B slots
+    };
+    std::vector<int> tab;
+    std::vector<Ev> evs;
+    std::vector<Act> acts;
+    long nsteps = 0;
+    {
+      std::vector<int> order(P);
+      for (int i = 0; i < P; ++i) order[i] = i;
+      std::stable_sort(order.begin(), order.end(),
+                       [&](int a, int b) { return len_host[a] > len_host[b]; });
+      std::vector<int> hp(B, -1), hk(B, 0), hl(B, 0), act, prev_act;
+      int next = 0;
+      for (long step = 0;; ++step) {
+        std::vector<int> slots, mr, nr_;
+        for (int b = 0; b < B && next < P; ++b)
+          if (hp[b] < 0 || hk[b] >= hl[b]) {
+            const int pi = order[next++];
+            hp[b] = pi;
+            hk[b] = 0;
+            hl[b] = len_host[pi];
+            slots.push_back(b);
+            mr.push_back(orb_row(m_host[pi]));
+            nr_.push_back(orb_row(n_host[pi]));
+          }
+        if (!slots.empty()) {
+          for (int b = 0; b < B; ++b)
+            if (hp[b] >= 0 && hk[b] >= hl[b]) hp[b] = -1;
+          Ev e;
+          e.step = step;
+          e.cnt = (int)slots.size();
+          e.contiguous = true;
+          for (int i = 0; i < e.cnt; ++i) e.contiguous &= (slots[i] == slots[0] + i);
+          auto put = [&](const std::vector<int>& v) {
+            const long o = (long)tab.size();
+            tab.insert(tab.end(), v.begin(), v.end());
+            return o;
+          };
+          e.o_slots = put(slots);
+          e.o_m = put(mr);
+          e.o_n = put(nr_);
+          e.o_pair = put(hp);
+          e.o_len = put(hl);
+          evs.push_back(e);
+        }
+        act.clear();
+        for (int b = 0; b < B; ++b)
+          if (hp[b] >= 0 && hk[b] < hl[b]) act.push_back(b);
+        if (act.empty()) {
+          nsteps = step;
+          break;
+        }
+        if (act != prev_act) {
+          Act a;
+          a.step = step;
+          a.nact = (int)act.size();
+          a.o_rows = -1;
+          if (a.nact < B) {
+            a.o_rows = (long)tab.size();
+            tab.insert(tab.end(), act.begin(), act.end());
+          }
+          acts.push_back(a);
+          prev_act = act;
+        }
+        for (int b = 0; b < B; ++b)
+          if (hp[b] >= 0 && hk[b] < hl[b]) ++hk[b];
+      }
+    }
+    // ---- upload it once
+    sched_tab.ensure(std::max<size_t>(tab.size(), 1));
+    GWL_HIP(hipMemcpyAsync(sched_tab.p, tab.data(), tab.size() * sizeof(int),
+                           hipMemcpyHostToDevice, stream));
+    GWL_HIP(hipStreamSynchronize(stream));  // tab may go once the copy is done
+    const int* T = sched_tab.p;
+    // ---- run
+    size_t ie = 0, ia = 0;
+    int nact = B;
+    const int* rows = nullptr;
+    for (long step = 0; step < nsteps; ++step) {
+      if (ie < evs.size() && evs[ie].step == step) {
+        const Ev& e = evs[ie++];
+        GWL_HIP(hipMemcpyAsync(s_pair.p, T + e.o_pair, B * sizeof(int), hipMemcpyDeviceToDevice,
+                               stream));
+        GWL_HIP(hipMemcpyAsync(s_len.p, T + e.o_len, B * sizeof(int), hipMemcpyDeviceToDevice,
+                               stream));
+        std::vector<int> hs;  // host copy of the slot list, for the row copies below
+        if (start_dev || !e.contiguous) hs.assign(tab.begin() + e.o_slots, tab.begin() + e.o_slots + e.cnt);
+        if (start_dev) {
+          const int* hpair = tab.data() + e.o_pair;
+          for (int i = 0; i < e.cnt; ++i)
+            GWL_HIP(hipMemcpyAsync(q.p + (size_t)hs[i] * nvc,
+                                   start_dev + (size_t)hpair[hs[i]] * nvc, nvc * sizeof(double),
+                                   hipMemcpyDeviceToDevice, stream));
+        } else if (e.contiguous) {
+          coupling_rows(e.cnt, T + e.o_m, T + e.o_n, q.p + (size_t)tab[e.o_slots] * nvc, nvc);
+        } else {
+          coupling_rows(e.cnt, T + e.o_m, T + e.o_n, w.p, nvc);
+          for (int i = 0; i < e.cnt; ++i)
+            GWL_HIP(hipMemcpyAsync(q.p + (size_t)hs[i] * nvc, w.p + (size_t)i * nvc,
+                                   nvc * sizeof(double), hipMemcpyDeviceToDevice, stream));
+        }
+        lz_start(ss, B, T + e.o_slots, e.cnt, q.p, qprev.p, full ? basis.p : nullptr, bstride,
+                 nvc, stream);
+      }
+      if (ia < acts.size() && acts[ia].step == step) {
+        nact = acts[ia].nact;
+        rows = acts[ia].o_rows >= 0 ? T + acts[ia].o_rows : nullptr;
+        ++ia;
+      }
+      if (!rows) {
+        lanczos_step_graph(B, ld, on_c, ss, full);
+      } else {
+        cur_rows = rows;
+        try {
+          step_product(nact, prec, on_c, true);
+        } catch (...) {
+          cur_rows = nullptr;
+          throw;
+        }
+        cur_rows = nullptr;
+        lz_alpha(ss, B, q.p, qprev.p, w.p, nvc, stream);
+        lz_reorth(ss, B, ld - 1, reorth, full ? basis.p : nullptr, bstride, q.p, qprev.p, w.p,
+                  hbuf.p, ReorthScratch{rw_n0.p, rw_part.p, rw_skip.p}, nvc, stream);
+        lz_beta(ss, B, q.p, qprev.p, w.p, full ? basis.p : nullptr, bstride, full ? 1 : 0,
+                nvc, stream);
+      }
+      if (profile && prof_recs.size() > 4096) {
+        GWL_HIP(hipStreamSynchronize(stream));
+        prof_flush();
+      }
+    }
+    GWL_HIP(hipStreamSynchronize(stream));
+    prof_flush();
+  }
+
+  // The host-driven scheduler: refills decided and uploaded step by step
+  // (a host synchronisation and copies per refill); the product of a step is
+  // a replayed graph, the vector kernels are launched eagerly.
+  void run_pairs_host(int P, const int* m_host, const int* n_host, const int* len_host, int ld,
+                      bool on_c, const double* start_dev) {
+    const int prec = precision;
+    const bool full = (reorth == GWL_REORTH_FULL);
+    const int B = prepare_pairs(P, ld, full);
+    const SlotState ss = slot_state(ld);
     const long bstride = (long)ld * nvc;
     std::vector<int> hp(B, -1), hk(B, 0), hl(B, 0);
     GWL_HIP(hipMemcpyAsync(s_pair.p, hp.data(), B * sizeof(int), hipMemcpyHostToDevice, stream));
@@ -890,7 +1188,6 @@ struct gwl_ctx {
     }
     GWL_HIP(hipStreamSynchronize(stream));
     prof_flush();
-    if (!on_c && !tda) check_interval(P, ld);
   }
 
   int auto_block(int P, int L) const {

@@ -4,10 +4,13 @@
 //
 // gfx950 design: HBM-bound.  Two real fields are packed into one complex
 // field (exact because v(G) is real and even, so each real field maps to a
-// real potential).  The 3-D transform is five passes of batched 1-D
-// transforms, each staging a batch of lines through LDS:
-//   z forward (+ pack, + sum of GEMM partials) -> y forward ->
-//   x forward, multiply by v(G)/N, x inverse -> y inverse -> z inverse (+ unpack).
+// real potential).  When a yz plane (fixed x, contiguous in memory) and its
+// ping-pong copy fit in LDS, the 3-D transform is three passes, each one
+// HBM round trip:
+//   yz forward (+ pack, + sum of GEMM partials) ->
+//   x forward, multiply by v(G)/N, x inverse -> yz inverse (+ unpack);
+// otherwise five passes of batched 1-D transforms:
+//   z forward (+ pack) -> y forward -> x (as above) -> y inverse -> z inverse.
 // The 1-D transforms are mixed-radix (2, 3, 4, 8) Stockham autosort passes
 // with ping-pong LDS buffers (Govindaraju et al., SC'08 formulation); the
 // inverse uses conj(FFT(conj(x))).
@@ -79,50 +82,61 @@ __device__ inline void dft8(cplx<T>* v) {
   v[7] = csub(e[3], o3);
 }
 
-// One Stockham radix-R stage over nl lines (line stride ls) from in to out.
-template <typename T, int R>
+// One Stockham radix-R stage over nl lines from in to out.  Element i of line
+// l sits at l * ls + i * es.  LINE_FAST: consecutive threads take consecutive
+// lines (for lines whose elements are strided in LDS, so that a wave's
+// accesses stay on consecutive addresses); otherwise consecutive butterflies
+// of one line.
+template <typename T, int R, bool LINE_FAST>
 __device__ inline void fft_stage(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
-                                 int nl, int n, int ls, int ns,
+                                 int nl, int n, int ls, int es, int ns,
                                  const cplx<T>* __restrict__ tw) {
   const int m = n / R;
   const int tstride = n / (ns * R);
   const int total = nl * m;
   for (int bf = threadIdx.x; bf < total; bf += blockDim.x) {
-    const int line = bf / m;
-    const int j = bf - line * m;
+    int line, j;
+    if (LINE_FAST) {
+      j = bf / nl;
+      line = bf - j * nl;
+    } else {
+      line = bf / m;
+      j = bf - line * m;
+    }
     const int jq = j / ns;
     const int k = j - jq * ns;
     cplx<T> v[R];
-    const cplx<T>* src = in + line * ls + j;
+    const cplx<T>* src = in + line * ls + j * es;
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = src[r * m];
+    for (int r = 0; r < R; ++r) v[r] = src[r * m * es];
 #pragma unroll
     for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[r * k * tstride]);
     if constexpr (R == 2) dft2(v);
     if constexpr (R == 3) dft3(v);
     if constexpr (R == 4) dft4(v);
     if constexpr (R == 8) dft8(v);
-    cplx<T>* dst = out + line * ls + jq * ns * R + k;
+    cplx<T>* dst = out + line * ls + (jq * ns * R + k) * es;
 #pragma unroll
-    for (int r = 0; r < R; ++r) dst[r * ns] = v[r];
+    for (int r = 0; r < R; ++r) dst[r * ns * es] = v[r];
   }
 }
 
-// Transform nl lines of length n held in LDS at buf0 (line stride ls).
-// Returns the buffer that holds the result.  All threads of the block call it.
-template <typename T>
+// Transform nl lines of length n held in LDS at buf0 (line stride ls,
+// element stride es).  Returns the buffer that holds the result.  All
+// threads of the block call it.
+template <typename T, bool LINE_FAST = false>
 __device__ cplx<T>* fft_lines(cplx<T>* buf0, cplx<T>* buf1, int nl, int n, int ls,
-                              const FftPlan& plan, const cplx<T>* __restrict__ tw) {
+                              const FftPlan& plan, const cplx<T>* __restrict__ tw, int es = 1) {
   cplx<T>* in = buf0;
   cplx<T>* out = buf1;
   int ns = 1;
   for (int s = 0; s < plan.nstages; ++s) {
     const int R = plan.radix[s];
     switch (R) {
-      case 2: fft_stage<T, 2>(in, out, nl, n, ls, ns, tw); break;
-      case 3: fft_stage<T, 3>(in, out, nl, n, ls, ns, tw); break;
-      case 4: fft_stage<T, 4>(in, out, nl, n, ls, ns, tw); break;
-      default: fft_stage<T, 8>(in, out, nl, n, ls, ns, tw); break;
+      case 2: fft_stage<T, 2, LINE_FAST>(in, out, nl, n, ls, es, ns, tw); break;
+      case 3: fft_stage<T, 3, LINE_FAST>(in, out, nl, n, ls, es, ns, tw); break;
+      case 4: fft_stage<T, 4, LINE_FAST>(in, out, nl, n, ls, es, ns, tw); break;
+      default: fft_stage<T, 8, LINE_FAST>(in, out, nl, n, ls, es, ns, tw); break;
     }
     __syncthreads();
     cplx<T>* t = in;
@@ -131,6 +145,108 @@ __device__ cplx<T>* fft_lines(cplx<T>* buf0, cplx<T>* buf1, int nl, int n, int l
     ns *= R;
   }
   return in;
+}
+
+// Largest |value| over the block, one atomic maximum (float bits:
+// non-negative floats order like their bit patterns, so the result does not
+// depend on the order of the atomics).
+template <typename T>
+__device__ inline void block_max_atomic(T m, unsigned* dst) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  __shared__ float wm[4];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) wm[wid] = (float)m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float a = 0.0f;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) a = fmaxf(a, wm[i]);
+    atomicMax(dst, __float_as_uint(a));
+  }
+}
+
+// Optional output scaling of the mixed product (FP16 operands downstream):
+// the x pass records xmax[p] = max(|Re X|, |Im X|) over its output for the
+// field pair p; the rest of the transform is an unnormalised inverse DFT over
+// the ny nz (y, z) frequencies, so every potential value obeys
+// |V| <= 2 ny nz xmax[p] (|X| <= sqrt 2 max(|Re|, |Im|)), and the last pass
+// multiplies both fields by 2^e, e = f16_operand_exp(2 ny nz xmax[p], pexp),
+// recording e in vexp[f].  The first pass clears xmax.
+struct VScale {
+  unsigned* xmax;  // [npairs] float bits, or nullptr (no scaling)
+  int* vexp;       // [nf]
+  int pexp;
+};
+
+// Transform of whole yz planes (fixed x, contiguous in memory): the z lines,
+// then the y lines, both in LDS, so the plane crosses HBM once each way.
+// Forward: builds the complex field from the real fields 2p and 2p+1 (summing
+// nparts GEMM partial densities) and clears vmax.  Inverse (conj(FFT(conj)),
+// y lines then z lines): writes the real part to field 2p and the imaginary
+// part to field 2p+1 and leaves each field's max |V| in vmax.
+template <typename T, bool INVERSE>
+__global__ void __launch_bounds__(256)
+fft_pass_yz(cplx<T>* __restrict__ X, const T* __restrict__ rin, T* __restrict__ rout, int nf,
+            long ld_real, long part_stride, int nparts, int ny, int nz, long nr, FftPlan py,
+            FftPlan pz, const cplx<T>* __restrict__ twy, const cplx<T>* __restrict__ twz,
+            VScale vs) {
+  extern __shared__ unsigned char smem_raw[];
+  const int ls = nz + 1;
+  cplx<T>* buf0 = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* buf1 = buf0 + ny * ls;
+  const int pair = blockIdx.y;
+  const int f0 = 2 * pair, f1 = 2 * pair + 1;
+  const long base = (long)blockIdx.x * ny * nz;
+  cplx<T>* Xp = X + (long)pair * nr;
+  const int cnt = ny * nz;
+  for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+    const int y = e / nz, z = e - y * nz;
+    cplx<T> v;
+    if (!INVERSE) {
+      T a = 0, b = 0;
+      for (int q = 0; q < nparts; ++q) {
+        const T* src = rin + (long)q * part_stride;
+        a += src[(long)f0 * ld_real + base + e];
+        if (f1 < nf) b += src[(long)f1 * ld_real + base + e];
+      }
+      v = {a, b};
+    } else {
+      v = Xp[base + e];
+      v.y = -v.y;
+    }
+    buf0[y * ls + z] = v;
+  }
+  __syncthreads();
+  cplx<T>* res;
+  if (!INVERSE) {
+    res = fft_lines<T>(buf0, buf1, ny, nz, ls, pz, twz);
+    cplx<T>* oth = (res == buf0) ? buf1 : buf0;
+    res = fft_lines<T, true>(res, oth, nz, ny, 1, py, twy, ls);
+  } else {
+    res = fft_lines<T, true>(buf0, buf1, nz, ny, 1, py, twy, ls);
+    cplx<T>* oth = (res == buf0) ? buf1 : buf0;
+    res = fft_lines<T>(res, oth, ny, nz, ls, pz, twz);
+  }
+  T sc = 1;
+  if (INVERSE && vs.xmax) {
+    const int e = f16_operand_exp(__uint_as_float(vs.xmax[pair]) * (float)(2 * ny * nz), vs.pexp);
+    sc = (T)ldexpf(1.0f, e);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      vs.vexp[f0] = e;
+      if (f1 < nf) vs.vexp[f1] = e;
+    }
+  }
+  if (!INVERSE && vs.xmax && blockIdx.x == 0 && threadIdx.x == 0) vs.xmax[pair] = 0u;
+  for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+    const int y = e / nz, z = e - y * nz;
+    const cplx<T> v = res[y * ls + z];
+    if (!INVERSE) {
+      Xp[base + e] = v;
+    } else {
+      rout[(long)f0 * ld_real + base + e] = sc * v.x;
+      if (f1 < nf) rout[(long)f1 * ld_real + base + e] = -(sc * v.y);
+    }
+  }
 }
 
 // Pass along z (contiguous lines).  Forward: builds the complex field from the
@@ -143,8 +259,8 @@ template <typename T, bool INVERSE>
 __global__ void __launch_bounds__(256)
 fft_pass_z(cplx<T>* __restrict__ X, const T* __restrict__ rin, T* __restrict__ rout,
            int nf, long ld_real, long part_stride, int nparts, int nlines, int nz,
-           long nr, int lpb, FftPlan plan, const cplx<T>* __restrict__ tw,
-           unsigned* __restrict__ vmax) {
+           long nr, int lpb, FftPlan plan, const cplx<T>* __restrict__ tw, VScale vs,
+           int nyz) {
   extern __shared__ unsigned char smem_raw[];
   cplx<T>* buf0 = reinterpret_cast<cplx<T>*>(smem_raw);
   const int ls = nz + 1;
@@ -176,48 +292,24 @@ fft_pass_z(cplx<T>* __restrict__ X, const T* __restrict__ rin, T* __restrict__ r
   }
   __syncthreads();
   cplx<T>* res = fft_lines<T>(buf0, buf1, nl, nz, ls, plan, tw);
-  T m0 = 0, m1 = 0;
+  T sc = 1;
+  if (INVERSE && vs.xmax) {
+    const int e = f16_operand_exp(__uint_as_float(vs.xmax[pair]) * (float)(2 * nyz), vs.pexp);
+    sc = (T)ldexpf(1.0f, e);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      vs.vexp[f0] = e;
+      if (f1 < nf) vs.vexp[f1] = e;
+    }
+  }
+  if (!INVERSE && vs.xmax && blockIdx.x == 0 && threadIdx.x == 0) vs.xmax[pair] = 0u;
   for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
     const int l = e / nz, p = e - l * nz;
     cplx<T> v = res[l * ls + p];
     if (!INVERSE) {
       Xp[base + e] = v;
     } else {
-      rout[(long)f0 * ld_real + base + e] = v.x;
-      if (f1 < nf) rout[(long)f1 * ld_real + base + e] = -v.y;
-      m0 = fmax(m0, fabs(v.x));
-      m1 = fmax(m1, fabs(v.y));
-    }
-  }
-  if (vmax) {
-    if (!INVERSE) {
-      if (blockIdx.x == 0 && threadIdx.x == 0) {
-        vmax[f0] = 0u;
-        if (f1 < nf) vmax[f1] = 0u;
-      }
-    } else {
-      // block maximum, then one atomic per field
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        m0 = fmax(m0, __shfl_xor(m0, off, 64));
-        m1 = fmax(m1, __shfl_xor(m1, off, 64));
-      }
-      __shared__ float wm[2][4];
-      const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-      if (lane == 0) {
-        wm[0][wid] = (float)m0;
-        wm[1][wid] = (float)m1;
-      }
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        float a = 0.0f, b = 0.0f;
-        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
-          a = fmaxf(a, wm[0][i]);
-          b = fmaxf(b, wm[1][i]);
-        }
-        atomicMax(&vmax[f0], __float_as_uint(a));
-        if (f1 < nf) atomicMax(&vmax[f1], __float_as_uint(b));
-      }
+      rout[(long)f0 * ld_real + base + e] = sc * v.x;
+      if (f1 < nf) rout[(long)f1 * ld_real + base + e] = -(sc * v.y);
     }
   }
 }
@@ -232,7 +324,7 @@ fft_pass_strided(cplx<T>* __restrict__ X, int n, long pstride, long outer_stride
                  int nzb, int nz, long nr, int lpb, FftPlan plan,
                  const cplx<T>* __restrict__ tw, const T* __restrict__ g2x,
                  const T* __restrict__ g2y, const T* __restrict__ g2z, T vscale,
-                 int ny) {
+                 int ny, unsigned* __restrict__ xmax) {
   extern __shared__ unsigned char smem_raw[];
   cplx<T>* buf0 = reinterpret_cast<cplx<T>*>(smem_raw);
   const int ls = n + 1;
@@ -266,13 +358,19 @@ fft_pass_strided(cplx<T>* __restrict__ X, int n, long pstride, long outer_stride
     __syncthreads();
     res = fft_lines<T>(other, res, nl, n, ls, plan, tw);
   }
+  T mx = 0;
   for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
     const int p = e / nl, l = e - p * nl;
     cplx<T> v = res[l * ls + p];
     if (MODE == 1 || MODE == 2) v.y = -v.y;
     Xp[(long)p * pstride + l] = v;
+    mx = fmax(mx, fmax(fabs(v.x), fabs(v.y)));
   }
+  if (MODE == 2 && xmax) block_max_atomic(mx, &xmax[pair]);
 }
+
+// LDS of the yz-plane pass (two planes); larger planes take the five-pass route
+constexpr size_t kYzLdsMax = 80 * 1024;
 
 // Lines per block of the contiguous (z) pass: about 16 KB of complex data per
 // LDS buffer, between 4 and 32 lines.
@@ -285,6 +383,19 @@ int lines_per_block(int n) {
 }
 
 }  // namespace
+
+void poisson_prepare_device() {
+  // dynamic LDS beyond 64 KB must be allowed per kernel, on the current device
+  const int lim = (int)kYzLdsMax;
+  GWL_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&fft_pass_yz<float, false>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+  GWL_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&fft_pass_yz<float, true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+  GWL_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&fft_pass_yz<double, false>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+  GWL_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&fft_pass_yz<double, true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+}
 
 FftPlan make_plan(int n) {
   FftPlan p{};
@@ -300,11 +411,39 @@ FftPlan make_plan(int n) {
 template <typename T>
 void poisson_launch(const PoissonGeom<T>& g, const T* rin, long ld_in, long part_stride,
                     int nparts, T* rout, long ld_out, int nf, cplx<T>* scratch,
-                    hipStream_t st, unsigned* vmax) {
+                    hipStream_t st, unsigned* xmax, int* vexp, int pexp) {
+  const VScale vs{vexp ? xmax : nullptr, vexp, pexp};
+  unsigned* xm = vs.xmax;
+  const int nyz = g.ny * g.nz;
   if (nf <= 0) return;
   const int npairs = (nf + 1) / 2;
   const long nr = (long)g.nx * g.ny * g.nz;
-  // z forward + pack
+  const int nmax = g.nx > g.ny ? g.nx : g.ny;
+  int lpb = 1024 / nmax;
+  if (lpb > 16) lpb = 16;
+  if (lpb < 2) lpb = 2;
+  if (lpb > g.nz) lpb = g.nz;
+  const int nzb = ceil_div(g.nz, lpb);
+  // Three HBM round trips when a yz plane and its ping-pong copy fit in LDS:
+  // yz forward (+ pack), x forward / kernel / x inverse, yz inverse (+ unpack)
+  const size_t sm_yz = 2 * (size_t)g.ny * (g.nz + 1) * sizeof(cplx<T>);
+  if (sm_yz <= kYzLdsMax) {
+    dim3 gyz(g.nx, npairs);
+    fft_pass_yz<T, false><<<gyz, 256, sm_yz, st>>>(scratch, rin, nullptr, nf, ld_in, part_stride,
+                                                   nparts, g.ny, g.nz, nr, g.py, g.pz, g.twy,
+                                                   g.twz, vs);
+    dim3 grid(g.ny * nzb, npairs);
+    size_t sm = 2 * (size_t)lpb * (g.nx + 1) * sizeof(cplx<T>);
+    fft_pass_strided<T, 2><<<grid, 256, sm, st>>>(scratch, g.nx, (long)g.ny * g.nz, g.nz,
+                                                  nzb, g.nz, nr, lpb, g.px, g.twx, g.g2x,
+                                                  g.g2y, g.g2z, g.vscale, g.ny, xm);
+    fft_pass_yz<T, true><<<gyz, 256, sm_yz, st>>>(scratch, nullptr, rout, nf, ld_out, 0, 1,
+                                                  g.ny, g.nz, nr, g.py, g.pz, g.twy, g.twz,
+                                                  vs);
+    GWL_HIP(hipGetLastError());
+    return;
+  }
+  // otherwise five: z forward + pack
   {
     const int lpb = lines_per_block<T>(g.nz);
     const int nlines = g.nx * g.ny;
@@ -312,21 +451,15 @@ void poisson_launch(const PoissonGeom<T>& g, const T* rin, long ld_in, long part
     size_t sm = 2 * (size_t)lpb * (g.nz + 1) * sizeof(cplx<T>);
     fft_pass_z<T, false><<<grid, 256, sm, st>>>(scratch, rin, nullptr, nf, ld_in,
                                                 part_stride, nparts, nlines, g.nz, nr,
-                                                lpb, g.pz, g.twz, vmax);
+                                                lpb, g.pz, g.twz, vs, nyz);
   }
-  const int nmax = g.nx > g.ny ? g.nx : g.ny;
-  int lpb = 1024 / nmax;
-  if (lpb > 16) lpb = 16;
-  if (lpb < 2) lpb = 2;
-  if (lpb > g.nz) lpb = g.nz;
-  const int nzb = ceil_div(g.nz, lpb);
   // y forward
   {
     dim3 grid(g.nx * nzb, npairs);
     size_t sm = 2 * (size_t)lpb * (g.ny + 1) * sizeof(cplx<T>);
     fft_pass_strided<T, 0><<<grid, 256, sm, st>>>(scratch, g.ny, g.nz, (long)g.ny * g.nz,
                                                   nzb, g.nz, nr, lpb, g.py, g.twy, nullptr,
-                                                  nullptr, nullptr, (T)0, g.ny);
+                                                  nullptr, nullptr, (T)0, g.ny, nullptr);
   }
   // x forward, kernel, x inverse
   {
@@ -334,7 +467,7 @@ void poisson_launch(const PoissonGeom<T>& g, const T* rin, long ld_in, long part
     size_t sm = 2 * (size_t)lpb * (g.nx + 1) * sizeof(cplx<T>);
     fft_pass_strided<T, 2><<<grid, 256, sm, st>>>(scratch, g.nx, (long)g.ny * g.nz, g.nz,
                                                   nzb, g.nz, nr, lpb, g.px, g.twx, g.g2x,
-                                                  g.g2y, g.g2z, g.vscale, g.ny);
+                                                  g.g2y, g.g2z, g.vscale, g.ny, xm);
   }
   // y inverse
   {
@@ -342,7 +475,7 @@ void poisson_launch(const PoissonGeom<T>& g, const T* rin, long ld_in, long part
     size_t sm = 2 * (size_t)lpb * (g.ny + 1) * sizeof(cplx<T>);
     fft_pass_strided<T, 1><<<grid, 256, sm, st>>>(scratch, g.ny, g.nz, (long)g.ny * g.nz,
                                                   nzb, g.nz, nr, lpb, g.py, g.twy, nullptr,
-                                                  nullptr, nullptr, (T)0, g.ny);
+                                                  nullptr, nullptr, (T)0, g.ny, nullptr);
   }
   // z inverse + unpack
   {
@@ -351,15 +484,16 @@ void poisson_launch(const PoissonGeom<T>& g, const T* rin, long ld_in, long part
     dim3 grid(ceil_div(nlines, lpbz), npairs);
     size_t sm = 2 * (size_t)lpbz * (g.nz + 1) * sizeof(cplx<T>);
     fft_pass_z<T, true><<<grid, 256, sm, st>>>(scratch, nullptr, rout, nf, ld_out, 0, 1,
-                                               nlines, g.nz, nr, lpbz, g.pz, g.twz, vmax);
+                                               nlines, g.nz, nr, lpbz, g.pz, g.twz, vs, nyz);
   }
   GWL_HIP(hipGetLastError());
 }
 
 template void poisson_launch<float>(const PoissonGeom<float>&, const float*, long, long, int,
-                                    float*, long, int, cplx<float>*, hipStream_t, unsigned*);
+                                    float*, long, int, cplx<float>*, hipStream_t, unsigned*,
+                                    int*, int);
 template void poisson_launch<double>(const PoissonGeom<double>&, const double*, long, long,
                                      int, double*, long, int, cplx<double>*, hipStream_t,
-                                     unsigned*);
+                                     unsigned*, int*, int);
 
 }  // namespace gwl

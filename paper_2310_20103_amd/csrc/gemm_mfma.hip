@@ -307,6 +307,7 @@ struct LoadU16 {  // plain [M][K] rows
 #pragma unroll
     for (int q = 0; q < 4; ++q) r.c[q] = *reinterpret_cast<const u4*>(p + (long)64 * q * lda);
   }
+  __device__ void prep(Raw&) const {}
   __device__ u4 finish(const Raw& r, int q) const { return r.c[q]; }
 };
 
@@ -326,13 +327,12 @@ __device__ inline u4 scale8(u4 pv, f4v v0, f4v v1) {
   return out;
 }
 
-// A[(b,v)][r] = f16(phi_v(r) V_b(r) s_b), phi_v in FP16 (scaled) and s_b the
-// power of two that keeps the pair vector's products inside FP16's range
-// (f16_operand_exp of max_r |V_b| and the orbitals' maximum), applied to the
-// potential as it is loaded.  NVP = padded N_v when it is 64 or 128 (a
-// thread's four rows then share one or two phi_v rows and use four or two
-// potentials), 256 when it is a multiple of 256 (a tile lies inside one pair
-// vector: four phi_v rows, one potential), 0 otherwise.
+// A[(b,v)][r] = f16(phi_v(r) V_b(r)), phi_v in FP16 and V_b as the Poisson
+// solve wrote it (both already scaled by powers of two into FP16's range).
+// NVP = padded N_v when it is 64 or 128 (a thread's four rows then share one
+// or two phi_v rows and use four or two potentials), 256 when it is a
+// multiple of 256 (a tile lies inside one pair vector: four phi_v rows, one
+// potential), 0 otherwise.
 template <int NVP>
 struct LoadPsiV16 {
   const f16_t* psi_v_t;
@@ -341,25 +341,10 @@ struct LoadPsiV16 {
   int nvp;
   static constexpr int NPV = NVP == 64 ? 1 : (NVP == 128 ? 2 : 4);
   static constexpr int NB = NVP == 128 ? 2 : (NVP == 256 ? 1 : 4);
-  float sc[NB];  // s_b of the potentials this thread loads
   struct Raw {
     u4 pv[NPV];
     f4v v[NB][2];
   };
-  __device__ LoadPsiV16(const f16_t* pv, const float* vp, long nrp_, int nvp_, int m0, int t,
-                        const unsigned* __restrict__ vmax, int pexp)
-      : psi_v_t(pv), vpot(vp), nrp(nrp_), nvp(nvp_) {
-    const int r0 = t >> 2;
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      int b;
-      if constexpr (NVP == 64) b = m0 / 64 + i;
-      else if constexpr (NVP == 128) b = m0 / 128 + i;
-      else if constexpr (NVP == 256) b = m0 / nvp;
-      else b = (m0 + r0 + 64 * i) / nvp;
-      sc[i] = ldexpf(1.0f, f16_operand_exp(__uint_as_float(vmax[b]), pexp));
-    }
-  }
   __device__ void load(int m0, int t, int k0, Raw& r) const {
     const int k = k0 + (t & 3) * 8;
     const int r0 = t >> 2;
@@ -368,8 +353,8 @@ struct LoadPsiV16 {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const float* vp = vpot + (long)(m0 / 64 + q) * nrp + k;
-        r.v[q][0] = *reinterpret_cast<const f4v*>(vp) * sc[q];
-        r.v[q][1] = *reinterpret_cast<const f4v*>(vp + 4) * sc[q];
+        r.v[q][0] = *reinterpret_cast<const f4v*>(vp);
+        r.v[q][1] = *reinterpret_cast<const f4v*>(vp + 4);
       }
     } else if constexpr (NVP == 128) {
       r.pv[0] = *reinterpret_cast<const u4*>(psi_v_t + (long)r0 * nrp + k);
@@ -377,8 +362,8 @@ struct LoadPsiV16 {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const float* vp = vpot + (long)(m0 / 128 + h) * nrp + k;
-        r.v[h][0] = *reinterpret_cast<const f4v*>(vp) * sc[h];
-        r.v[h][1] = *reinterpret_cast<const f4v*>(vp + 4) * sc[h];
+        r.v[h][0] = *reinterpret_cast<const f4v*>(vp);
+        r.v[h][1] = *reinterpret_cast<const f4v*>(vp + 4);
       }
     } else if constexpr (NVP == 256) {
       const int b = m0 / nvp, v0 = m0 - b * nvp + r0;
@@ -386,8 +371,8 @@ struct LoadPsiV16 {
       for (int q = 0; q < 4; ++q)
         r.pv[q] = *reinterpret_cast<const u4*>(psi_v_t + (long)(v0 + 64 * q) * nrp + k);
       const float* vp = vpot + (long)b * nrp + k;
-      r.v[0][0] = *reinterpret_cast<const f4v*>(vp) * sc[0];
-      r.v[0][1] = *reinterpret_cast<const f4v*>(vp + 4) * sc[0];
+      r.v[0][0] = *reinterpret_cast<const f4v*>(vp);
+      r.v[0][1] = *reinterpret_cast<const f4v*>(vp + 4);
     } else {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -395,11 +380,12 @@ struct LoadPsiV16 {
         const int b = m / nvp, vv = m - b * nvp;
         r.pv[q] = *reinterpret_cast<const u4*>(psi_v_t + (long)vv * nrp + k);
         const float* vp = vpot + (long)b * nrp + k;
-        r.v[q][0] = *reinterpret_cast<const f4v*>(vp) * sc[q];
-        r.v[q][1] = *reinterpret_cast<const f4v*>(vp + 4) * sc[q];
+        r.v[q][0] = *reinterpret_cast<const f4v*>(vp);
+        r.v[q][1] = *reinterpret_cast<const f4v*>(vp + 4);
       }
     }
   }
+  __device__ void prep(Raw&) const {}
   __device__ u4 finish(const Raw& r, int q) const {
     if constexpr (NVP == 64) return scale8(r.pv[0], r.v[q][0], r.v[q][1]);
     else if constexpr (NVP == 128) return scale8(r.pv[q & 1], r.v[q >> 1][0], r.v[q >> 1][1]);
@@ -433,9 +419,9 @@ __device__ inline void bf_gload(const LA& la, const bf16_t* __restrict__ bop, lo
 }
 
 template <typename LA, int BN>
-__device__ inline void bf_lstore(const LA& la, BfSmem<BN>& sm, int buf,
-                                 const BfStage<LA, BN>& x) {
+__device__ inline void bf_lstore(const LA& la, BfSmem<BN>& sm, int buf, BfStage<LA, BN>& x) {
   const int t = threadIdx.x;
+  la.prep(x.a);
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int row = (t >> 2) + 64 * q;
@@ -718,7 +704,6 @@ __device__ inline void gemm2_f16_body(const GemmDims& d, int M, int splitk, int 
                                       const f16_t* __restrict__ psi_v_t,
                                       const f16_t* __restrict__ psi_c_t16,
                                       const float* __restrict__ vpot,
-                                      const unsigned* __restrict__ vmax, int pexp,
                                       float* __restrict__ ypart) {
   const bf16_t* psi_c_t = reinterpret_cast<const bf16_t*>(psi_c_t16);  // raw 16-bit rows
   constexpr int WN = BfCfg<BN>::WN;
@@ -736,7 +721,7 @@ __device__ inline void gemm2_f16_body(const GemmDims& d, int M, int splitk, int 
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < WN; ++j) acc[i][j] = f16v{};
-  LoadPsiV16<NVP> la(psi_v_t, vpot, d.nrp, d.nvp, m0, threadIdx.x, vmax, pexp);
+  LoadPsiV16<NVP> la{psi_v_t, vpot, d.nrp, d.nvp};
   // Two register stages: the loads of step i + 2 are in flight while step i
   // computes and step i + 1 is scaled into the other LDS buffer.  The last
   // steps reload the final slab instead of branching.
@@ -780,17 +765,15 @@ template <int NVP>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 gemm2_f16_n128_kernel(GemmDims d, int M, int splitk, int kchunk,
                       const f16_t* __restrict__ psi_v_t, const f16_t* __restrict__ psi_c_t,
-                      const float* __restrict__ vpot, const unsigned* __restrict__ vmax,
-                      int pexp, float* __restrict__ ypart) {
-  gemm2_f16_body<128, NVP>(d, M, splitk, kchunk, psi_v_t, psi_c_t, vpot, vmax, pexp, ypart);
+                      const float* __restrict__ vpot, float* __restrict__ ypart) {
+  gemm2_f16_body<128, NVP>(d, M, splitk, kchunk, psi_v_t, psi_c_t, vpot, ypart);
 }
 template <int NVP>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 gemm2_f16_n256_kernel(GemmDims d, int M, int splitk, int kchunk,
                       const f16_t* __restrict__ psi_v_t, const f16_t* __restrict__ psi_c_t,
-                      const float* __restrict__ vpot, const unsigned* __restrict__ vmax,
-                      int pexp, float* __restrict__ ypart) {
-  gemm2_f16_body<256, NVP>(d, M, splitk, kchunk, psi_v_t, psi_c_t, vpot, vmax, pexp, ypart);
+                      const float* __restrict__ vpot, float* __restrict__ ypart) {
+  gemm2_f16_body<256, NVP>(d, M, splitk, kchunk, psi_v_t, psi_c_t, vpot, ypart);
 }
 
 }  // namespace
@@ -838,15 +821,14 @@ int gemm2_f16_blocks(const GemmDims& d, int nb, int bn) {
 }
 
 void gemm2_f16(const GemmDims& d, int nb, int bn, int splitk, const f16_t* psi_v_t,
-               const f16_t* psi_c_t, const float* vpot, const unsigned* vmax, int pexp,
-               float* ypart, hipStream_t st) {
+               const f16_t* psi_c_t, const float* vpot, float* ypart, hipStream_t st) {
   if (nb <= 0) return;
   const int M = nb * d.nvp;
   const int kchunk = (int)round_up(ceil_div(d.nrp, splitk), 2 * HK);
   const int blocks = gemm2_f16_blocks(d, nb, bn) * splitk;
 #define GWL_G2(BNV, NVPV)                                                                  \
   gemm2_f16_n##BNV##_kernel<NVPV><<<blocks, 256, 0, st>>>(d, M, splitk, kchunk, psi_v_t, \
-                                                           psi_c_t, vpot, vmax, pexp, ypart)
+                                                           psi_c_t, vpot, ypart)
   if (bn == 256) {
     if (d.nvp == 64) GWL_G2(256, 64);
     else if (d.nvp == 128) GWL_G2(256, 128);

@@ -155,6 +155,7 @@ gwl_status gwl_setup(const void* orbitals, int orb_dtype, int orb_on_device, int
     auto ctx = std::make_unique<gwl_ctx>();
     gwl_ctx& c = *ctx;
     GWL_HIP(hipGetDevice(&c.device));
+    poisson_prepare_device();
     if (o.stream) {
       c.stream = (hipStream_t)o.stream;
     } else {
@@ -403,6 +404,10 @@ gwl_status gwl_set_option(gwl_ctx* ctx, int key, double value) {
         ctx->use_graphs = (int)value;
         if (!ctx->use_graphs) ctx->drop_graph();
         break;
+      case GWL_KEY_SCHEDULER:
+        GWL_CHECK(value == 0 || value == 1, GWL_EINVAL, "scheduler must be 0 or 1");
+        ctx->sched_tables = (int)value;
+        break;
       default:
         throw Error{GWL_EINVAL, "unknown or read-only option key"};
     }
@@ -435,6 +440,7 @@ gwl_status gwl_query(gwl_ctx* ctx, int key, double* out) {
       case GWL_KEY_ISDF_NMU: *out = ctx->isdf_ready ? ctx->n_mu : 0; break;
       case GWL_KEY_PROFILE: *out = ctx->profile; break;
       case GWL_KEY_GRAPHS: *out = ctx->use_graphs; break;
+      case GWL_KEY_SCHEDULER: *out = ctx->sched_tables; break;
       case GWL_KEY_TUNED_BLOCK: *out = ctx->tuned[ctx->precision].B; break;
       case GWL_KEY_TUNED_SPLITK: *out = ctx->tuned[ctx->precision].S; break;
       case GWL_KEY_TUNED_TILE: *out = ctx->tuned[ctx->precision].tile; break;

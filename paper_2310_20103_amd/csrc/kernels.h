@@ -12,6 +12,8 @@ struct FftPlan {
   int ok;
 };
 FftPlan make_plan(int n);
+// Once per device at setup: lets the yz-plane pass use up to 80 KB of LDS.
+void poisson_prepare_device();
 
 template <typename T>
 struct PoissonGeom {
@@ -27,12 +29,15 @@ struct PoissonGeom {
 };
 
 // rin: [nparts][nf][ld_in] partial densities (summed); rout: [nf][ld_out].
-// scratch: [(nf+1)/2][N_r] complex.  vmax (optional, [nf]): receives
-// max_r |rout_f(r)| as float bits.
+// scratch: [(nf+1)/2][N_r] complex.  With vexp (the mixed product), every
+// output field f is multiplied by 2^vexp[f], the power of two that keeps
+// |phi| |V_f| 2^vexp[f] below 2^14 for orbital values up to 2^pexp (from a
+// bound of |V_f| the solve records in xmax, [(nf+1)/2] scratch).
 template <typename T>
 void poisson_launch(const PoissonGeom<T>& g, const T* rin, long ld_in, long part_stride,
                     int nparts, T* rout, long ld_out, int nf, cplx<T>* scratch,
-                    hipStream_t st, unsigned* vmax = nullptr);
+                    hipStream_t st, unsigned* xmax = nullptr, int* vexp = nullptr,
+                    int pexp = 0);
 
 // ---------------------------------------------------------------- GEMMs
 // Padded operand layouts (NRp, NVp, NCp multiples of the tile sizes):
@@ -68,13 +73,12 @@ void gemm2_f64(const GemmDims& d, int nb, int splitk, const double* psi_v_t,
                const double* psi_c_t, const double* vpot, double* ypart, hipStream_t st);
 
 // FP16 operands, FP32 accumulation, plain FMA tiles (checks the MFMA kernels;
-// the second GEMM's operand phi_v V_b s_b is rounded to FP16 as there).
+// the second GEMM's operand phi_v V_b is rounded to FP16 as there).
 int gemm1_f16s_vtiles(const GemmDims& d);
 void gemm1_f16s(const GemmDims& d, int nb, const f16_t* psi_c_rc, const float* psi_v_rv,
                 const f16_t* u, float* rho_part, hipStream_t st);
 void gemm2_f16s(const GemmDims& d, int nb, int splitk, const f16_t* psi_v_t,
-                const f16_t* psi_c_t, const float* vpot, const unsigned* vmax, int pexp,
-                float* ypart, hipStream_t st);
+                const f16_t* psi_c_t, const float* vpot, float* ypart, hipStream_t st);
 
 // FP64 on MFMA (v_mfma_f64_16x16x4).
 int gemm1_f64m_vtiles(const GemmDims& d);
@@ -90,16 +94,14 @@ int gemm1_f16_vtiles(const GemmDims& d);
 // psi_v_rv16: the same in FP16 (used when N_vp is 64 or 128)
 void gemm1_f16(const GemmDims& d, int nb, const f16_t* psi_c_rc, const float* psi_v_rv,
                const f16_t* psi_v_rv16, const f16_t* u, float* rho_part, hipStream_t st);
-// Second GEMM of the mixed path: A = f16(phi_v V_b s_b) formed while staging
-// (psi_v_t, psi_c_t: FP16 orbitals scaled by the orbital scale; vmax [nb]:
-// max_r |V_b| as float bits from the Poisson solve; pexp: frexp exponent of
-// the largest scaled orbital value; s_b = 2^f16_operand_exp(vmax_b, pexp)).
-// bn = block tile width (128 or 256).
+// Second GEMM of the mixed path: A = f16(phi_v V_b) formed while staging
+// (psi_v_t, psi_c_t: FP16 orbitals scaled by the orbital scale; vpot: the
+// potentials as the Poisson solve scaled them).  bn = block tile width (128
+// or 256).
 int gemm2_f16_blocks(const GemmDims& d, int nb, int bn);  // blocks per split of the K range
 int gemm2_f64m_blocks(const GemmDims& d, int nb);
 void gemm2_f16(const GemmDims& d, int nb, int bn, int splitk, const f16_t* psi_v_t,
-               const f16_t* psi_c_t, const float* vpot, const unsigned* vmax, int pexp,
-               float* ypart, hipStream_t st);
+               const f16_t* psi_c_t, const float* vpot, float* ypart, hipStream_t st);
 
 // ---------------------------------------------------------------- pair-space ops
 struct PairGeom {
@@ -118,10 +120,9 @@ struct PairGeom {
   // cast_u / combine only: GEMM operand row b belongs to pair-vector slot
   // rows[b] (device, nb entries); nullptr = row b is slot b
   const int* rows = nullptr;
-  // mixed second GEMM: row b of its sum also carries s_b =
-  // 2^f16_operand_exp(vmax[b], pexp), divided out next to yscale
-  const unsigned* vmax = nullptr;
-  int pexp = 0;
+  // mixed second GEMM: row b of its sum also carries the potential's scale
+  // 2^vexp[b] (set by the Poisson solve), divided out next to yscale
+  const int* vexp = nullptr;
 };
 
 // Elementwise orbital products rho_i = phi_{n_i} phi_{m_i} (FP64), [cnt][NRp].

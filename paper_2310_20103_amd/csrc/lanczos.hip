@@ -76,9 +76,8 @@ __global__ void combine_kernel(PairGeom g, int nb, int splitk, const Y* __restri
   const Y* yb = ypart + (long)b * g.nvp * g.ncp;
   const double* xb = x + (long)slot * g.nvc;
   const double inv = 1.0 / (hi - lo);
-  // the mixed second GEMM's row scale s_b is divided out with the operand scales
-  const double ysc =
-      g.vmax ? ldexp(g.yscale, -f16_operand_exp(__uint_as_float(g.vmax[b]), g.pexp)) : g.yscale;
+  // the potential's scale of the mixed product is divided out with the others
+  const double ysc = g.vexp ? ldexp(g.yscale, -g.vexp[b]) : g.yscale;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < g.nvc; i += (long)gridDim.x * blockDim.x) {
     const int v = (int)(i / g.nc), c = (int)(i - (long)v * g.nc);
     const long off = (long)v * g.ncp + c;

@@ -558,3 +558,51 @@ def test_autotuner_choice(small, ctx_small):
     assert ctx_small.query(G.KEY_TUNED_BLOCK) in (32, 64, 128, 256)
     assert 1 <= ctx_small.query(G.KEY_TUNED_SPLITK) <= 32
     assert ctx_small.query(G.KEY_TUNED_TILE) in (128, 256)
+
+
+# ------------------------------------------------------------------ schedulers
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("reorth", ["full", "local"])
+def test_table_scheduler_matches_host_scheduler(small, precision, reorth):
+    """The scheduler that uploads its refill schedule once and replays a graph
+    of the whole Lanczos step gives bitwise the coefficients of the
+    host-driven loop (same kernels in the same order): uneven lengths over
+    3 slots, so slots retire, are refilled mid-run and fall idle at the end;
+    also with graphs off and on the C route (quadrature); and it matches the
+    oracle."""
+    import paper_2310_20103_amd as G
+    _say("table vs host scheduler", precision, reorth)
+    m = int(small.sys.qp_states[0])
+    ns = [4, 9, 30, 17, 2, 22, 35, 11]
+    lens = [6, 40, 12, 25, 3, 64, 1, 19]
+    out = {}
+    with make_ctx(small.sys, precision=precision, interval=(small.lo, small.hi), block=3,
+                  reorth=reorth) as ctx:
+        assert ctx.query(G.KEY_SCHEDULER) == 1
+        for sched, graphs in ((1, 1), (0, 1), (1, 0)):
+            ctx.set_option(G.KEY_SCHEDULER, sched)
+            ctx.set_option(G.KEY_GRAPHS, graphs)
+            out[(sched, graphs)] = ctx.lanczos_pairs([m] * len(ns), ns, lens)
+            assert ctx.query(G.KEY_LAST_C_MATVECS) == sum(lens) * small.wl.poly_degree
+        if precision == "fp64":
+            ctx.set_quadrature(True)
+            q = {}
+            for sched in (1, 0):
+                ctx.set_option(G.KEY_SCHEDULER, sched)
+                ctx.set_option(G.KEY_GRAPHS, 1)
+                q[sched] = ctx.lanczos_pairs([m] * len(ns), ns, lens)
+            for x, y in zip(q[1], q[0]):
+                assert np.array_equal(x, y)
+    ref = out[(0, 1)]
+    for key in ((1, 1), (1, 0)):
+        for x, y in zip(out[key], ref):
+            assert np.array_equal(x, y), key
+    a, b, n2, ol = ref
+    for i, n in enumerate(ns):
+        ra, rb, rn2 = small.pr.lanczos_coeffs(m, lens[i], small.lo, small.hi,
+                                              small.wl.poly_degree, n_list=[n])[0]
+        assert ol[i] == lens[i]
+        if precision == "fp64" and reorth == "full":
+            assert relerr(a[i, :lens[i]], ra) <= 1e-9
+        else:
+            assert relerr(a[i, :min(6, lens[i])], ra[:6]) <= 1e-4
