@@ -193,6 +193,29 @@ gwl_status gwl_sigma_from_coeffs(gwl_ctx* ctx, const int* n_idx, int n_pairs,
                                  const double* omega_ev, int n_omega,
                                  double eta_ev, double* sigma_out);
 
+/* Allocation-free variant of gwl_sigma_from_coeffs, for callers that cannot
+ * allocate device memory (code under stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, layouts, units and
+ * results (the same kernels); the device buffers it needs (the staged
+ * coefficients, per-pair energies and signs, frequencies in hartree and the
+ * per-pair Sigma) are carved from one static 32 MiB array per device
+ * instead of the context's allocations, so it calls no hipMalloc, hipFree or
+ * other allocating routine.  Need, in bytes, each of its ten pieces rounded
+ * up to 256: 16 n_pairs (ld + n_omega + 2) + 8 (n_orb + n_omega); more is
+ * GWL_EINVAL with the figure in gwl_last_error.  Every call on a device
+ * shares that device's array and leaves its contents behind; each call
+ * writes every byte it reads first.  Calls that can overlap on one device
+ * (from several threads, whatever their contexts or streams) race; calls
+ * made one after another do not.  The polynomial continued fraction
+ * and the Tamm-Dancoff option are covered; the quadrature option returns
+ * GWL_EUNSUPPORTED.  The current device must be the context's (GWL_EINVAL
+ * otherwise).  Synchronous on the context stream. */
+gwl_status gwl_sigma_from_coeffs_noalloc(gwl_ctx* ctx, const int* n_idx, int n_pairs,
+                                         const double* alpha, const double* beta,
+                                         const double* p_norm2, const int* lens, int ld,
+                                         const double* omega_ev, int n_omega,
+                                         double eta_ev, double* sigma_out);
+
 /* Vector-Jacobian product of the self-energy (reverse-mode derivative).
  * For the scalar l = sum_{q,w} Re(conj(G_qw) Sigma_q(w)) with
  *   grad_sigma  host [n_qp][n_omega][2]: G (re, im), per eV of Sigma,

@@ -62,6 +62,7 @@ _SIGS = {
     "gwl_sigma_c_range": (_I, [_P, _P, _I, _I, _I, _P, _I, _D, _I, _P]),
     "gwl_lanczos_pairs": (_I, [_P, _P, _P, _P, _I, _P, _P, _P, _P, _I]),
     "gwl_sigma_from_coeffs": (_I, [_P, _P, _I, _P, _P, _P, _P, _I, _P, _I, _D, _P]),
+    "gwl_sigma_from_coeffs_noalloc": (_I, [_P, _P, _I, _P, _P, _P, _P, _I, _P, _I, _D, _P]),
     "gwl_sigma_c_vjp": (_I, [_P, _P, _I, _P, _I, _D, _I, _P, _P, _P, _P]),
     "gwl_sigma_c_range_vjp": (_I, [_P, _P, _I, _I, _I, _P, _I, _D, _I, _P, _P, _P, _P]),
     "gwl_poisson": (_I, [_P, _P, _P, _I, _I]),
@@ -348,6 +349,19 @@ class Context:
         _check(lib().gwl_sigma_from_coeffs(self._h, _ptr(n), len(n), _ptr(a), _ptr(b), _ptr(n2),
                                            _ptr(ln), a.shape[1], _ptr(om), len(om), float(eta_ev),
                                            _ptr(out)))
+        return out[..., 0] + 1j * out[..., 1]
+
+    def sigma_from_coeffs_noalloc(self, n_idx, alpha, beta, norm2, lens, omega_ev, eta_ev):
+        """As sigma_from_coeffs, through the entry point that allocates no
+        device memory (its buffers live in a fixed per-device array)."""
+        n = _i32(n_idx)
+        a, b, n2 = _f64(alpha), _f64(beta), _f64(norm2)
+        ln = _i32(lens)
+        om = _f64(omega_ev)
+        out = np.zeros((len(n), len(om), 2))
+        _check(lib().gwl_sigma_from_coeffs_noalloc(self._h, _ptr(n), len(n), _ptr(a), _ptr(b),
+                                                   _ptr(n2), _ptr(ln), a.shape[1], _ptr(om),
+                                                   len(om), float(eta_ev), _ptr(out)))
         return out[..., 0] + 1j * out[..., 1]
 
     # -- components (device tensors) ----------------------------------------

@@ -156,6 +156,7 @@ gwl_status gwl_setup(const void* orbitals, int orb_dtype, int orb_on_device, int
     gwl_ctx& c = *ctx;
     GWL_HIP(hipGetDevice(&c.device));
     poisson_prepare_device();
+    noalloc_bind_current_device();
     if (o.stream) {
       c.stream = (hipStream_t)o.stream;
     } else {

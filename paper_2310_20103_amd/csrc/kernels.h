@@ -275,4 +275,9 @@ void adj_dbar_zops(const PairGeom& g, int nb, const double* s, const double* ks,
                    const double* kt, double alpha, double kappa, double* dbar, double* us,
                    double* ut, hipStream_t st);
 
+// ---------------------------------------------------------------- allocation-free entry
+// Takes the device address of the static scratch array of the allocation-free
+// entry point for the current device (once per device).
+void noalloc_bind_current_device();
+
 }  // namespace gwl
