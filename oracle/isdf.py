@@ -171,3 +171,47 @@ def kmeans(w, shape, spacing, init_points, max_iter):
         if members.size:
             pts.append(int(members[np.argmin(best[members])]))
     return np.sort(np.array(pts, dtype=np.int64)), cent, n_assign
+
+
+# ---------------------------------------------------------------------------
+# Interpolation points by column-pivoted QR (the selection the ISDF
+# literature pairs with the interpolative decomposition).  The pair-density
+# matrix Z[(vc), r] = phi_v(r) phi_c(r) is too large to pivot directly, so it
+# is sketched: with caller-given random matrices Gv [N_v, p] and Gc [N_c, p]
+# (the random numbers are inputs, not drawn here),
+#     S[k, r] = (sum_v Gv[v, k] phi_v(r)) (sum_c Gc[c, k] phi_c(r)),
+# i.e. S = Gv^T Z-rows combined through the Khatri-Rao structure of Z; its
+# column space follows Z's.  The points are the first n_mu pivots of
+# column-pivoted Gram-Schmidt on S (Businger-Golub pivoting): at each step
+# the column (grid point) with the largest residual 2-norm is taken (ties to
+# the lower index), normalised, and projected out of every column.
+
+def qrcp_sketch(phi, n_occ, gv, gc):
+    """S [p, N_r] = (Gv^T phi_v) * (Gc^T phi_c), elementwise."""
+    pv, pc = phi[:n_occ], phi[n_occ:]
+    return (np.asarray(gv).T @ pv) * (np.asarray(gc).T @ pc)
+
+
+def qrcp_pivots(s, n_mu):
+    """First n_mu pivots (grid indices, in pivot order) of column-pivoted
+    Gram-Schmidt on s [p, N_r]; also the residual norms at each pivot."""
+    r = np.array(s, dtype=np.float64, copy=True)
+    taken = np.zeros(r.shape[1], dtype=bool)
+    piv, rdiag = [], []
+    for _ in range(n_mu):
+        nrm = np.einsum("kr,kr->r", r, r)
+        nrm[taken] = -1.0
+        j = int(np.argmax(nrm))           # first index of the maximum
+        q = r[:, j] / np.sqrt(nrm[j])
+        r -= np.outer(q, q @ r)
+        r[:, j] = 0.0
+        taken[j] = True
+        piv.append(j)
+        rdiag.append(float(np.sqrt(nrm[j])))
+    return np.array(piv), np.array(rdiag)
+
+
+def qrcp_points(phi, n_occ, n_mu, gv, gc):
+    """Interpolation points (increasing grid indices) by QRCP of the sketch."""
+    piv, _ = qrcp_pivots(qrcp_sketch(phi, n_occ, gv, gc), n_mu)
+    return np.sort(piv)

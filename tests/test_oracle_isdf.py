@@ -143,3 +143,51 @@ def test_kmeans_points_beat_random_points():
         pts, _ = I.kmeans_points(w, wl.grid, (wl.h,) * 3, init, 30)
         err = lambda p: np.linalg.norm(I.k_isdf(s.phi, wl.n_occ, wl.grid, wl.h, p) - k_ex)
         assert err(pts) < 0.9 * err(init)
+
+
+# ------------------------------------------------------------------ QRCP points
+def _gauss(shape, seed):
+    return np.random.default_rng(seed).standard_normal(shape)
+
+
+def test_qrcp_sketch_is_khatri_rao_projection():
+    """S[k, r] = sum_vc Gv[v, k] Gc[c, k] Z[(vc), r], by brute force."""
+    wl, s = sys_(n_occ=2, n_emp=3, grid=(6, 6, 6), box=5.0)
+    gv, gc = _gauss((2, 5), 1), _gauss((3, 5), 2)
+    z = casida.pair_densities(s.phi, wl.n_occ)          # [(vc), r]
+    w = np.array([[gv[v, k] * gc[c, k] for v in range(2) for c in range(3)] for k in range(5)])
+    assert np.max(np.abs(I.qrcp_sketch(s.phi, wl.n_occ, gv, gc) - w @ z)) <= 1e-13 * np.max(np.abs(z))
+
+
+def test_qrcp_pivots_match_lapack():
+    """Column-pivoted Gram-Schmidt picks the same pivots as LAPACK's pivoted
+    Householder QR (dgeqp3) on a generic matrix, with |R_jj| equal."""
+    import scipy.linalg as sl
+    a = _gauss((12, 60), 5) * np.linspace(0.2, 3.0, 60)[None, :]
+    piv, rd = I.qrcp_pivots(a, 12)
+    _, rr, p = sl.qr(a, pivoting=True, mode="economic")
+    assert np.array_equal(piv, p[:12])
+    assert np.max(np.abs(rd - np.abs(np.diag(rr)))) <= 1e-12 * rd[0]
+
+
+def test_qrcp_exact_at_full_rank():
+    """With as many pivots as pairs (and a sketch at least that wide), the
+    QRCP points carry the whole column space of Z: K_ISDF = K."""
+    wl, s = sys_()
+    nvc = wl.n_occ * wl.n_emp
+    pts = I.qrcp_points(s.phi, wl.n_occ, nvc, _gauss((wl.n_occ, nvc + 4), 7),
+                        _gauss((wl.n_emp, nvc + 4), 8))
+    assert len(set(pts.tolist())) == nvc
+    k_ex, _ = casida.hartree_matrix(s.phi, wl.n_occ, wl.grid, wl.h)
+    k_is = I.k_isdf(s.phi, wl.n_occ, wl.grid, wl.h, pts)
+    assert np.max(np.abs(k_is - k_ex)) <= 1e-9 * np.max(np.abs(k_ex))
+
+
+def test_qrcp_points_beat_random_points():
+    wl, s = sys_(n_occ=4, n_emp=16, grid=(12, 12, 12), box=7.0, seed=9)
+    k_ex, _ = casida.hartree_matrix(s.phi, wl.n_occ, wl.grid, wl.h)
+    err = lambda p: np.linalg.norm(I.k_isdf(s.phi, wl.n_occ, wl.grid, wl.h, p) - k_ex)
+    for n_mu in (24, 40):
+        pts = I.qrcp_points(s.phi, wl.n_occ, n_mu, _gauss((wl.n_occ, n_mu + 8), 1),
+                            _gauss((wl.n_emp, n_mu + 8), 2))
+        assert err(pts) < 0.9 * err(gi.random_grid_points(n_mu, wl.n_r, seed=3))
