@@ -207,6 +207,7 @@ struct gwl_ctx {
   DevBuf<unsigned char> rho;   // [nvt][cap][NRp] x 8 (fully written by the first GEMM)
   DevBuf<double> vpot64;       // [cap][NRp]
   DevBuf<float> vpot32;        // [cap][NRp]
+  DevBuf<f16_t> vpot16;        // [cap][NRp] mixed product: scaled FP16 potentials
   DevBuf<unsigned char> fftx;  // [(cap+1)/2][N_r] x 16
   DevBuf<unsigned char> ypart; // [S][cap][NVp][NCp] x 8
   DevBuf<double> basis;        // [cap][cap_L][nvc]
@@ -341,7 +342,8 @@ struct gwl_ctx {
     else
       blocks = gemm2_f16_blocks(d, nb, bf16_tile);
     int s = 1;
-    while (blocks * s < 1024 && s < 32 && (long)d.nrp / (s * 2) >= 2048) s *= 2;
+    // fill the chip (about 1024 blocks) while each split keeps >= 512 grid points
+    while (blocks * s < 1024 && s < 32 && (long)d.nrp / (s * 2) >= 512) s *= 2;
     return s;
   }
 
@@ -359,6 +361,7 @@ struct gwl_ctx {
       rho.ensure((size_t)nvt_max() * nb * gd.nrp * 8);
       vpot64.ensure((size_t)nb * gd.nrp);
       vpot32.ensure((size_t)alloc_rows_v(nb, gd.nvp) * gd.nrp);
+      vpot16.ensure((size_t)alloc_rows_v(nb, gd.nvp) * gd.nrp);
       xmax32.ensure((size_t)alloc_rows_v(nb, gd.nvp));
       vexp32.ensure((size_t)alloc_rows_v(nb, gd.nvp));
       fftx.ensure((size_t)((nb + 1) / 2) * nr * 16);
@@ -461,15 +464,15 @@ struct gwl_ctx {
       else
         poisson_launch<float>(pg32, rp, d.nrp, (long)nb * d.nrp, nvt, vp, d.nrp, nb,
                               reinterpret_cast<cplx<float>*>(fftx.p), st, xmax32.p,
-                              vexp32.p, pv16_exp);
+                              vexp32.p, pv16_exp, vpot16.p);
       prof_end(2, nb);
       const f16_t* pv = pt;
       const f16_t* pc = pt + (size_t)d.nvp * d.nrp;
       prof_begin();
       if (fp64_kernel)
-        gemm2_f16(d, nb, bf16_tile, S, pv, pc, vp, yp, st);
+        gemm2_f16(d, nb, bf16_tile, S, pv, pc, vpot16.p, yp, st);
       else
-        gemm2_f16s(d, nb, S, pv, pc, vp, yp, st);
+        gemm2_f16s(d, nb, S, pv, pc, vpot16.p, yp, st);
       prof_end(1, nb);
     }
   }

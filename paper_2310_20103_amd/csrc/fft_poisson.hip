@@ -165,6 +165,11 @@ __device__ inline void block_max_atomic(T m, unsigned* dst) {
   }
 }
 
+// Threads of the yz-plane pass: a plane and its copy take 66.5 KB of LDS at
+// 64 x 64 in FP32, so two blocks share a CU; 16 waves each keep enough loads
+// in flight.
+constexpr int kYzThreads = 1024;
+
 // Optional output scaling of the mixed product (FP16 operands downstream):
 // the x pass records xmax[p] = max(|Re X|, |Im X|) over its output for the
 // field pair p; the rest of the transform is an unnormalised inverse DFT over
@@ -176,7 +181,16 @@ struct VScale {
   unsigned* xmax;  // [npairs] float bits, or nullptr (no scaling)
   int* vexp;       // [nf]
   int pexp;
+  f16_t* out16;    // scaled output rounded to FP16 (instead of the real output)
 };
+
+// One value of an output field: FP16 (scaled) when the solve feeds the mixed
+// product, else in the working precision.
+template <typename T>
+__device__ inline void put_v(T* rout, f16_t* out16, long i, T v) {
+  if (out16) out16[i] = f32_to_f16((float)v);
+  else rout[i] = v;
+}
 
 // Transform of whole yz planes (fixed x, contiguous in memory): the z lines,
 // then the y lines, both in LDS, so the plane crosses HBM once each way.
@@ -185,7 +199,7 @@ struct VScale {
 // y lines then z lines): writes the real part to field 2p and the imaginary
 // part to field 2p+1 and leaves each field's max |V| in vmax.
 template <typename T, bool INVERSE>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kYzThreads)
 fft_pass_yz(cplx<T>* __restrict__ X, const T* __restrict__ rin, T* __restrict__ rout, int nf,
             long ld_real, long part_stride, int nparts, int ny, int nz, long nr, FftPlan py,
             FftPlan pz, const cplx<T>* __restrict__ twy, const cplx<T>* __restrict__ twz,
@@ -243,8 +257,8 @@ fft_pass_yz(cplx<T>* __restrict__ X, const T* __restrict__ rin, T* __restrict__ 
     if (!INVERSE) {
       Xp[base + e] = v;
     } else {
-      rout[(long)f0 * ld_real + base + e] = sc * v.x;
-      if (f1 < nf) rout[(long)f1 * ld_real + base + e] = -(sc * v.y);
+      put_v(rout, vs.out16, (long)f0 * ld_real + base + e, sc * v.x);
+      if (f1 < nf) put_v(rout, vs.out16, (long)f1 * ld_real + base + e, -(sc * v.y));
     }
   }
 }
@@ -308,8 +322,8 @@ fft_pass_z(cplx<T>* __restrict__ X, const T* __restrict__ rin, T* __restrict__ r
     if (!INVERSE) {
       Xp[base + e] = v;
     } else {
-      rout[(long)f0 * ld_real + base + e] = sc * v.x;
-      if (f1 < nf) rout[(long)f1 * ld_real + base + e] = -(sc * v.y);
+      put_v(rout, vs.out16, (long)f0 * ld_real + base + e, sc * v.x);
+      if (f1 < nf) put_v(rout, vs.out16, (long)f1 * ld_real + base + e, -(sc * v.y));
     }
   }
 }
@@ -411,8 +425,8 @@ FftPlan make_plan(int n) {
 template <typename T>
 void poisson_launch(const PoissonGeom<T>& g, const T* rin, long ld_in, long part_stride,
                     int nparts, T* rout, long ld_out, int nf, cplx<T>* scratch,
-                    hipStream_t st, unsigned* xmax, int* vexp, int pexp) {
-  const VScale vs{vexp ? xmax : nullptr, vexp, pexp};
+                    hipStream_t st, unsigned* xmax, int* vexp, int pexp, f16_t* rout16) {
+  const VScale vs{vexp ? xmax : nullptr, vexp, pexp, vexp ? rout16 : nullptr};
   unsigned* xm = vs.xmax;
   const int nyz = g.ny * g.nz;
   if (nf <= 0) return;
@@ -429,7 +443,7 @@ void poisson_launch(const PoissonGeom<T>& g, const T* rin, long ld_in, long part
   const size_t sm_yz = 2 * (size_t)g.ny * (g.nz + 1) * sizeof(cplx<T>);
   if (sm_yz <= kYzLdsMax) {
     dim3 gyz(g.nx, npairs);
-    fft_pass_yz<T, false><<<gyz, 256, sm_yz, st>>>(scratch, rin, nullptr, nf, ld_in, part_stride,
+    fft_pass_yz<T, false><<<gyz, kYzThreads, sm_yz, st>>>(scratch, rin, nullptr, nf, ld_in, part_stride,
                                                    nparts, g.ny, g.nz, nr, g.py, g.pz, g.twy,
                                                    g.twz, vs);
     dim3 grid(g.ny * nzb, npairs);
@@ -437,7 +451,7 @@ void poisson_launch(const PoissonGeom<T>& g, const T* rin, long ld_in, long part
     fft_pass_strided<T, 2><<<grid, 256, sm, st>>>(scratch, g.nx, (long)g.ny * g.nz, g.nz,
                                                   nzb, g.nz, nr, lpb, g.px, g.twx, g.g2x,
                                                   g.g2y, g.g2z, g.vscale, g.ny, xm);
-    fft_pass_yz<T, true><<<gyz, 256, sm_yz, st>>>(scratch, nullptr, rout, nf, ld_out, 0, 1,
+    fft_pass_yz<T, true><<<gyz, kYzThreads, sm_yz, st>>>(scratch, nullptr, rout, nf, ld_out, 0, 1,
                                                   g.ny, g.nz, nr, g.py, g.pz, g.twy, g.twz,
                                                   vs);
     GWL_HIP(hipGetLastError());
@@ -491,9 +505,9 @@ void poisson_launch(const PoissonGeom<T>& g, const T* rin, long ld_in, long part
 
 template void poisson_launch<float>(const PoissonGeom<float>&, const float*, long, long, int,
                                     float*, long, int, cplx<float>*, hipStream_t, unsigned*,
-                                    int*, int);
+                                    int*, int, f16_t*);
 template void poisson_launch<double>(const PoissonGeom<double>&, const double*, long, long,
                                      int, double*, long, int, cplx<double>*, hipStream_t,
-                                     unsigned*, int*, int);
+                                     unsigned*, int*, int, f16_t*);
 
 }  // namespace gwl

@@ -318,32 +318,28 @@ __device__ inline unsigned pack_f16(float a, float b) {
   return __builtin_bit_cast(unsigned, v);
 }
 
-__device__ inline u4 scale8(u4 pv, f4v v0, f4v v1) {
-  u4 out;
-  out[0] = pack_f16(lo_f16(pv[0]) * v0[0], hi_f16(pv[0]) * v0[1]);
-  out[1] = pack_f16(lo_f16(pv[1]) * v0[2], hi_f16(pv[1]) * v0[3]);
-  out[2] = pack_f16(lo_f16(pv[2]) * v1[0], hi_f16(pv[2]) * v1[1]);
-  out[3] = pack_f16(lo_f16(pv[3]) * v1[2], hi_f16(pv[3]) * v1[3]);
-  return out;
+// eight packed FP16 products phi_v V (v_pk_mul_f16, round to nearest even:
+// the exact product of two FP16 numbers rounded once, as in FP32 and back)
+__device__ inline u4 mul8(u4 pv, u4 v) {
+  return __builtin_bit_cast(u4, __builtin_bit_cast(h8, pv) * __builtin_bit_cast(h8, v));
 }
 
-// A[(b,v)][r] = f16(phi_v(r) V_b(r)), phi_v in FP16 and V_b as the Poisson
-// solve wrote it (both already scaled by powers of two into FP16's range).
-// NVP = padded N_v when it is 64 or 128 (a thread's four rows then share one
-// or two phi_v rows and use four or two potentials), 256 when it is a
-// multiple of 256 (a tile lies inside one pair vector: four phi_v rows, one
-// potential), 0 otherwise.
+// A[(b,v)][r] = f16(phi_v(r) V_b(r)), phi_v and V_b in FP16 (both already
+// scaled by powers of two into FP16's range).  NVP = padded N_v when it is 64
+// or 128 (a thread's four rows then share one or two phi_v rows and use four
+// or two potentials), 256 when it is a multiple of 256 (a tile lies inside
+// one pair vector: four phi_v rows, one potential), 0 otherwise.
 template <int NVP>
 struct LoadPsiV16 {
   const f16_t* psi_v_t;
-  const float* vpot;
+  const f16_t* vpot;
   long nrp;
   int nvp;
   static constexpr int NPV = NVP == 64 ? 1 : (NVP == 128 ? 2 : 4);
   static constexpr int NB = NVP == 128 ? 2 : (NVP == 256 ? 1 : 4);
   struct Raw {
     u4 pv[NPV];
-    f4v v[NB][2];
+    u4 v[NB];
   };
   __device__ void load(int m0, int t, int k0, Raw& r) const {
     const int k = k0 + (t & 3) * 8;
@@ -351,46 +347,36 @@ struct LoadPsiV16 {
     if constexpr (NVP == 64) {
       r.pv[0] = *reinterpret_cast<const u4*>(psi_v_t + (long)r0 * nrp + k);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const float* vp = vpot + (long)(m0 / 64 + q) * nrp + k;
-        r.v[q][0] = *reinterpret_cast<const f4v*>(vp);
-        r.v[q][1] = *reinterpret_cast<const f4v*>(vp + 4);
-      }
+      for (int q = 0; q < 4; ++q)
+        r.v[q] = *reinterpret_cast<const u4*>(vpot + (long)(m0 / 64 + q) * nrp + k);
     } else if constexpr (NVP == 128) {
       r.pv[0] = *reinterpret_cast<const u4*>(psi_v_t + (long)r0 * nrp + k);
       r.pv[1] = *reinterpret_cast<const u4*>(psi_v_t + (long)(r0 + 64) * nrp + k);
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const float* vp = vpot + (long)(m0 / 128 + h) * nrp + k;
-        r.v[h][0] = *reinterpret_cast<const f4v*>(vp);
-        r.v[h][1] = *reinterpret_cast<const f4v*>(vp + 4);
-      }
+      for (int h = 0; h < 2; ++h)
+        r.v[h] = *reinterpret_cast<const u4*>(vpot + (long)(m0 / 128 + h) * nrp + k);
     } else if constexpr (NVP == 256) {
       const int b = m0 / nvp, v0 = m0 - b * nvp + r0;
 #pragma unroll
       for (int q = 0; q < 4; ++q)
         r.pv[q] = *reinterpret_cast<const u4*>(psi_v_t + (long)(v0 + 64 * q) * nrp + k);
-      const float* vp = vpot + (long)b * nrp + k;
-      r.v[0][0] = *reinterpret_cast<const f4v*>(vp);
-      r.v[0][1] = *reinterpret_cast<const f4v*>(vp + 4);
+      r.v[0] = *reinterpret_cast<const u4*>(vpot + (long)b * nrp + k);
     } else {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int m = m0 + r0 + 64 * q;
         const int b = m / nvp, vv = m - b * nvp;
         r.pv[q] = *reinterpret_cast<const u4*>(psi_v_t + (long)vv * nrp + k);
-        const float* vp = vpot + (long)b * nrp + k;
-        r.v[q][0] = *reinterpret_cast<const f4v*>(vp);
-        r.v[q][1] = *reinterpret_cast<const f4v*>(vp + 4);
+        r.v[q] = *reinterpret_cast<const u4*>(vpot + (long)b * nrp + k);
       }
     }
   }
   __device__ void prep(Raw&) const {}
   __device__ u4 finish(const Raw& r, int q) const {
-    if constexpr (NVP == 64) return scale8(r.pv[0], r.v[q][0], r.v[q][1]);
-    else if constexpr (NVP == 128) return scale8(r.pv[q & 1], r.v[q >> 1][0], r.v[q >> 1][1]);
-    else if constexpr (NVP == 256) return scale8(r.pv[q], r.v[0][0], r.v[0][1]);
-    else return scale8(r.pv[q], r.v[q][0], r.v[q][1]);
+    if constexpr (NVP == 64) return mul8(r.pv[0], r.v[q]);
+    else if constexpr (NVP == 128) return mul8(r.pv[q & 1], r.v[q >> 1]);
+    else if constexpr (NVP == 256) return mul8(r.pv[q], r.v[0]);
+    else return mul8(r.pv[q], r.v[q]);
   }
 };
 
@@ -675,23 +661,23 @@ gemm1_f16_n128_kernel(GemmDims d, int M, int nb, const f16_t* __restrict__ psi_c
   gemm1_f16_body<128, SEG, NVW>(d, M, nb, psi_c_rc, psi_v_rv, psi_v_rv16, u, rho_part);
 }
 
-// Instruction order of one second-GEMM K step at the 256 x 256 tile (per
-// wave 32 MFMAs, 16 LDS fragment reads, 10 global loads two steps ahead,
-// about 70 VALU operations scaling the A operand, 8 LDS stores), imposed on
-// the compiler's scheduler: four fragment reads, then per MFMA one fragment
-// read (first twelve), two VALU operations, a global load every third MFMA
-// and the stores of the next step behind MFMAs 14 to 21.  With one wave per
-// SIMD nothing else hides the latencies; measured 13 % faster than the
-// compiler's own order.
+// Instruction order of one second-GEMM K step (256 x 256 tile, per wave 32
+// MFMAs, 16 LDS fragment reads, 8 global loads of the step after next, 16
+// packed FP16 products phi_v V and 8 LDS stores of the next step), imposed
+// on the compiler's scheduler: the fragment reads and every global load up
+// front, then the products once the loads of the next step have landed
+// (the ones just issued stay in flight), the stores behind them.
 template <int G>
 __device__ inline void g2_sched() {
   if constexpr (G < 32) {
-    if constexpr (G == 0) __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);  // LDS reads
+    if constexpr (G == 0) {
+      __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);  // LDS reads
+      __builtin_amdgcn_sched_group_barrier(0x020, 8, 0);  // global loads
+    }
     __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                       // MFMA
-    if constexpr (G < 12) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-    __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);                       // VALU
-    if constexpr (G % 3 == 1) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // global loads
-    if constexpr (G >= 14 && G < 22) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);  // LDS writes
+    if constexpr (G < 12) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // LDS reads
+    if constexpr (G >= 4 && G < 20) __builtin_amdgcn_sched_group_barrier(0x002, 1, 0);  // VALU
+    if constexpr (G >= 20 && G < 28) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);  // LDS writes
     g2_sched<G + 1>();
   }
 }
@@ -703,7 +689,7 @@ template <int BN, int NVP>
 __device__ inline void gemm2_f16_body(const GemmDims& d, int M, int splitk, int kchunk,
                                       const f16_t* __restrict__ psi_v_t,
                                       const f16_t* __restrict__ psi_c_t16,
-                                      const float* __restrict__ vpot,
+                                      const f16_t* __restrict__ vpot,
                                       float* __restrict__ ypart) {
   const bf16_t* psi_c_t = reinterpret_cast<const bf16_t*>(psi_c_t16);  // raw 16-bit rows
   constexpr int WN = BfCfg<BN>::WN;
@@ -765,14 +751,14 @@ template <int NVP>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 gemm2_f16_n128_kernel(GemmDims d, int M, int splitk, int kchunk,
                       const f16_t* __restrict__ psi_v_t, const f16_t* __restrict__ psi_c_t,
-                      const float* __restrict__ vpot, float* __restrict__ ypart) {
+                      const f16_t* __restrict__ vpot, float* __restrict__ ypart) {
   gemm2_f16_body<128, NVP>(d, M, splitk, kchunk, psi_v_t, psi_c_t, vpot, ypart);
 }
 template <int NVP>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 gemm2_f16_n256_kernel(GemmDims d, int M, int splitk, int kchunk,
                       const f16_t* __restrict__ psi_v_t, const f16_t* __restrict__ psi_c_t,
-                      const float* __restrict__ vpot, float* __restrict__ ypart) {
+                      const f16_t* __restrict__ vpot, float* __restrict__ ypart) {
   gemm2_f16_body<256, NVP>(d, M, splitk, kchunk, psi_v_t, psi_c_t, vpot, ypart);
 }
 
@@ -821,7 +807,7 @@ int gemm2_f16_blocks(const GemmDims& d, int nb, int bn) {
 }
 
 void gemm2_f16(const GemmDims& d, int nb, int bn, int splitk, const f16_t* psi_v_t,
-               const f16_t* psi_c_t, const float* vpot, float* ypart, hipStream_t st) {
+               const f16_t* psi_c_t, const f16_t* vpot, float* ypart, hipStream_t st) {
   if (nb <= 0) return;
   const int M = nb * d.nvp;
   const int kchunk = (int)round_up(ceil_div(d.nrp, splitk), 2 * HK);

@@ -74,10 +74,10 @@ gemm1_simple_kernel(GemmDims d, const TO* __restrict__ psi_c_rc,
   }
 }
 
-template <typename A, typename TO>
+template <typename A, typename TO, typename TV>
 __global__ void __launch_bounds__(256)
 gemm2_simple_kernel(GemmDims d, const TO* __restrict__ psi_v_t,
-                 const TO* __restrict__ psi_c_t, const A* __restrict__ vpot,
+                 const TO* __restrict__ psi_c_t, const TV* __restrict__ vpot,
                  A* __restrict__ ypart, int nb, int splitk, int kchunk, int round16) {
   __shared__ A As[TK][LDT];
   __shared__ A Bs[TK][LDT];
@@ -87,12 +87,12 @@ gemm2_simple_kernel(GemmDims d, const TO* __restrict__ psi_v_t,
   const int b = blockIdx.z / splitk, s = blockIdx.z - b * splitk;
   const int rbeg = s * kchunk;
   const int rend = min(d.nrp, rbeg + kchunk);
-  const A* vb = vpot + (long)b * d.nrp;
+  const TV* vb = vpot + (long)b * d.nrp;
   A acc[4][4] = {};
   for (int r = rbeg; r < rend; r += TK) {
     for (int e = tid; e < TK * TM; e += 256) {
       const int kk = e & (TK - 1), i = e >> 4;
-      A av = (A)ldx(psi_v_t, (long)(v0 + i) * d.nrp + r + kk) * vb[r + kk];
+      A av = (A)ldx(psi_v_t, (long)(v0 + i) * d.nrp + r + kk) * (A)ldx(vb, r + kk);
       // mixed path: the operand phi_v V_b is rounded to FP16 as in the MFMA kernel
       if (round16) av = (A)(float)(_Float16)(float)av;
       As[kk][i] = av;
@@ -147,11 +147,11 @@ void gemm1_f16s(const GemmDims& d, int nb, const f16_t* psi_c_rc, const float* p
 }
 
 void gemm2_f16s(const GemmDims& d, int nb, int splitk, const f16_t* psi_v_t,
-                const f16_t* psi_c_t, const float* vpot, float* ypart, hipStream_t st) {
+                const f16_t* psi_c_t, const f16_t* vpot, float* ypart, hipStream_t st) {
   if (nb <= 0) return;
   const int kchunk = (int)round_up(ceil_div(d.nrp, splitk), TK);
   dim3 grid(d.ncp / TN, d.nvp / TM, nb * splitk);
-  gemm2_simple_kernel<float, f16_t><<<grid, 256, 0, st>>>(d, psi_v_t, psi_c_t, vpot, ypart,
+  gemm2_simple_kernel<float, f16_t, f16_t><<<grid, 256, 0, st>>>(d, psi_v_t, psi_c_t, vpot, ypart,
                                                           nb, splitk, kchunk, 1);
   GWL_HIP(hipGetLastError());
 }
@@ -161,7 +161,7 @@ void gemm2_f64(const GemmDims& d, int nb, int splitk, const double* psi_v_t,
   if (nb <= 0) return;
   const int kchunk = (int)round_up(ceil_div(d.nrp, splitk), TK);
   dim3 grid(d.ncp / TN, d.nvp / TM, nb * splitk);
-  gemm2_simple_kernel<double, double><<<grid, 256, 0, st>>>(d, psi_v_t, psi_c_t, vpot, ypart,
+  gemm2_simple_kernel<double, double, double><<<grid, 256, 0, st>>>(d, psi_v_t, psi_c_t, vpot, ypart,
                                                              nb, splitk, kchunk, 0);
   GWL_HIP(hipGetLastError());
 }

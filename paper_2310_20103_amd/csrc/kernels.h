@@ -32,12 +32,13 @@ struct PoissonGeom {
 // scratch: [(nf+1)/2][N_r] complex.  With vexp (the mixed product), every
 // output field f is multiplied by 2^vexp[f], the power of two that keeps
 // |phi| |V_f| 2^vexp[f] below 2^14 for orbital values up to 2^pexp (from a
-// bound of |V_f| the solve records in xmax, [(nf+1)/2] scratch).
+// bound of |V_f| the solve records in xmax, [(nf+1)/2] scratch), and written
+// rounded to FP16 into rout16 (same layout as rout) instead of rout.
 template <typename T>
 void poisson_launch(const PoissonGeom<T>& g, const T* rin, long ld_in, long part_stride,
                     int nparts, T* rout, long ld_out, int nf, cplx<T>* scratch,
                     hipStream_t st, unsigned* xmax = nullptr, int* vexp = nullptr,
-                    int pexp = 0);
+                    int pexp = 0, f16_t* rout16 = nullptr);
 
 // ---------------------------------------------------------------- GEMMs
 // Padded operand layouts (NRp, NVp, NCp multiples of the tile sizes):
@@ -78,7 +79,7 @@ int gemm1_f16s_vtiles(const GemmDims& d);
 void gemm1_f16s(const GemmDims& d, int nb, const f16_t* psi_c_rc, const float* psi_v_rv,
                 const f16_t* u, float* rho_part, hipStream_t st);
 void gemm2_f16s(const GemmDims& d, int nb, int splitk, const f16_t* psi_v_t,
-                const f16_t* psi_c_t, const float* vpot, float* ypart, hipStream_t st);
+                const f16_t* psi_c_t, const f16_t* vpot, float* ypart, hipStream_t st);
 
 // FP64 on MFMA (v_mfma_f64_16x16x4).
 int gemm1_f64m_vtiles(const GemmDims& d);
@@ -94,14 +95,14 @@ int gemm1_f16_vtiles(const GemmDims& d);
 // psi_v_rv16: the same in FP16 (used when N_vp is 64 or 128)
 void gemm1_f16(const GemmDims& d, int nb, const f16_t* psi_c_rc, const float* psi_v_rv,
                const f16_t* psi_v_rv16, const f16_t* u, float* rho_part, hipStream_t st);
-// Second GEMM of the mixed path: A = f16(phi_v V_b) formed while staging
-// (psi_v_t, psi_c_t: FP16 orbitals scaled by the orbital scale; vpot: the
-// potentials as the Poisson solve scaled them).  bn = block tile width (128
-// or 256).
+// Second GEMM of the mixed path: A = phi_v V_b formed while staging by
+// packed FP16 products (psi_v_t, psi_c_t: FP16 orbitals scaled by the orbital
+// scale; vpot: the FP16 potentials as the Poisson solve scaled them).
+// bn = block tile width (128 or 256).
 int gemm2_f16_blocks(const GemmDims& d, int nb, int bn);  // blocks per split of the K range
 int gemm2_f64m_blocks(const GemmDims& d, int nb);
 void gemm2_f16(const GemmDims& d, int nb, int bn, int splitk, const f16_t* psi_v_t,
-               const f16_t* psi_c_t, const float* vpot, float* ypart, hipStream_t st);
+               const f16_t* psi_c_t, const f16_t* vpot, float* ypart, hipStream_t st);
 
 // ---------------------------------------------------------------- pair-space ops
 struct PairGeom {
