@@ -202,7 +202,8 @@ def qrcp_pivots(s, n_mu):
         nrm = np.einsum("kr,kr->r", r, r)
         nrm[taken] = -1.0
         j = int(np.argmax(nrm))           # first index of the maximum
-        q = r[:, j] / np.sqrt(nrm[j])
+        # a zero residual (sketch rank exhausted) is taken without projecting
+        q = r[:, j] / np.sqrt(nrm[j]) if nrm[j] > 0.0 else np.zeros(r.shape[0])
         r -= np.outer(q, q @ r)
         r[:, j] = 0.0
         taken[j] = True
