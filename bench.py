@@ -379,6 +379,12 @@ def run_isdf(args):
         n_mu = len(pts)
         torch.cuda.synchronize()
         log(f"isdf kmeans {time.perf_counter() - t:.1f}s, {km_iters} passes, {n_mu} points")
+    elif args.isdf_points == "qrcp":
+        rng = np.random.default_rng([wl.seed, 5])
+        pts = ctx.isdf_qrcp(rng.standard_normal((wl.n_occ, n_mu + 16)),
+                            rng.standard_normal((wl.n_emp, n_mu + 16)), n_mu)
+        torch.cuda.synchronize()
+        log(f"isdf qrcp {time.perf_counter() - t:.1f}s, {n_mu} points")
     ctx.isdf_setup(pts)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t
@@ -406,7 +412,8 @@ def run_isdf(args):
                    "n_emp": wl.n_emp, "n_mu": n_mu,
                    "points": ("weighted K-means from seeded random grid points, "
                               f"{km_iters} assignment passes") if km_iters else
-                   "seeded random grid points",
+                   ("column-pivoted QR of a sketch (p = N_mu + 16)"
+                    if args.isdf_points == "qrcp" else "seeded random grid points"),
                    "n_lanczos": wl.n_lanczos, "n_omega": wl.n_omega, "block": B,
                    "steps": args.steps},
         "ms_per_step": round(dt / max(args.steps, 1) * 1e3, 1),
@@ -417,6 +424,65 @@ def run_isdf(args):
                                "max_abs_sigma_ev": float(np.max(np.abs(s_grid))),
                                "sample": f"8 start vectors, L={acc_L}, FP64, all omega"}}),
           flush=True)
+
+
+def run_isdf_sweep(args):
+    """Sigma error of the ISDF product against the grid product as the point
+    count N_mu = r N_orb grows, for three point selections (seeded random
+    points, weighted K-means from them, column-pivoted QR of a sketch), on
+    the smooth-orbital variant of grid48_v64c256 (FP64): 8 start vectors of
+    one QP state at L = 40, every frequency; selection + setup time."""
+    import torch
+    import gw_inputs as gi
+    import paper_2310_20103_amd as G
+    base = args.workload if args.workload != "grid64_v128c512" else "grid48_v64c256"
+    wl = gi.workload(base, name=base + "_smooth", smooth_sigma=1.0)
+    phi = gi.make_orbitals(wl)
+    eps = gi.make_energies(wl)
+    qp = gi.frontier_states(eps, wl.n_occ, wl.n_qp_occ, wl.n_qp_emp)
+    omega = gi.omega_grid(wl)
+    box = tuple(k * wl.h for k in wl.grid)
+    ns = list(np.linspace(0, wl.n_orb - 1, 8).astype(int))
+    m0 = int(qp[0])
+    acc_L = 40
+    ctx = G.Context(phi, eps, wl.n_occ, wl.grid, box, precision="fp64",
+                    poly_degree=wl.poly_degree, reorth="full", block=64)
+    a, b, n2, ol = ctx.lanczos_pairs([m0] * len(ns), ns, [acc_L] * len(ns))
+    s_grid = ctx.sigma_from_coeffs(ns, a, b, n2, ol, omega, wl.eta)
+    smax = float(np.max(np.abs(s_grid)))
+    rows = []
+    for r in (2, 4, 8, 16):
+        n_mu = min(wl.n_r, r * wl.n_orb)
+        for how in ("random", "kmeans", "qrcp"):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            pts = gi.random_grid_points(n_mu, wl.n_r, seed=wl.seed)
+            if how == "kmeans":
+                pts, _ = ctx.isdf_kmeans(pts, 50)
+            elif how == "qrcp":
+                rng = np.random.default_rng([wl.seed, 5])
+                pts = ctx.isdf_qrcp(rng.standard_normal((wl.n_occ, n_mu + 16)),
+                                    rng.standard_normal((wl.n_emp, n_mu + 16)), n_mu)
+            ctx.isdf_setup(pts)
+            torch.cuda.synchronize()
+            t_sel = time.perf_counter() - t
+            ctx.set_option(G.KEY_ISDF, 1)
+            a, b, n2, ol = ctx.lanczos_pairs([m0] * len(ns), ns, [acc_L] * len(ns))
+            s_is = ctx.sigma_from_coeffs(ns, a, b, n2, ol, omega, wl.eta)
+            ctx.set_option(G.KEY_ISDF, 0)
+            err = float(np.max(np.abs(s_is - s_grid)))
+            rows.append({"r": r, "n_mu": int(len(pts)), "points": how,
+                         "max_abs_err_ev": err, "rel_err": err / smax,
+                         "select_and_setup_s": round(t_sel, 2)})
+            log(f"isdf sweep r={r} {how}: {err:.3e} eV ({t_sel:.1f}s)")
+    ctx.close()
+    print(json.dumps({
+        "metric": "Sigma_c error of the ISDF product against the grid product, FP64",
+        "unit": "eV", "n_gpus": 1, "data": "synthetic",
+        "config": {"workload": wl.name, "grid": list(wl.grid), "n_occ": wl.n_occ,
+                   "n_emp": wl.n_emp, "sample": f"8 start vectors of m={m0}, L={acc_L}, "
+                   f"{wl.n_omega} omega", "max_abs_sigma_ev": smax},
+        "rows": rows}), flush=True)
 
 
 def run_large(args):
@@ -579,7 +645,8 @@ def run_libref(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--mode", choices=("headline", "uneven", "sched", "adjoint", "isdf", "libref",
+    ap.add_argument("--mode", choices=("headline", "uneven", "sched", "adjoint", "isdf",
+                                       "isdf_sweep", "libref",
                                        "large"),
                     default="headline")
     ap.add_argument("--pairs", type=int, default=256, help="uneven mode: pairs measured")
@@ -598,11 +665,12 @@ def main():
                     help="uneven mode: comma-separated block sizes (default: 32,64,128,256 "
                          "with graphs and 128 without)")
     ap.add_argument("--isdf-ratio", type=int, default=4, help="isdf mode: N_mu / N_orb")
-    ap.add_argument("--isdf-points", choices=("kmeans", "random"), default="kmeans",
+    ap.add_argument("--isdf-points", choices=("kmeans", "random", "qrcp"), default="kmeans",
                     help="isdf mode: interpolation points (K-means or the random start)")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=0)
-    ap.add_argument("--block", type=int, default=128)
+    ap.add_argument("--block", type=int, default=0,
+                    help="vectors per batch (default 64 in adjoint mode, else 128)")
     ap.add_argument("--workload", default="grid64_v128c512")
     ap.add_argument("--fp64-window", type=int, default=2, help="Lanczos steps of the FP64 window")
     ap.add_argument("--cpu-steps", type=int, default=4,
@@ -615,13 +683,15 @@ def main():
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if not args.block:
+        args.block = 64 if args.mode == "adjoint" else 128
     if args.mode == "sched":
         return run_sched(args)
+    if args.mode == "isdf_sweep":
+        return run_isdf_sweep(args)
     if args.mode == "uneven":
         return run_uneven(args)
     if args.mode == "adjoint":
-        if args.block == 128:
-            args.block = 64
         return run_adjoint(args)
     if args.mode == "isdf":
         return run_isdf(args)

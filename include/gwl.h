@@ -310,6 +310,24 @@ gwl_status gwl_isdf_setup(gwl_ctx* ctx, const int* points, int n_mu);
 gwl_status gwl_isdf_kmeans(gwl_ctx* ctx, const int* init_points, int n_init, int max_iter,
                            int* points_out, int* n_points, int* n_assign);
 
+/* Interpolation points for gwl_isdf_setup by column-pivoted QR (the
+ * selection the interpolative decomposition uses).  The pair densities
+ * Z[(vc), r] = phi_v(r) phi_c(r) of the context's orbitals are sketched with
+ * the caller's random factors (gv host [N_v][p], gc host [N_c][p], row-major;
+ * the library draws no random numbers):
+ *   S[r][k] = (sum_v gv[v][k] phi_v(r)) (sum_c gc[c][k] phi_c(r)),
+ * and n_mu steps of column-pivoted Gram-Schmidt over the grid points take,
+ * each time, the point whose residual column of S has the largest norm
+ * (ties to the lower index), then project its normalised column out of all
+ * others (a zero residual is taken without projecting).  points_out: host
+ * [n_mu], the pivots in increasing order (ready for gwl_isdf_setup).  FP64,
+ * on the device, reproducible bit for bit; device scratch N_r p + 2 N_r
+ * doubles, allocated and freed by the call.  GWL_EINVAL unless
+ * 1 <= n_mu <= p and n_mu <= N_r; GWL_EUNSUPPORTED for p > 8192 or a sketch
+ * over 64 GB. */
+gwl_status gwl_isdf_qrcp(gwl_ctx* ctx, const double* gv, const double* gc, int p, int n_mu,
+                         int* points_out);
+
 /* Exchange part of the self-energy, Sigma^ex_mm = -sum_v (vm|vm) (Eq. 6; the
  * frequency-independent term of Eq. 5), in eV, for n_qp states: pair
  * densities phi_v phi_m on the grid, the same FFT Poisson solve and kernel as

@@ -73,6 +73,7 @@ _SIGS = {
     "gwl_isdf_setup": (_I, [_P, _P, _I]),
     "gwl_sigma_c_offdiag": (_I, [_P, _I, _I, _P, _I, _D, _I, _P]),
     "gwl_isdf_kmeans": (_I, [_P, _P, _I, _I, _P, _P, _P]),
+    "gwl_isdf_qrcp": (_I, [_P, _P, _P, _I, _I, _P]),
     "gwl_qp_solve": (_I, [_P, _I, _P, _D, _D, _D, _P, _P]),
     "gwl_set_option": (_I, [_P, _I, _D]),
     "gwl_query": (_I, [_P, _I, ct.POINTER(_D)]),
@@ -245,6 +246,17 @@ class Context:
         the ISDF product on."""
         p = _i32(points)
         _check(lib().gwl_isdf_setup(self._h, _ptr(p), len(p)))
+
+    def isdf_qrcp(self, gv, gc, n_mu: int):
+        """ISDF points by column-pivoted QR of the pair densities sketched with
+        the random factors gv [N_v, p], gc [N_c, p]; increasing grid indices."""
+        a, b = _f64(gv), _f64(gc)
+        if a.shape[0] != self.n_occ or b.shape[0] != self.n_emp or a.shape[1] != b.shape[1]:
+            raise ValueError("gv must be [n_occ, p] and gc [n_emp, p]")
+        out = np.zeros(int(n_mu), dtype=np.int32)
+        _check(lib().gwl_isdf_qrcp(self._h, _ptr(a), _ptr(b), int(a.shape[1]), int(n_mu),
+                                   _ptr(out)))
+        return out
 
     def isdf_kmeans(self, init_points, max_iter=50):
         """Weighted K-means interpolation points from the initial centroids

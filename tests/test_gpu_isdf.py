@@ -209,3 +209,36 @@ def test_kmeans_points_fit_better(smooth):
         ctx.isdf_setup(pts)
         err_km = relerr(ctx.apply_c(torch.tensor(x, device="cuda")).cpu().numpy(), ref)
     assert err_km < 0.9 * err_rand
+
+
+# ------------------------------------------------------------------ QRCP points
+@pytest.mark.parametrize("shape", [((12, 12, 12), 7.0, 4, 16, (24, 40)),
+                                   ((16, 12, 8), 6.0, 3, 11, (20, 33))])
+def test_qrcp_points_match_oracle(shape):
+    """gwl_isdf_qrcp against the oracle's pivoted Gram-Schmidt on the same
+    sketch (random factors passed to both): the same point set; with the
+    points the ISDF C x fits better than with random ones."""
+    import paper_2310_20103_amd as G
+    grid, box, n_occ, n_emp, n_mus = shape
+    wl = gi.workload("grid24_v8c32", name="qrcp", seed=9, grid=grid, box=box, n_occ=n_occ,
+                     n_emp=n_emp, smooth_sigma=1.0)
+    s = gi.make_system(wl)
+    k_ex, _ = oracle.casida.hartree_matrix(s.phi, wl.n_occ, wl.grid, wl.h)
+    with G.Context(s.phi, s.energies_ev, wl.n_occ, wl.grid,
+                   tuple(n * wl.h for n in wl.grid)) as c:
+        for n_mu in n_mus:
+            rng = np.random.default_rng(n_mu)
+            gv = rng.standard_normal((n_occ, n_mu + 8))
+            gc = rng.standard_normal((n_emp, n_mu + 8))
+            _say(f"qrcp grid {grid}, {n_occ}+{n_emp}, n_mu {n_mu}")
+            got = c.isdf_qrcp(gv, gc, n_mu)
+            ref = I.qrcp_points(s.phi, wl.n_occ, n_mu, gv, gc)
+            assert np.array_equal(got, ref)
+            err = lambda p: np.linalg.norm(I.k_isdf(s.phi, wl.n_occ, wl.grid, wl.h, p) - k_ex)
+            assert err(got) < 0.9 * err(gi.random_grid_points(n_mu, wl.n_r, seed=3))
+        # the points feed the ISDF product directly
+        c.isdf_setup(got)
+        c.set_option(G.KEY_ISDF, 1)
+        assert c.query(G.KEY_ISDF_NMU) == n_mus[-1]
+        with pytest.raises(G.GwlError):
+            c.isdf_qrcp(gv, gc, gv.shape[1] + 1)   # more points than sketch columns
