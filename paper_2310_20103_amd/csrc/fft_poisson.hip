@@ -8,7 +8,9 @@
 // ping-pong copy fit in LDS, the 3-D transform is three passes, each one
 // HBM round trip:
 //   yz forward (+ pack, + sum of GEMM partials) ->
-//   x forward, multiply by v(G)/N, x inverse -> yz inverse (+ unpack);
+//   x forward, multiply by v(G)/N, x inverse -> yz inverse (+ unpack),
+// with the spectrum in between stored y-major (X[ky][x][kz]) so that the x
+// pass reads and writes contiguous (x, kz) slabs;
 // otherwise five passes of batched 1-D transforms:
 //   z forward (+ pack) -> y forward -> x (as above) -> y inverse -> z inverse.
 // The 1-D transforms are mixed-radix (2, 3, 4, 8) Stockham autosort passes
@@ -147,6 +149,33 @@ __device__ cplx<T>* fft_lines(cplx<T>* buf0, cplx<T>* buf1, int nl, int n, int l
   return in;
 }
 
+// Moves cnt elements, e = threadIdx.x + k NT, from ld(e) to put(e, v), PER
+// per thread at a time: every load of a batch is issued before the first of
+// them is consumed, so a thread keeps PER loads in flight instead of one.
+template <int NT, int PER, typename V, typename Load, typename Put>
+__device__ inline void batched_copy(int cnt, Load ld, Put put) {
+  for (int e0 = threadIdx.x; e0 < cnt; e0 += PER * NT) {
+    V v[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = e0 + i * NT;
+      if (e < cnt) v[i] = ld(e);
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = e0 + i * NT;
+      if (e < cnt) put(e, v[i]);
+    }
+  }
+}
+
+// Copies a twiddle table (n entries) into LDS; the first __syncthreads of the
+// caller publishes it.
+template <typename T>
+__device__ inline void stage_twiddles(cplx<T>* dst, const cplx<T>* __restrict__ src, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+}
+
 // Largest |value| over the block, one atomic maximum (float bits:
 // non-negative floats order like their bit patterns, so the result does not
 // depend on the order of the atomics).
@@ -154,7 +183,7 @@ template <typename T>
 __device__ inline void block_max_atomic(T m, unsigned* dst) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
-  __shared__ float wm[4];
+  __shared__ float wm[16];  // up to 1024 threads
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (lane == 0) wm[wid] = (float)m;
   __syncthreads();
@@ -195,51 +224,71 @@ __device__ inline void put_v(T* rout, f16_t* out16, long i, T v) {
 // Transform of whole yz planes (fixed x, contiguous in memory): the z lines,
 // then the y lines, both in LDS, so the plane crosses HBM once each way.
 // Forward: builds the complex field from the real fields 2p and 2p+1 (summing
-// nparts GEMM partial densities) and clears vmax.  Inverse (conj(FFT(conj)),
+// nparts GEMM partial densities) and clears xmax.  Inverse (conj(FFT(conj)),
 // y lines then z lines): writes the real part to field 2p and the imaginary
-// part to field 2p+1 and leaves each field's max |V| in vmax.
+// part to field 2p+1.  The spectrum between the passes is stored y-major,
+// X[p][ky][x][kz], so that the x pass reads whole contiguous (x, kz) slabs;
+// a plane's 64 rows of kz go out as 512-byte runs.  LDS: the plane and its
+// ping-pong copy (rows padded by one), then the y and z twiddles.
 template <typename T, bool INVERSE>
 __global__ void __launch_bounds__(kYzThreads)
 fft_pass_yz(cplx<T>* __restrict__ X, const T* __restrict__ rin, T* __restrict__ rout, int nf,
-            long ld_real, long part_stride, int nparts, int ny, int nz, long nr, FftPlan py,
-            FftPlan pz, const cplx<T>* __restrict__ twy, const cplx<T>* __restrict__ twz,
-            VScale vs) {
+            long ld_real, long part_stride, int nparts, int nx, int ny, int nz, long nr,
+            FftPlan py, FftPlan pz, const cplx<T>* __restrict__ twy,
+            const cplx<T>* __restrict__ twz, VScale vs) {
   extern __shared__ unsigned char smem_raw[];
   const int ls = nz + 1;
   cplx<T>* buf0 = reinterpret_cast<cplx<T>*>(smem_raw);
   cplx<T>* buf1 = buf0 + ny * ls;
+  cplx<T>* twy_s = buf1 + ny * ls;
+  cplx<T>* twz_s = twy_s + ny;
+  stage_twiddles(twy_s, twy, ny);
+  stage_twiddles(twz_s, twz, nz);
   const int pair = blockIdx.y;
+  const int x = blockIdx.x;
   const int f0 = 2 * pair, f1 = 2 * pair + 1;
-  const long base = (long)blockIdx.x * ny * nz;
+  const long base = (long)x * ny * nz;     // plane x of a real field
   cplx<T>* Xp = X + (long)pair * nr;
+  const long yrow = (long)nx * nz;         // spectrum: row ky of plane x at (ky nx + x) nz
   const int cnt = ny * nz;
-  for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
-    const int y = e / nz, z = e - y * nz;
-    cplx<T> v;
-    if (!INVERSE) {
-      T a = 0, b = 0;
-      for (int q = 0; q < nparts; ++q) {
-        const T* src = rin + (long)q * part_stride;
-        a += src[(long)f0 * ld_real + base + e];
-        if (f1 < nf) b += src[(long)f1 * ld_real + base + e];
-      }
-      v = {a, b};
-    } else {
-      v = Xp[base + e];
-      v.y = -v.y;
-    }
-    buf0[y * ls + z] = v;
+  if (!INVERSE) {
+    batched_copy<kYzThreads, 4, cplx<T>>(
+        cnt,
+        [&](int e) {
+          T a = 0, b = 0;
+          for (int q = 0; q < nparts; ++q) {
+            const T* src = rin + (long)q * part_stride;
+            a += src[(long)f0 * ld_real + base + e];
+            if (f1 < nf) b += src[(long)f1 * ld_real + base + e];
+          }
+          return cplx<T>{a, b};
+        },
+        [&](int e, cplx<T> v) {
+          const int y = e / nz, z = e - y * nz;
+          buf0[y * ls + z] = v;
+        });
+  } else {
+    batched_copy<kYzThreads, 4, cplx<T>>(
+        cnt,
+        [&](int e) {
+          const int y = e / nz, z = e - y * nz;
+          return Xp[y * yrow + (long)x * nz + z];
+        },
+        [&](int e, cplx<T> v) {
+          const int y = e / nz, z = e - y * nz;
+          buf0[y * ls + z] = {v.x, -v.y};
+        });
   }
   __syncthreads();
   cplx<T>* res;
   if (!INVERSE) {
-    res = fft_lines<T>(buf0, buf1, ny, nz, ls, pz, twz);
+    res = fft_lines<T>(buf0, buf1, ny, nz, ls, pz, twz_s);
     cplx<T>* oth = (res == buf0) ? buf1 : buf0;
-    res = fft_lines<T, true>(res, oth, nz, ny, 1, py, twy, ls);
+    res = fft_lines<T, true>(res, oth, nz, ny, 1, py, twy_s, ls);
   } else {
-    res = fft_lines<T, true>(buf0, buf1, nz, ny, 1, py, twy, ls);
+    res = fft_lines<T, true>(buf0, buf1, nz, ny, 1, py, twy_s, ls);
     cplx<T>* oth = (res == buf0) ? buf1 : buf0;
-    res = fft_lines<T>(res, oth, ny, nz, ls, pz, twz);
+    res = fft_lines<T>(res, oth, ny, nz, ls, pz, twz_s);
   }
   T sc = 1;
   if (INVERSE && vs.xmax) {
@@ -251,11 +300,11 @@ fft_pass_yz(cplx<T>* __restrict__ X, const T* __restrict__ rin, T* __restrict__ 
     }
   }
   if (!INVERSE && vs.xmax && blockIdx.x == 0 && threadIdx.x == 0) vs.xmax[pair] = 0u;
-  for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+  for (int e = threadIdx.x; e < cnt; e += kYzThreads) {
     const int y = e / nz, z = e - y * nz;
     const cplx<T> v = res[y * ls + z];
     if (!INVERSE) {
-      Xp[base + e] = v;
+      Xp[y * yrow + (long)x * nz + z] = v;
     } else {
       put_v(rout, vs.out16, (long)f0 * ld_real + base + e, sc * v.x);
       if (f1 < nf) put_v(rout, vs.out16, (long)f1 * ld_real + base + e, -(sc * v.y));
@@ -266,9 +315,7 @@ fft_pass_yz(cplx<T>* __restrict__ X, const T* __restrict__ rin, T* __restrict__ 
 // Pass along z (contiguous lines).  Forward: builds the complex field from the
 // real fields 2p and 2p+1, summing nparts GEMM partial densities.  Inverse:
 // writes the real part to field 2p and the imaginary part to field 2p+1.
-// vmax (optional, [nf]): the forward pass clears it, the inverse pass leaves
-// max_r |V_f(r)| of each output field in it (float bits; the maximum of
-// non-negative floats is order-independent, so the value is deterministic).
+// LDS: lpb lines and their ping-pong copy (padded by one), then the twiddles.
 template <typename T, bool INVERSE>
 __global__ void __launch_bounds__(256)
 fft_pass_z(cplx<T>* __restrict__ X, const T* __restrict__ rin, T* __restrict__ rout,
@@ -279,6 +326,8 @@ fft_pass_z(cplx<T>* __restrict__ X, const T* __restrict__ rin, T* __restrict__ r
   cplx<T>* buf0 = reinterpret_cast<cplx<T>*>(smem_raw);
   const int ls = nz + 1;
   cplx<T>* buf1 = buf0 + lpb * ls;
+  cplx<T>* tws = buf1 + lpb * ls;
+  stage_twiddles(tws, tw, nz);
   const int pair = blockIdx.y;
   const int f0 = 2 * pair, f1 = 2 * pair + 1;
   const int line0 = blockIdx.x * lpb;
@@ -286,26 +335,34 @@ fft_pass_z(cplx<T>* __restrict__ X, const T* __restrict__ rin, T* __restrict__ r
   cplx<T>* Xp = X + (long)pair * nr;
   const long base = (long)line0 * nz;
   const int cnt = nl * nz;
-  // load
-  for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+  auto put = [&](int e, cplx<T> v) {
     const int l = e / nz, p = e - l * nz;
-    cplx<T> v;
-    if (!INVERSE) {
-      T a = 0, b = 0;
-      for (int q = 0; q < nparts; ++q) {
-        const T* src = rin + (long)q * part_stride;
-        a += src[(long)f0 * ld_real + base + e];
-        if (f1 < nf) b += src[(long)f1 * ld_real + base + e];
-      }
-      v = {a, b};
-    } else {
-      v = Xp[base + e];
-      v.y = -v.y;
-    }
     buf0[l * ls + p] = v;
+  };
+  if (!INVERSE) {
+    batched_copy<256, 4, cplx<T>>(
+        cnt,
+        [&](int e) {
+          T a = 0, b = 0;
+          for (int q = 0; q < nparts; ++q) {
+            const T* src = rin + (long)q * part_stride;
+            a += src[(long)f0 * ld_real + base + e];
+            if (f1 < nf) b += src[(long)f1 * ld_real + base + e];
+          }
+          return cplx<T>{a, b};
+        },
+        put);
+  } else {
+    batched_copy<256, 4, cplx<T>>(
+        cnt,
+        [&](int e) {
+          const cplx<T> v = Xp[base + e];
+          return cplx<T>{v.x, -v.y};
+        },
+        put);
   }
   __syncthreads();
-  cplx<T>* res = fft_lines<T>(buf0, buf1, nl, nz, ls, plan, tw);
+  cplx<T>* res = fft_lines<T>(buf0, buf1, nl, nz, ls, plan, tws);
   T sc = 1;
   if (INVERSE && vs.xmax) {
     const int e = f16_operand_exp(__uint_as_float(vs.xmax[pair]) * (float)(2 * nyz), vs.pexp);
@@ -328,54 +385,66 @@ fft_pass_z(cplx<T>* __restrict__ X, const T* __restrict__ rin, T* __restrict__ r
   }
 }
 
-// Pass along a strided axis (y: stride nz inside an x-slab; x: stride ny*nz).
-// A block takes lpb consecutive z-columns at a fixed (outer) index, so global
-// loads are coalesced along z.  MODE 0: forward, 1: inverse, 2: forward,
-// multiply by the Coulomb kernel, inverse (x axis only).
-template <typename T, int MODE>
-__global__ void __launch_bounds__(256)
+// Pass along a strided axis: element p of line l sits at p * pstride + l
+// from the block's corner, which is outer * outer_stride + iz0; a block takes
+// lpb consecutive lines (columns along the fastest index), so a row of its
+// tile is one contiguous run.  MODE 0: forward, 1: inverse, 2: forward,
+// multiply by the Coulomb kernel, inverse (x axis; outer is then ky and the
+// lines are kz).  LDS holds the tile element-major (element p of line l at
+// p (lpb + 1) + l), so consecutive threads touch consecutive words both when
+// loading rows and inside the butterflies, and the ping-pong copy and the
+// twiddles follow it.
+template <typename T, int MODE, int NT>
+__global__ void __launch_bounds__(NT)
 fft_pass_strided(cplx<T>* __restrict__ X, int n, long pstride, long outer_stride,
                  int nzb, int nz, long nr, int lpb, FftPlan plan,
                  const cplx<T>* __restrict__ tw, const T* __restrict__ g2x,
                  const T* __restrict__ g2y, const T* __restrict__ g2z, T vscale,
-                 int ny, unsigned* __restrict__ xmax) {
+                 unsigned* __restrict__ xmax) {
   extern __shared__ unsigned char smem_raw[];
+  const int es = lpb + 1;
   cplx<T>* buf0 = reinterpret_cast<cplx<T>*>(smem_raw);
-  const int ls = n + 1;
-  cplx<T>* buf1 = buf0 + lpb * ls;
+  cplx<T>* buf1 = buf0 + n * es;
+  cplx<T>* tws = buf1 + n * es;
+  stage_twiddles(tws, tw, n);
   const int pair = blockIdx.y;
   const int outer = blockIdx.x / nzb;
   const int iz0 = (blockIdx.x - outer * nzb) * lpb;
   const int nl = min(lpb, nz - iz0);
   cplx<T>* Xp = X + (long)pair * nr + (long)outer * outer_stride + iz0;
   const int cnt = nl * n;
-  for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
-    const int p = e / nl, l = e - p * nl;
-    cplx<T> v = Xp[(long)p * pstride + l];
-    if (MODE == 1) v.y = -v.y;
-    buf0[l * ls + p] = v;
-  }
+  batched_copy<NT, 4, cplx<T>>(
+      cnt,
+      [&](int e) {
+        const int p = e / nl, l = e - p * nl;
+        return Xp[(long)p * pstride + l];
+      },
+      [&](int e, cplx<T> v) {
+        const int p = e / nl, l = e - p * nl;
+        if (MODE == 1) v.y = -v.y;
+        buf0[p * es + l] = v;
+      });
   __syncthreads();
-  cplx<T>* res = fft_lines<T>(buf0, buf1, nl, n, ls, plan, tw);
+  cplx<T>* res = fft_lines<T, true>(buf0, buf1, nl, n, 1, plan, tws, es);
   if (MODE == 2) {
-    // res holds X(kx, ky = outer, kz = iz0 + l); multiply by v(G)/N and
+    // res holds X(kx = p, ky = outer, kz = iz0 + l); multiply by v(G)/N and
     // conjugate for the inverse transform.
     cplx<T>* other = (res == buf0) ? buf1 : buf0;
     const T gyz = g2y[outer];
-    for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
-      const int l = e / n, p = e - l * n;
+    for (int e = threadIdx.x; e < cnt; e += NT) {
+      const int p = e / nl, l = e - p * nl;
       const T g2 = g2x[p] + gyz + g2z[iz0 + l];
       const T k = (g2 > (T)0) ? vscale / g2 : (T)0;
-      cplx<T> v = res[l * ls + p];
-      other[l * ls + p] = {k * v.x, -k * v.y};
+      const cplx<T> v = res[p * es + l];
+      other[p * es + l] = {k * v.x, -k * v.y};
     }
     __syncthreads();
-    res = fft_lines<T>(other, res, nl, n, ls, plan, tw);
+    res = fft_lines<T, true>(other, res, nl, n, 1, plan, tws, es);
   }
   T mx = 0;
-  for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+  for (int e = threadIdx.x; e < cnt; e += NT) {
     const int p = e / nl, l = e - p * nl;
-    cplx<T> v = res[l * ls + p];
+    cplx<T> v = res[p * es + l];
     if (MODE == 1 || MODE == 2) v.y = -v.y;
     Xp[(long)p * pstride + l] = v;
     mx = fmax(mx, fmax(fabs(v.x), fabs(v.y)));
@@ -409,6 +478,12 @@ void poisson_prepare_device() {
                               hipFuncAttributeMaxDynamicSharedMemorySize, lim));
   GWL_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&fft_pass_yz<double, true>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+  GWL_HIP(hipFuncSetAttribute(
+      reinterpret_cast<const void*>(&fft_pass_strided<float, 2, kYzThreads>),
+      hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+  GWL_HIP(hipFuncSetAttribute(
+      reinterpret_cast<const void*>(&fft_pass_strided<double, 2, kYzThreads>),
+      hipFuncAttributeMaxDynamicSharedMemorySize, lim));
 }
 
 FftPlan make_plan(int n) {
@@ -420,6 +495,12 @@ FftPlan make_plan(int n) {
   while (m % 3 == 0 && m > 1) { p.radix[p.nstages++] = 3; m /= 3; }
   p.ok = (m == 1) && p.nstages <= 8;
   return p;
+}
+
+// LDS of the strided pass: the tile, its copy and the twiddles
+template <typename T>
+size_t strided_lds(int n, int lpb) {
+  return (2 * (size_t)n * (lpb + 1) + n) * sizeof(cplx<T>);
 }
 
 template <typename T>
@@ -439,64 +520,64 @@ void poisson_launch(const PoissonGeom<T>& g, const T* rin, long ld_in, long part
   if (lpb > g.nz) lpb = g.nz;
   const int nzb = ceil_div(g.nz, lpb);
   // Three HBM round trips when a yz plane and its ping-pong copy fit in LDS:
-  // yz forward (+ pack), x forward / kernel / x inverse, yz inverse (+ unpack)
-  const size_t sm_yz = 2 * (size_t)g.ny * (g.nz + 1) * sizeof(cplx<T>);
-  if (sm_yz <= kYzLdsMax) {
+  // yz forward (+ pack), x forward / kernel / x inverse over (x, kz) slabs of
+  // the y-major spectrum, yz inverse (+ unpack)
+  const size_t sm_yz = (2 * (size_t)g.ny * (g.nz + 1) + g.ny + g.nz) * sizeof(cplx<T>);
+  int lx = g.nz;  // kz columns per block of the x pass
+  while (lx > 1 && strided_lds<T>(g.nx, lx) > kYzLdsMax) lx = (lx + 1) / 2;
+  if (sm_yz <= kYzLdsMax && strided_lds<T>(g.nx, lx) <= kYzLdsMax) {
     dim3 gyz(g.nx, npairs);
-    fft_pass_yz<T, false><<<gyz, kYzThreads, sm_yz, st>>>(scratch, rin, nullptr, nf, ld_in, part_stride,
-                                                   nparts, g.ny, g.nz, nr, g.py, g.pz, g.twy,
-                                                   g.twz, vs);
-    dim3 grid(g.ny * nzb, npairs);
-    size_t sm = 2 * (size_t)lpb * (g.nx + 1) * sizeof(cplx<T>);
-    fft_pass_strided<T, 2><<<grid, 256, sm, st>>>(scratch, g.nx, (long)g.ny * g.nz, g.nz,
-                                                  nzb, g.nz, nr, lpb, g.px, g.twx, g.g2x,
-                                                  g.g2y, g.g2z, g.vscale, g.ny, xm);
-    fft_pass_yz<T, true><<<gyz, kYzThreads, sm_yz, st>>>(scratch, nullptr, rout, nf, ld_out, 0, 1,
-                                                  g.ny, g.nz, nr, g.py, g.pz, g.twy, g.twz,
-                                                  vs);
+    fft_pass_yz<T, false><<<gyz, kYzThreads, sm_yz, st>>>(
+        scratch, rin, nullptr, nf, ld_in, part_stride, nparts, g.nx, g.ny, g.nz, nr, g.py, g.pz,
+        g.twy, g.twz, vs);
+    const int nzbx = ceil_div(g.nz, lx);
+    dim3 gx(g.ny * nzbx, npairs);
+    fft_pass_strided<T, 2, kYzThreads><<<gx, kYzThreads, strided_lds<T>(g.nx, lx), st>>>(
+        scratch, g.nx, g.nz, (long)g.nx * g.nz, nzbx, g.nz, nr, lx, g.px, g.twx, g.g2x, g.g2y,
+        g.g2z, g.vscale, xm);
+    fft_pass_yz<T, true><<<gyz, kYzThreads, sm_yz, st>>>(
+        scratch, nullptr, rout, nf, ld_out, 0, 1, g.nx, g.ny, g.nz, nr, g.py, g.pz, g.twy, g.twz,
+        vs);
     GWL_HIP(hipGetLastError());
     return;
   }
   // otherwise five: z forward + pack
   {
-    const int lpb = lines_per_block<T>(g.nz);
+    const int lpbz = lines_per_block<T>(g.nz);
     const int nlines = g.nx * g.ny;
-    dim3 grid(ceil_div(nlines, lpb), npairs);
-    size_t sm = 2 * (size_t)lpb * (g.nz + 1) * sizeof(cplx<T>);
+    dim3 grid(ceil_div(nlines, lpbz), npairs);
+    size_t sm = (2 * (size_t)lpbz * (g.nz + 1) + g.nz) * sizeof(cplx<T>);
     fft_pass_z<T, false><<<grid, 256, sm, st>>>(scratch, rin, nullptr, nf, ld_in,
                                                 part_stride, nparts, nlines, g.nz, nr,
-                                                lpb, g.pz, g.twz, vs, nyz);
+                                                lpbz, g.pz, g.twz, vs, nyz);
   }
   // y forward
   {
     dim3 grid(g.nx * nzb, npairs);
-    size_t sm = 2 * (size_t)lpb * (g.ny + 1) * sizeof(cplx<T>);
-    fft_pass_strided<T, 0><<<grid, 256, sm, st>>>(scratch, g.ny, g.nz, (long)g.ny * g.nz,
-                                                  nzb, g.nz, nr, lpb, g.py, g.twy, nullptr,
-                                                  nullptr, nullptr, (T)0, g.ny, nullptr);
+    fft_pass_strided<T, 0, 256><<<grid, 256, strided_lds<T>(g.ny, lpb), st>>>(
+        scratch, g.ny, g.nz, (long)g.ny * g.nz, nzb, g.nz, nr, lpb, g.py, g.twy, nullptr,
+        nullptr, nullptr, (T)0, nullptr);
   }
   // x forward, kernel, x inverse
   {
     dim3 grid(g.ny * nzb, npairs);
-    size_t sm = 2 * (size_t)lpb * (g.nx + 1) * sizeof(cplx<T>);
-    fft_pass_strided<T, 2><<<grid, 256, sm, st>>>(scratch, g.nx, (long)g.ny * g.nz, g.nz,
-                                                  nzb, g.nz, nr, lpb, g.px, g.twx, g.g2x,
-                                                  g.g2y, g.g2z, g.vscale, g.ny, xm);
+    fft_pass_strided<T, 2, 256><<<grid, 256, strided_lds<T>(g.nx, lpb), st>>>(
+        scratch, g.nx, (long)g.ny * g.nz, g.nz, nzb, g.nz, nr, lpb, g.px, g.twx, g.g2x, g.g2y,
+        g.g2z, g.vscale, xm);
   }
   // y inverse
   {
     dim3 grid(g.nx * nzb, npairs);
-    size_t sm = 2 * (size_t)lpb * (g.ny + 1) * sizeof(cplx<T>);
-    fft_pass_strided<T, 1><<<grid, 256, sm, st>>>(scratch, g.ny, g.nz, (long)g.ny * g.nz,
-                                                  nzb, g.nz, nr, lpb, g.py, g.twy, nullptr,
-                                                  nullptr, nullptr, (T)0, g.ny, nullptr);
+    fft_pass_strided<T, 1, 256><<<grid, 256, strided_lds<T>(g.ny, lpb), st>>>(
+        scratch, g.ny, g.nz, (long)g.ny * g.nz, nzb, g.nz, nr, lpb, g.py, g.twy, nullptr,
+        nullptr, nullptr, (T)0, nullptr);
   }
   // z inverse + unpack
   {
     const int lpbz = lines_per_block<T>(g.nz);
     const int nlines = g.nx * g.ny;
     dim3 grid(ceil_div(nlines, lpbz), npairs);
-    size_t sm = 2 * (size_t)lpbz * (g.nz + 1) * sizeof(cplx<T>);
+    size_t sm = (2 * (size_t)lpbz * (g.nz + 1) + g.nz) * sizeof(cplx<T>);
     fft_pass_z<T, true><<<grid, 256, sm, st>>>(scratch, nullptr, rout, nf, ld_out, 0, 1,
                                                nlines, g.nz, nr, lpbz, g.pz, g.twz, vs, nyz);
   }

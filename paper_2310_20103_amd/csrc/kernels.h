@@ -12,7 +12,7 @@ struct FftPlan {
   int ok;
 };
 FftPlan make_plan(int n);
-// Once per device at setup: lets the yz-plane pass use up to 80 KB of LDS.
+// Once per device at setup: lets the yz-plane and x-slab passes use up to 80 KB of LDS.
 void poisson_prepare_device();
 
 template <typename T>
