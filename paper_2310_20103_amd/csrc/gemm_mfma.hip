@@ -331,12 +331,15 @@ __device__ inline u4 mul8(u4 pv, u4 v) {
 // one pair vector: four phi_v rows, one potential), 0 otherwise.
 template <int NVP>
 struct LoadPsiV16 {
-  const f16_t* psi_v_t;
+  const f16_t* psi_v_t;  // K panels
   const f16_t* vpot;
   long nrp;
   int nvp;
+  long ph;  // halves per K panel
+  __device__ long at(int row, int k) const { return (long)(k >> 5) * ph + (long)row * 32 + (k & 31); }
   static constexpr int NPV = NVP == 64 ? 1 : (NVP == 128 ? 2 : 4);
   static constexpr int NB = NVP == 128 ? 2 : (NVP == 256 ? 1 : 4);
+  static constexpr int kLoads = NPV + NB;  // global loads per thread and K step
   struct Raw {
     u4 pv[NPV];
     u4 v[NB];
@@ -345,13 +348,13 @@ struct LoadPsiV16 {
     const int k = k0 + (t & 3) * 8;
     const int r0 = t >> 2;
     if constexpr (NVP == 64) {
-      r.pv[0] = *reinterpret_cast<const u4*>(psi_v_t + (long)r0 * nrp + k);
+      r.pv[0] = *reinterpret_cast<const u4*>(psi_v_t + at(r0, k));
 #pragma unroll
       for (int q = 0; q < 4; ++q)
         r.v[q] = *reinterpret_cast<const u4*>(vpot + (long)(m0 / 64 + q) * nrp + k);
     } else if constexpr (NVP == 128) {
-      r.pv[0] = *reinterpret_cast<const u4*>(psi_v_t + (long)r0 * nrp + k);
-      r.pv[1] = *reinterpret_cast<const u4*>(psi_v_t + (long)(r0 + 64) * nrp + k);
+      r.pv[0] = *reinterpret_cast<const u4*>(psi_v_t + at(r0, k));
+      r.pv[1] = *reinterpret_cast<const u4*>(psi_v_t + at(r0 + 64, k));
 #pragma unroll
       for (int h = 0; h < 2; ++h)
         r.v[h] = *reinterpret_cast<const u4*>(vpot + (long)(m0 / 128 + h) * nrp + k);
@@ -359,14 +362,14 @@ struct LoadPsiV16 {
       const int b = m0 / nvp, v0 = m0 - b * nvp + r0;
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        r.pv[q] = *reinterpret_cast<const u4*>(psi_v_t + (long)(v0 + 64 * q) * nrp + k);
+        r.pv[q] = *reinterpret_cast<const u4*>(psi_v_t + at(v0 + 64 * q, k));
       r.v[0] = *reinterpret_cast<const u4*>(vpot + (long)b * nrp + k);
     } else {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int m = m0 + r0 + 64 * q;
         const int b = m / nvp, vv = m - b * nvp;
-        r.pv[q] = *reinterpret_cast<const u4*>(psi_v_t + (long)vv * nrp + k);
+        r.pv[q] = *reinterpret_cast<const u4*>(psi_v_t + at(vv, k));
         r.v[q] = *reinterpret_cast<const u4*>(vpot + (long)b * nrp + k);
       }
     }
@@ -402,6 +405,18 @@ __device__ inline void bf_gload(const LA& la, const bf16_t* __restrict__ bop, lo
 #pragma unroll
   for (int q = 0; q < BfCfg<BN>::QB; ++q)
     x.b[q] = *reinterpret_cast<const u4*>(p + (long)64 * q * ldb);
+}
+
+// Second GEMM: as bf_gload, with the B operand (conduction orbitals) read from
+// K panels (bop = panel base + N_vp * 32, ph = halves per panel).
+template <typename LA, int BN>
+__device__ inline void g2_gload(const LA& la, const bf16_t* __restrict__ bop, long ph, int m0,
+                                int n0, int k0, BfStage<LA, BN>& x) {
+  const int t = threadIdx.x;
+  la.load(m0, t, k0, x.a);
+  const bf16_t* p = bop + (long)(k0 >> 5) * ph + (long)(n0 + (t >> 2)) * 32 + (t & 3) * 8;
+#pragma unroll
+  for (int q = 0; q < BfCfg<BN>::QB; ++q) x.b[q] = *reinterpret_cast<const u4*>(p + 64 * 32 * q);
 }
 
 template <typename LA, int BN>
@@ -662,30 +677,33 @@ gemm1_f16_n128_kernel(GemmDims d, int M, int nb, const f16_t* __restrict__ psi_c
 }
 
 // Instruction order of one second-GEMM K step (256 x 256 tile, per wave 32
-// MFMAs, 16 LDS fragment reads, 8 global loads of the step after next, 16
-// packed FP16 products phi_v V and 8 LDS stores of the next step), imposed
-// on the compiler's scheduler: four fragment reads, then per MFMA one
-// fragment read (first twelve), the products two per MFMA over the first
-// eight, a global load every third MFMA and the stores behind MFMAs 14 to
-// 21.  Spreading the loads is what matters: issuing all eight up front made
-// the compiler drain the load counter before the stores (4.66 ms per launch
-// at the headline shape against 3.69 ms with this order).
-template <int G>
+// MFMAs, 16 LDS fragment reads, NL global loads of the step after next: 8 or
+// 9 at N_v = 64, 128, 256, 12 otherwise; 16 packed FP16 products phi_v V and
+// 8 LDS stores of the next step), imposed on the compiler's scheduler: four
+// fragment reads, then per MFMA one fragment read (first twelve), the
+// products two per MFMA over the first eight, the loads one every third MFMA
+// (every second for more than ten) and the stores behind MFMAs 14 to 21.
+// Spreading the loads is what matters: issuing them all up front made the
+// compiler drain the load counter before the stores (4.66 ms per launch at
+// the headline shape against 3.69 ms with this order), and so did a load
+// left without a slot (514 ms against 314 ms at N_v = 512).
+template <int G, int NL>
 __device__ inline void g2_sched() {
+  constexpr int SP = NL <= 10 ? 3 : 2;
   if constexpr (G < 32) {
     if constexpr (G == 0) __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);  // LDS reads
     __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                       // MFMA
     if constexpr (G < 12) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // LDS reads
     if constexpr (G < 8) __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);   // VALU
-    if constexpr (G % 3 == 1 && G < 24) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // loads
+    if constexpr (G % SP == 1 && G / SP < NL) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
     if constexpr (G >= 14 && G < 22) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);  // LDS writes
-    g2_sched<G + 1>();
+    g2_sched<G + 1, NL>();
   }
 }
 
-// Second GEMM over one split of the grid sum: global loads two K steps ahead,
-// the A operand of the next step scaled by the potential and stored after the
-// current step's MFMAs.
+// Second GEMM over one split of the grid sum: global loads two K steps ahead
+// (orbitals from K panels), the A operand of the next step scaled by the
+// potential and stored after the current step's MFMAs.
 template <int BN, int NVP>
 __device__ inline void gemm2_f16_body(const GemmDims& d, int M, int splitk, int kchunk,
                                       const f16_t* __restrict__ psi_v_t,
@@ -708,27 +726,28 @@ __device__ inline void gemm2_f16_body(const GemmDims& d, int M, int splitk, int 
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < WN; ++j) acc[i][j] = f16v{};
-  LoadPsiV16<NVP> la{psi_v_t, vpot, d.nrp, d.nvp};
+  const long ph = panel_halves(d);
+  LoadPsiV16<NVP> la{psi_v_t, vpot, d.nrp, d.nvp, ph};
   // Two register stages: the loads of step i + 2 are in flight while step i
   // computes and step i + 1 is scaled into the other LDS buffer.  The last
   // steps reload the final slab instead of branching.
   BfStage<LoadPsiV16<NVP>, BN> x0, x1;
   if (nsteps > 0) {
-    bf_gload(la, psi_c_t, d.nrp, m0, n0, kb, x0);
-    bf_gload(la, psi_c_t, d.nrp, m0, n0, kb + HK, x1);
+    g2_gload(la, psi_c_t, ph, m0, n0, kb, x0);
+    g2_gload(la, psi_c_t, ph, m0, n0, kb + HK, x1);
     bf_lstore(la, sm, 0, x0);
   }
   __syncthreads();
   for (int i = 0; i < nsteps; i += 2) {
-    bf_gload(la, psi_c_t, d.nrp, m0, n0, kb + min(i + 2, nsteps - 1) * HK, x0);
+    g2_gload(la, psi_c_t, ph, m0, n0, kb + min(i + 2, nsteps - 1) * HK, x0);
     bf_compute<BN, OpF16>(sm, 0, acc);
     bf_lstore(la, sm, 1, x1);
-    if constexpr (BN == 256) g2_sched<0>();
+    if constexpr (BN == 256) g2_sched<0, LoadPsiV16<NVP>::kLoads + BfCfg<BN>::QB>();
     __syncthreads();
-    bf_gload(la, psi_c_t, d.nrp, m0, n0, kb + min(i + 3, nsteps - 1) * HK, x1);
+    g2_gload(la, psi_c_t, ph, m0, n0, kb + min(i + 3, nsteps - 1) * HK, x1);
     bf_compute<BN, OpF16>(sm, 1, acc);
     bf_lstore(la, sm, 0, x0);
-    if constexpr (BN == 256) g2_sched<0>();
+    if constexpr (BN == 256) g2_sched<0, LoadPsiV16<NVP>::kLoads + BfCfg<BN>::QB>();
     __syncthreads();
   }
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;

@@ -78,7 +78,11 @@ template <typename A, typename TO, typename TV>
 __global__ void __launch_bounds__(256)
 gemm2_simple_kernel(GemmDims d, const TO* __restrict__ psi_v_t,
                  const TO* __restrict__ psi_c_t, const TV* __restrict__ vpot,
-                 A* __restrict__ ypart, int nb, int splitk, int kchunk, int round16) {
+                 A* __restrict__ ypart, int nb, int splitk, int kchunk, int round16, long ph) {
+  // orbital (row, r): K panels of 32 points when ph > 0, else rows of N_rp
+  auto at = [&](int row, int r) {
+    return ph ? (long)(r >> 5) * ph + (long)row * 32 + (r & 31) : (long)row * d.nrp + r;
+  };
   __shared__ A As[TK][LDT];
   __shared__ A Bs[TK][LDT];
   const int tid = threadIdx.x;
@@ -92,11 +96,11 @@ gemm2_simple_kernel(GemmDims d, const TO* __restrict__ psi_v_t,
   for (int r = rbeg; r < rend; r += TK) {
     for (int e = tid; e < TK * TM; e += 256) {
       const int kk = e & (TK - 1), i = e >> 4;
-      A av = (A)ldx(psi_v_t, (long)(v0 + i) * d.nrp + r + kk) * (A)ldx(vb, r + kk);
+      A av = (A)ldx(psi_v_t, at(v0 + i, r + kk)) * (A)ldx(vb, r + kk);
       // mixed path: the operand phi_v V_b is rounded to FP16 as in the MFMA kernel
       if (round16) av = (A)(float)(_Float16)(float)av;
       As[kk][i] = av;
-      Bs[kk][i] = ldx(psi_c_t, (long)(c0 + i) * d.nrp + r + kk);
+      Bs[kk][i] = ldx(psi_c_t, at(c0 + i, r + kk));
     }
     __syncthreads();
 #pragma unroll
@@ -152,7 +156,7 @@ void gemm2_f16s(const GemmDims& d, int nb, int splitk, const f16_t* psi_v_t,
   const int kchunk = (int)round_up(ceil_div(d.nrp, splitk), TK);
   dim3 grid(d.ncp / TN, d.nvp / TM, nb * splitk);
   gemm2_simple_kernel<float, f16_t, f16_t><<<grid, 256, 0, st>>>(d, psi_v_t, psi_c_t, vpot, ypart,
-                                                          nb, splitk, kchunk, 1);
+                                                          nb, splitk, kchunk, 1, panel_halves(d));
   GWL_HIP(hipGetLastError());
 }
 
@@ -162,7 +166,7 @@ void gemm2_f64(const GemmDims& d, int nb, int splitk, const double* psi_v_t,
   const int kchunk = (int)round_up(ceil_div(d.nrp, splitk), TK);
   dim3 grid(d.ncp / TN, d.nvp / TM, nb * splitk);
   gemm2_simple_kernel<double, double, double><<<grid, 256, 0, st>>>(d, psi_v_t, psi_c_t, vpot, ypart,
-                                                             nb, splitk, kchunk, 0);
+                                                             nb, splitk, kchunk, 0, 0);
   GWL_HIP(hipGetLastError());
 }
 
