@@ -106,16 +106,16 @@ def oracle_vector(wl, pr, m, n, steps, lo, hi, omega):
     return sig, time.perf_counter() - t0
 
 
-def cpu_baseline(wl, seconds, m, n, steps):
-    """The oracle's time for one start vector over `steps` Lanczos steps
-    (coupling vector included), extrapolated to spectra/s."""
-    per_spectrum = seconds / steps * wl.n_lanczos * wl.n_orb
+def cpu_baseline(wl, seconds, m, ns, steps):
+    """The oracle's time for len(ns) start vectors over `steps` Lanczos steps
+    each (coupling vectors included), extrapolated to spectra/s."""
+    per_spectrum = seconds / (len(ns) * steps) * wl.n_lanczos * wl.n_orb
     return {
         "value": 1.0 / per_spectrum, "unit": "spectra/s", "cores": oracle_threads(),
         "kind": "oracle",
-        "sample": (f"oracle matrix-free Lanczos on p_{wl.poly_degree}(C), 1 start vector "
-                   f"(m={m}, n={n}), {steps} steps incl. its coupling vector, "
-                   f"{seconds:.1f} s, extrapolated x {wl.n_lanczos} steps x "
+        "sample": (f"oracle matrix-free Lanczos on p_{wl.poly_degree}(C), {len(ns)} start "
+                   f"vectors (m={m}, n in {list(ns)}), {steps} steps each incl. the coupling "
+                   f"vector, {seconds:.1f} s, extrapolated x {wl.n_lanczos} steps x "
                    f"{wl.n_orb} vectors; BLAS on the stated threads, FFT on one"),
     }
 
@@ -673,7 +673,7 @@ def main():
                     help="vectors per batch (default 64 in adjoint mode, else 128)")
     ap.add_argument("--workload", default="grid64_v128c512")
     ap.add_argument("--fp64-window", type=int, default=2, help="Lanczos steps of the FP64 window")
-    ap.add_argument("--cpu-steps", type=int, default=4,
+    ap.add_argument("--cpu-steps", type=int, default=6,
                     help="Lanczos steps of the oracle sample (timed for cpu_baseline and "
                          "compared with the GPU paths)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -851,7 +851,7 @@ def main():
         "accuracy_smooth": stress,
         "roofline": roofline,
     }
-    line["cpu_baseline"] = cpu_baseline(wl, t_or[0], mw, ns[0], acc_L)
+    line["cpu_baseline"] = cpu_baseline(wl, float(sum(t_or)), mw, ns, acc_L)
     print(json.dumps(line), flush=True)
 
 

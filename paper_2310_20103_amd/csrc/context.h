@@ -178,7 +178,7 @@ struct gwl_ctx {
   DevBuf<double> psi_t;       // [NVp + NCp][NRp]
   DevBuf<double> psi_c_rc64;  // [NRp][NCp]
   DevBuf<double> psi_v_rv64;  // [NRp][NVp]
-  DevBuf<f16_t> psi_t16;      // K panels of [NVp + NCp][32] FP16, scaled by orb16_scale
+  DevBuf<f16_t> psi_t16;      // [NVp + NCp] rows or K panels (orb16_index), FP16, scaled
   int pv16_exp = 0;           // frexp exponent of max |phi_v| in psi_t16
   DevBuf<unsigned> xmax32;    // mixed Poisson solve: bound scratch per field pair
   DevBuf<int> vexp32;         // [cap] scale exponent of each mixed potential
@@ -466,8 +466,8 @@ struct gwl_ctx {
                               reinterpret_cast<cplx<float>*>(fftx.p), st, xmax32.p,
                               vexp32.p, pv16_exp, vpot16.p);
       prof_end(2, nb);
-      const f16_t* pv = pt;  // K panels: conduction rows follow the N_vp occupied ones
-      const f16_t* pc = pt + (size_t)d.nvp * 32;
+      const f16_t* pv = pt;
+      const f16_t* pc = pt + orb16_index(d, d.nvp, 0);  // the conduction rows follow
       prof_begin();
       if (fp64_kernel)
         gemm2_f16(d, nb, bf16_tile, S, pv, pc, vpot16.p, yp, st);

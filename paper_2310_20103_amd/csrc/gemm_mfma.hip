@@ -329,14 +329,17 @@ __device__ inline u4 mul8(u4 pv, u4 v) {
 // or 128 (a thread's four rows then share one or two phi_v rows and use four
 // or two potentials), 256 when it is a multiple of 256 (a tile lies inside
 // one pair vector: four phi_v rows, one potential), 0 otherwise.
-template <int NVP>
+template <int NVP, bool PANEL>
 struct LoadPsiV16 {
-  const f16_t* psi_v_t;  // K panels
+  const f16_t* psi_v_t;
   const f16_t* vpot;
   long nrp;
   int nvp;
-  long ph;  // halves per K panel
-  __device__ long at(int row, int k) const { return (long)(k >> 5) * ph + (long)row * 32 + (k & 31); }
+  long ph;  // halves per K panel (PANEL)
+  __device__ long at(int row, int k) const {
+    if constexpr (PANEL) return (long)(k >> 5) * ph + (long)row * 32 + (k & 31);
+    else return (long)row * nrp + k;
+  }
   static constexpr int NPV = NVP == 64 ? 1 : (NVP == 128 ? 2 : 4);
   static constexpr int NB = NVP == 128 ? 2 : (NVP == 256 ? 1 : 4);
   static constexpr int kLoads = NPV + NB;  // global loads per thread and K step
@@ -407,16 +410,21 @@ __device__ inline void bf_gload(const LA& la, const bf16_t* __restrict__ bop, lo
     x.b[q] = *reinterpret_cast<const u4*>(p + (long)64 * q * ldb);
 }
 
-// Second GEMM: as bf_gload, with the B operand (conduction orbitals) read from
-// K panels (bop = panel base + N_vp * 32, ph = halves per panel).
-template <typename LA, int BN>
-__device__ inline void g2_gload(const LA& la, const bf16_t* __restrict__ bop, long ph, int m0,
-                                int n0, int k0, BfStage<LA, BN>& x) {
-  const int t = threadIdx.x;
-  la.load(m0, t, k0, x.a);
-  const bf16_t* p = bop + (long)(k0 >> 5) * ph + (long)(n0 + (t >> 2)) * 32 + (t & 3) * 8;
+// Second GEMM: as bf_gload, with the B operand (conduction orbitals) read
+// from K panels when PANEL (bop = the first conduction value, ph = halves per
+// panel), else from rows of ldb values.
+template <bool PANEL, typename LA, int BN>
+__device__ inline void g2_gload(const LA& la, const bf16_t* __restrict__ bop, long ldb, long ph,
+                                int m0, int n0, int k0, BfStage<LA, BN>& x) {
+  if constexpr (PANEL) {
+    const int t = threadIdx.x;
+    la.load(m0, t, k0, x.a);
+    const bf16_t* p = bop + (long)(k0 >> 5) * ph + (long)(n0 + (t >> 2)) * 32 + (t & 3) * 8;
 #pragma unroll
-  for (int q = 0; q < BfCfg<BN>::QB; ++q) x.b[q] = *reinterpret_cast<const u4*>(p + 64 * 32 * q);
+    for (int q = 0; q < BfCfg<BN>::QB; ++q) x.b[q] = *reinterpret_cast<const u4*>(p + 64 * 32 * q);
+  } else {
+    bf_gload(la, bop, ldb, m0, n0, k0, x);
+  }
 }
 
 template <typename LA, int BN>
@@ -702,9 +710,9 @@ __device__ inline void g2_sched() {
 }
 
 // Second GEMM over one split of the grid sum: global loads two K steps ahead
-// (orbitals from K panels), the A operand of the next step scaled by the
+// (orbitals from rows or K panels), the A operand of the next step scaled by the
 // potential and stored after the current step's MFMAs.
-template <int BN, int NVP>
+template <int BN, int NVP, bool PANEL>
 __device__ inline void gemm2_f16_body(const GemmDims& d, int M, int splitk, int kchunk,
                                       const f16_t* __restrict__ psi_v_t,
                                       const f16_t* __restrict__ psi_c_t16,
@@ -726,28 +734,28 @@ __device__ inline void gemm2_f16_body(const GemmDims& d, int M, int splitk, int 
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < WN; ++j) acc[i][j] = f16v{};
-  const long ph = panel_halves(d);
-  LoadPsiV16<NVP> la{psi_v_t, vpot, d.nrp, d.nvp, ph};
+  const long ph = orb16_panel_halves(d);
+  LoadPsiV16<NVP, PANEL> la{psi_v_t, vpot, d.nrp, d.nvp, ph};
   // Two register stages: the loads of step i + 2 are in flight while step i
   // computes and step i + 1 is scaled into the other LDS buffer.  The last
   // steps reload the final slab instead of branching.
-  BfStage<LoadPsiV16<NVP>, BN> x0, x1;
+  BfStage<LoadPsiV16<NVP, PANEL>, BN> x0, x1;
   if (nsteps > 0) {
-    g2_gload(la, psi_c_t, ph, m0, n0, kb, x0);
-    g2_gload(la, psi_c_t, ph, m0, n0, kb + HK, x1);
+    g2_gload<PANEL>(la, psi_c_t, d.nrp, ph, m0, n0, kb, x0);
+    g2_gload<PANEL>(la, psi_c_t, d.nrp, ph, m0, n0, kb + HK, x1);
     bf_lstore(la, sm, 0, x0);
   }
   __syncthreads();
   for (int i = 0; i < nsteps; i += 2) {
-    g2_gload(la, psi_c_t, ph, m0, n0, kb + min(i + 2, nsteps - 1) * HK, x0);
+    g2_gload<PANEL>(la, psi_c_t, d.nrp, ph, m0, n0, kb + min(i + 2, nsteps - 1) * HK, x0);
     bf_compute<BN, OpF16>(sm, 0, acc);
     bf_lstore(la, sm, 1, x1);
-    if constexpr (BN == 256) g2_sched<0, LoadPsiV16<NVP>::kLoads + BfCfg<BN>::QB>();
+    if constexpr (BN == 256) g2_sched<0, LoadPsiV16<NVP, PANEL>::kLoads + BfCfg<BN>::QB>();
     __syncthreads();
-    g2_gload(la, psi_c_t, ph, m0, n0, kb + min(i + 3, nsteps - 1) * HK, x1);
+    g2_gload<PANEL>(la, psi_c_t, d.nrp, ph, m0, n0, kb + min(i + 3, nsteps - 1) * HK, x1);
     bf_compute<BN, OpF16>(sm, 1, acc);
     bf_lstore(la, sm, 0, x0);
-    if constexpr (BN == 256) g2_sched<0, LoadPsiV16<NVP>::kLoads + BfCfg<BN>::QB>();
+    if constexpr (BN == 256) g2_sched<0, LoadPsiV16<NVP, PANEL>::kLoads + BfCfg<BN>::QB>();
     __syncthreads();
   }
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -767,19 +775,19 @@ __device__ inline void gemm2_f16_body(const GemmDims& d, int M, int splitk, int 
   }
 }
 
-template <int NVP>
+template <int NVP, bool PANEL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 gemm2_f16_n128_kernel(GemmDims d, int M, int splitk, int kchunk,
                       const f16_t* __restrict__ psi_v_t, const f16_t* __restrict__ psi_c_t,
                       const f16_t* __restrict__ vpot, float* __restrict__ ypart) {
-  gemm2_f16_body<128, NVP>(d, M, splitk, kchunk, psi_v_t, psi_c_t, vpot, ypart);
+  gemm2_f16_body<128, NVP, PANEL>(d, M, splitk, kchunk, psi_v_t, psi_c_t, vpot, ypart);
 }
-template <int NVP>
+template <int NVP, bool PANEL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 gemm2_f16_n256_kernel(GemmDims d, int M, int splitk, int kchunk,
                       const f16_t* __restrict__ psi_v_t, const f16_t* __restrict__ psi_c_t,
                       const f16_t* __restrict__ vpot, float* __restrict__ ypart) {
-  gemm2_f16_body<256, NVP>(d, M, splitk, kchunk, psi_v_t, psi_c_t, vpot, ypart);
+  gemm2_f16_body<256, NVP, PANEL>(d, M, splitk, kchunk, psi_v_t, psi_c_t, vpot, ypart);
 }
 
 }  // namespace
@@ -832,9 +840,18 @@ void gemm2_f16(const GemmDims& d, int nb, int bn, int splitk, const f16_t* psi_v
   const int M = nb * d.nvp;
   const int kchunk = (int)round_up(ceil_div(d.nrp, splitk), 2 * HK);
   const int blocks = gemm2_f16_blocks(d, nb, bn) * splitk;
-#define GWL_G2(BNV, NVPV)                                                                  \
-  gemm2_f16_n##BNV##_kernel<NVPV><<<blocks, 256, 0, st>>>(d, M, splitk, kchunk, psi_v_t, \
-                                                           psi_c_t, vpot, ypart)
+  const bool panel = orb16_panel_halves(d) != 0;
+#define GWL_G2(BNV, NVPV)                                                                    \
+  do {                                                                                       \
+    if (panel)                                                                               \
+      gemm2_f16_n##BNV##_kernel<NVPV, true><<<blocks, 256, 0, st>>>(d, M, splitk, kchunk,    \
+                                                                    psi_v_t, psi_c_t, vpot,  \
+                                                                    ypart);                  \
+    else                                                                                     \
+      gemm2_f16_n##BNV##_kernel<NVPV, false><<<blocks, 256, 0, st>>>(d, M, splitk, kchunk,   \
+                                                                     psi_v_t, psi_c_t, vpot, \
+                                                                     ypart);                 \
+  } while (0)
   if (bn == 256) {
     if (d.nvp == 64) GWL_G2(256, 64);
     else if (d.nvp == 128) GWL_G2(256, 128);

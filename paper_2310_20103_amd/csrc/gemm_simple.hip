@@ -156,7 +156,7 @@ void gemm2_f16s(const GemmDims& d, int nb, int splitk, const f16_t* psi_v_t,
   const int kchunk = (int)round_up(ceil_div(d.nrp, splitk), TK);
   dim3 grid(d.ncp / TN, d.nvp / TM, nb * splitk);
   gemm2_simple_kernel<float, f16_t, f16_t><<<grid, 256, 0, st>>>(d, psi_v_t, psi_c_t, vpot, ypart,
-                                                          nb, splitk, kchunk, 1, panel_halves(d));
+                                                          nb, splitk, kchunk, 1, orb16_panel_halves(d));
   GWL_HIP(hipGetLastError());
 }
 

@@ -267,15 +267,14 @@ gwl_status gwl_setup(const void* orbitals, int orb_dtype, int orb_on_device, int
         c.orb16_scale = std::ldexp(1.0, e);
       }
       const double os = c.orb16_scale;
-      // the second GEMM's orbitals in K panels of 32 grid points
-      const long ph = panel_halves(c.gd);
+      // the second GEMM's orbitals, in rows or K panels (orb16_index)
       std::vector<f16_t> t16((size_t)panel_rows(c.gd) * nrp, f16_t{0});
       std::vector<f16_t> c16(crc.size());
       float pvmax = 0.0f;
       for (size_t i = 0; i < host.size(); ++i) {
         const long row = (long)(i / nrp), r = (long)(i % nrp);
         const f16_t h = f32_to_f16((float)(os * host[i]));
-        t16[(size_t)((r >> 5) * ph + row * 32 + (r & 31))] = h;
+        t16[(size_t)orb16_index(c.gd, row, r)] = h;
         if (row < nvp) pvmax = std::max(pvmax, std::fabs(f16_to_f32(h)));
       }
       c.pv16_exp = 0;

@@ -228,14 +228,13 @@ extern "C" gwl_status gwl_isdf_setup(gwl_ctx* ctx, const int* points, int n_mu) 
                              st));
       GWL_HIP(hipStreamSynchronize(st));
       const double os = c.orb16_scale;
-      // the second GEMM's sampled orbitals in K panels of 32 points
-      const long ph = panel_halves(di);
+      // the second GEMM's sampled orbitals, in rows or K panels (orb16_index)
       std::vector<f16_t> t16((size_t)panel_rows(di) * nrpi, f16_t{0});
       std::vector<f16_t> c16(crc.size()), v16(vrv.size());
       std::vector<float> v32(vrv.size());
       for (size_t i = 0; i < t.size(); ++i) {
         const long row = (long)(i / nrpi), r = (long)(i % nrpi);
-        t16[(size_t)((r >> 5) * ph + row * 32 + (r & 31))] = f32_to_f16((float)(os * t[i]));
+        t16[(size_t)orb16_index(di, row, r)] = f32_to_f16((float)(os * t[i]));
       }
       for (size_t i = 0; i < crc.size(); ++i) c16[i] = f32_to_f16((float)(os * crc[i]));
       for (size_t i = 0; i < vrv.size(); ++i) {

@@ -65,17 +65,28 @@ inline int pad_nv(int nv) { return nv <= 64 ? 64 : (nv <= 128 ? 128 : (int)round
 inline long alloc_rows_u(long nb, int nvp) { return round_up(nb * nvp, 256); }
 inline long alloc_rows_v(long nb, int nvp) { return alloc_rows_u(nb, nvp) / nvp + 1; }
 inline long alloc_rows_c(int ncp) { return round_up(ncp, 256); }
-// FP16 orbitals of the mixed second GEMM in K panels: the grid axis is cut
-// into panels of 32 points, and a panel holds 32 consecutive values of every
-// orbital row (N_vp occupied rows, then the conduction rows), so value (row,
-// r) sits at (r / 32) * panel_halves + row * 32 + r % 32.  One K step of a
-// tile is then one contiguous run per 16 rows, where row-major rows of N_rp
-// values would put every row on its own memory page (at 128^3, 4 MB apart:
-// the address translations, not the bytes, limited that layout).
+// FP16 orbitals of the mixed second GEMM: rows of N_rp values (N_vp occupied
+// rows, then the conduction rows), or, once rows are 2 MB or more apart
+// (N_rp >= 2^20), K panels: the grid axis is cut into panels of 32 points,
+// and a panel holds 32 consecutive values of every orbital row, so value
+// (row, r) sits at (r / 32) * panel_halves + row * 32 + r % 32.  One K step
+// of a tile is then one contiguous run per 16 rows, where long rows would put
+// every row on its own memory page (at 128^3, 4 MB apart: the address
+// translations, not the bytes, limited that layout: 488 against 280 ms per
+// launch).  At 64^3 the rows are faster (3.69 against 4.05 ms).
 __host__ __device__ inline long panel_rows(const GemmDims& d) {
   return d.nvp + ((long)d.ncp + 255) / 256 * 256;  // N_vp + alloc_rows_c(N_cp)
 }
 __host__ __device__ inline long panel_halves(const GemmDims& d) { return panel_rows(d) * 32; }
+// halves per K panel of the FP16 orbitals, 0 when they are stored in rows
+__host__ __device__ inline long orb16_panel_halves(const GemmDims& d) {
+  return d.nrp >= (1 << 20) ? panel_halves(d) : 0;
+}
+// index of orbital value (row, r) in the FP16 copy
+__host__ __device__ inline long orb16_index(const GemmDims& d, long row, long r) {
+  const long ph = orb16_panel_halves(d);
+  return ph ? (r >> 5) * ph + row * 32 + (r & 31) : row * d.nrp + r;
+}
 
 // FP64 (plain tiled FMA; reference-quality GPU path).
 int gemm1_f64_vtiles(const GemmDims& d);
@@ -89,7 +100,8 @@ void gemm2_f64(const GemmDims& d, int nb, int splitk, const double* psi_v_t,
 int gemm1_f16s_vtiles(const GemmDims& d);
 void gemm1_f16s(const GemmDims& d, int nb, const f16_t* psi_c_rc, const float* psi_v_rv,
                 const f16_t* u, float* rho_part, hipStream_t st);
-// psi_v_t, psi_c_t: K-panel FP16 orbitals (psi_c_t = panel base + N_vp * 32)
+// psi_v_t, psi_c_t: the FP16 orbitals (psi_c_t = the first conduction value,
+// orb16_index(d, N_vp, 0))
 void gemm2_f16s(const GemmDims& d, int nb, int splitk, const f16_t* psi_v_t,
                 const f16_t* psi_c_t, const f16_t* vpot, float* ypart, hipStream_t st);
 
@@ -108,9 +120,9 @@ int gemm1_f16_vtiles(const GemmDims& d);
 void gemm1_f16(const GemmDims& d, int nb, const f16_t* psi_c_rc, const float* psi_v_rv,
                const f16_t* psi_v_rv16, const f16_t* u, float* rho_part, hipStream_t st);
 // Second GEMM of the mixed path: A = phi_v V_b formed while staging by
-// packed FP16 products (psi_v_t, psi_c_t: K-panel FP16 orbitals scaled by the
-// orbital scale, psi_c_t = panel base + N_vp * 32; vpot: the FP16 potentials
-// [b][N_rp] as the Poisson solve scaled them).
+// packed FP16 products (psi_v_t, psi_c_t: the FP16 orbitals scaled by the
+// orbital scale, psi_c_t = the first conduction value, orb16_index(d, N_vp,
+// 0); vpot: the FP16 potentials [b][N_rp] as the Poisson solve scaled them).
 // bn = block tile width (128 or 256).
 int gemm2_f16_blocks(const GemmDims& d, int nb, int bn);  // blocks per split of the K range
 int gemm2_f64m_blocks(const GemmDims& d, int nb);

@@ -118,6 +118,32 @@ def test_grid_with_128_point_edge(grid):
             assert relerr(got - pr.delta ** 2 * x, dk) <= 2e-2
 
 
+# ------------------------------------------------------------------ 2^20 grid points
+def test_grid_of_2_20_points_k_panels():
+    """128 x 128 x 64 = 2^20 points: the mixed second GEMM reads its FP16
+    orbitals from K panels (rows of N_rp values below 2^20 points), in the
+    MFMA kernel and in the plain-FMA kernel; C x against the oracle."""
+    import paper_2310_20103_amd as G
+    grid = (128, 128, 64)
+    wl = gi.workload("grid24_v8c32", name="grid2p20", seed=71, grid=grid, box=0.375 * grid[0],
+                     n_occ=4, n_emp=12, n_qp_occ=1, n_qp_emp=1, n_lanczos=8, n_omega=9)
+    _say("grid", grid, "(2^20 points), 4+12 orbitals, mixed products from K panels")
+    s = gi.make_system(wl)
+    pr = oracle.Problem(s.phi, s.energies_ev, wl.n_occ, wl.grid, wl.h)
+    lo, hi = oracle.default_interval(pr)
+    x = gi.random_pair_vectors(4, wl.n_vc, seed=72)
+    ref_c = x @ pr.C.T
+    dk = ref_c - pr.delta ** 2 * x
+    with _ctx(s.phi, s.energies_ev, wl, lo, hi, precision="mixed") as c:
+        for kern in (1, 0):
+            c.set_option(G.KEY_KERNELS, kern)
+            got = c.apply_c(torch.tensor(x, device="cuda"), "mixed").cpu().numpy()
+            _say(f"  kernels {kern}: C x {relerr(got, ref_c):.2e}, "
+                 f"K x {relerr(got - pr.delta ** 2 * x, dk):.2e}")
+            assert relerr(got, ref_c) <= 1e-3
+            assert relerr(got - pr.delta ** 2 * x, dk) <= 2e-2
+
+
 # ------------------------------------------------------------------ smooth headline-shaped case
 def test_smooth_headline_shaped_sigma():
     wl = gi.workload("grid32_v32c128", name="grid32_v32c128_smooth", smooth_sigma=1.0)
