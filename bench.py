@@ -485,6 +485,53 @@ def run_isdf_sweep(args):
         "rows": rows}), flush=True)
 
 
+def calibration_copy():
+    """One elementwise kernel that reads 256 MiB and writes 256 MiB (the
+    scale of the FETCH_SIZE and WRITE_SIZE counters)."""
+    import torch
+    src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
+    log("calibration copy of 256 MiB done")
+
+
+def run_density(args):
+    """The first GEMM with its fused row-dot alone (gwl_pair_density, mixed
+    precision) at the headline launch configuration: --block pair vectors per
+    launch on the headline orbitals, --steps launches timed (the cast and the
+    partial sum around it included); with --calibrate-copy first, for counter
+    runs."""
+    import torch
+    import gw_inputs as gi
+    import paper_2310_20103_amd as G
+    if args.calibrate_copy:
+        calibration_copy()
+    wl = gi.workload(args.workload)
+    phi = gi.make_orbitals(wl)
+    eps = gi.make_energies(wl)
+    box = tuple(k * wl.h for k in wl.grid)
+    B = min(args.block, wl.n_vc)
+    ctx = G.Context(phi, eps, wl.n_occ, wl.grid, box, precision="mixed",
+                    poly_degree=wl.poly_degree, reorth="full", block=B)
+    x = torch.tensor(gi.random_pair_vectors(B, wl.n_vc, seed=3), device="cuda")
+    ctx.pair_density(x, "mixed")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.pair_density(x, "mixed")
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / max(args.steps, 1)
+    ctx.close()
+    flop = 2.0 * wl.n_r * wl.n_occ * wl.n_emp * B
+    print(json.dumps({
+        "metric": "first GEMM + row-dot (pair densities), mixed", "unit": "ms per launch",
+        "value": round(dt * 1e3, 4), "n_gpus": 1, "higher_is_better": False, "dtype": "f16",
+        "data": "synthetic", "tflops": round(flop / dt / 1e12, 1),
+        "config": {"workload": wl.name, "block": B, "launches": args.steps}}), flush=True)
+
+
 def run_large(args):
     """The 128^3, 512 + 1,024-orbital configuration (FP32 orbitals, pair dim
     524,288): a steady-state window of the mixed-precision path at B vectors,
@@ -646,7 +693,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--mode", choices=("headline", "uneven", "sched", "adjoint", "isdf",
-                                       "isdf_sweep", "libref",
+                                       "isdf_sweep", "libref", "density",
                                        "large"),
                     default="headline")
     ap.add_argument("--pairs", type=int, default=256, help="uneven mode: pairs measured")
@@ -676,6 +723,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=6,
                     help="Lanczos steps of the oracle sample (timed for cpu_baseline and "
                          "compared with the GPU paths)")
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="launch every kernel eagerly (no HIP graph replay), e.g. under counter "
+                         "collection")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -689,6 +739,8 @@ def main():
         return run_sched(args)
     if args.mode == "isdf_sweep":
         return run_isdf_sweep(args)
+    if args.mode == "density":
+        return run_density(args)
     if args.mode == "uneven":
         return run_uneven(args)
     if args.mode == "adjoint":
@@ -707,13 +759,7 @@ def main():
 
     assert torch.cuda.is_available(), "needs a GPU"
     if args.calibrate_copy:
-        # one elementwise kernel that reads 256 MiB and writes 256 MiB
-        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.mul(src, 1.0, out=dst)
-        torch.cuda.synchronize()
-        del src, dst
-        log("calibration copy of 256 MiB done")
+        calibration_copy()
     wl = gi.workload(args.workload)
     t = time.perf_counter()
     phi = gi.make_orbitals(wl)
@@ -728,6 +774,8 @@ def main():
                     poly_degree=wl.poly_degree, reorth="full", block=B)
     lo, hi = ctx.interval
     log(f"setup {time.perf_counter() - t:.1f}s, interval [{lo:.4g}, {hi:.4g}] Ha^2")
+    if args.no_graphs:
+        ctx.set_option(G.KEY_GRAPHS, 0)
 
     blocks_per_spectrum = (wl.n_orb + B - 1) // B
 

@@ -265,6 +265,17 @@ gwl_status gwl_sigma_c_range_vjp(gwl_ctx* ctx, const int* qp_states, int n_qp, i
 gwl_status gwl_poisson(gwl_ctx* ctx, const void* rho, void* v, int n_fields,
                        int precision);
 
+/* Pair densities of the factored product, the first GEMM with its fused
+ * row-dot (the density of Eqs. 2-3 for a pair vector):
+ *   rho_b(r) = sum_vc phi_v(r) phi_c(r) u_b,vc,  u = Delta^1/2 x
+ * (u = x under the Tamm-Dancoff option), for n_vec pair vectors in batches
+ * of up to 128.  x: device float64 [n_vec][N_v*N_c]; rho: device float64
+ * [n_vec][N_r] (the caller's buffers).  GWL_MIXED_F16: FP16 operands, FP32
+ * accumulation, the operand scales divided out in FP64.  GWL_EUNSUPPORTED
+ * while the ISDF product is switched on. */
+gwl_status gwl_pair_density(gwl_ctx* ctx, const double* x, double* rho, int n_vec,
+                            int precision);
+
 /* y = C x for n_vec pair vectors (Eq. 4), factored on the grid.
  * x, y: device float64 [n_vec][N_v*N_c]. */
 gwl_status gwl_apply_c(gwl_ctx* ctx, const double* x, double* y, int n_vec,

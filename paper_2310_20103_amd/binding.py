@@ -67,6 +67,7 @@ _SIGS = {
     "gwl_sigma_c_range_vjp": (_I, [_P, _P, _I, _I, _I, _P, _I, _D, _I, _P, _P, _P, _P]),
     "gwl_poisson": (_I, [_P, _P, _P, _I, _I]),
     "gwl_apply_c": (_I, [_P, _P, _P, _I, _I]),
+    "gwl_pair_density": (_I, [_P, _P, _P, _I, _I]),
     "gwl_apply_d": (_I, [_P, _P, _P, _I, _I]),
     "gwl_coupling": (_I, [_P, _P, _P, _I, _P]),
     "gwl_sigma_x": (_I, [_P, _P, _I, _P]),
@@ -384,6 +385,16 @@ class Context:
         out = torch.empty_like(rho)
         _sync_torch()
         _check(lib().gwl_poisson(self._h, _dev(rho, dt), _dev(out, dt), int(rho.shape[0]), p))
+        return out
+
+    def pair_density(self, x, precision: str = "fp64"):
+        """rho_b(r) = sum_vc phi_v(r) phi_c(r) (Delta^1/2 x_b)_vc for device
+        pair vectors x [n_vec][N_vc] (float64); float64 [n_vec][N_r]."""
+        import torch
+        out = torch.empty((x.shape[0], self.n_r), dtype=torch.float64, device=x.device)
+        _sync_torch()
+        _check(lib().gwl_pair_density(self._h, _dev(x, torch.float64), _dev(out, torch.float64),
+                                      int(x.shape[0]), PRECISIONS[precision]))
         return out
 
     def apply_c(self, x, precision: str = "fp64"):

@@ -395,6 +395,43 @@ struct gwl_ctx {
   // on the ISDF points (rho partials of the first GEMM summed over v tiles).
   void middle_step(int nb, int prec, int nvt, const void* rho_in, void* v_out);
 
+  // rho <- the first GEMM with its fused row-dot for nb vectors (u already
+  // cast): partial densities [nvt][nb][N_rp] in the working precision (FP64,
+  // or FP32 carrying the scales u_scale * orb16_scale^2); returns nvt.
+  int first_gemm(int nb, int prec) {
+    hipStream_t st = stream;
+    const bool is = isdf_on;
+    const GemmDims& d = kd();
+    int nvt;
+    prof_begin();
+    if (prec == GWL_FP64) {
+      const double* crc = is ? ipsi_c_rc64.p : psi_c_rc64.p;
+      const double* vrv = is ? ipsi_v_rv64.p : psi_v_rv64.p;
+      double* rp = reinterpret_cast<double*>(rho.p);
+      if (fp64_kernel) {
+        gemm1_f64m(d, nb, crc, vrv, u64.p, rp, st);
+        nvt = gemm1_f64m_vtiles(d);
+      } else {
+        gemm1_f64(d, nb, crc, vrv, u64.p, rp, st);
+        nvt = gemm1_f64_vtiles(d);
+      }
+    } else {
+      const f16_t* crc = is ? ipsi_c_rc16.p : psi_c_rc16.p;
+      const f16_t* vrv16 = is ? ipsi_v_rv16.p : psi_v_rv16.p;
+      const float* vrv32 = is ? ipsi_v_rv32.p : psi_v_rv32.p;
+      float* rp = reinterpret_cast<float*>(rho.p);
+      if (fp64_kernel) {
+        gemm1_f16(d, nb, crc, vrv32, vrv16, u16.p, rp, st);
+        nvt = gemm1_f16_vtiles(d);
+      } else {
+        gemm1_f16s(d, nb, crc, vrv32, u16.p, rp, st);
+        nvt = gemm1_f16s_vtiles(d);
+      }
+    }
+    prof_end(0, nb);
+    return nvt;
+  }
+
   // ypart <- second GEMM of K applied to u (u already cast for nb vectors).
   // FP64: the Hartree potentials of the nb densities go to vout64 [nb][N_rp]
   // when given (kept by the adjoint), else to vpot64.
@@ -407,23 +444,11 @@ struct gwl_ctx {
     GWL_CHECK(!is || prec == GWL_FP64, GWL_EUNSUPPORTED, "the ISDF product runs in FP64 only");
     const GemmDims& d = kd();
     if (prec == GWL_FP64) {
-      const double* uu = u64.p;
       double* rp = reinterpret_cast<double*>(rho.p);
       double* vp = vout64 ? vout64 : vpot64.p;
       double* yp = reinterpret_cast<double*>(ypart.p);
-      const double* crc = is ? ipsi_c_rc64.p : psi_c_rc64.p;
-      const double* vrv = is ? ipsi_v_rv64.p : psi_v_rv64.p;
       const double* pt = is ? ipsi_t.p : psi_t.p;
-      int nvt;
-      prof_begin();
-      if (fp64_kernel) {
-        gemm1_f64m(d, nb, crc, vrv, uu, rp, st);
-        nvt = gemm1_f64m_vtiles(d);
-      } else {
-        gemm1_f64(d, nb, crc, vrv, uu, rp, st);
-        nvt = gemm1_f64_vtiles(d);
-      }
-      prof_end(0, nb);
+      const int nvt = first_gemm(nb, prec);
       prof_begin();
       if (is)
         middle_step(nb, prec, nvt, rp, vp);
@@ -440,24 +465,11 @@ struct gwl_ctx {
         gemm2_f64(d, nb, S, pv, pc, vp, yp, st);
       prof_end(1, nb);
     } else {
-      const f16_t* uu = u16.p;
       float* rp = reinterpret_cast<float*>(rho.p);
       float* vp = vpot32.p;
       float* yp = reinterpret_cast<float*>(ypart.p);
-      const f16_t* crc = is ? ipsi_c_rc16.p : psi_c_rc16.p;
-      const f16_t* vrv16 = is ? ipsi_v_rv16.p : psi_v_rv16.p;
-      const float* vrv32 = is ? ipsi_v_rv32.p : psi_v_rv32.p;
       const f16_t* pt = is ? ipsi_t16.p : psi_t16.p;
-      int nvt;
-      prof_begin();
-      if (fp64_kernel) {
-        gemm1_f16(d, nb, crc, vrv32, vrv16, uu, rp, st);
-        nvt = gemm1_f16_vtiles(d);
-      } else {
-        gemm1_f16s(d, nb, crc, vrv32, uu, rp, st);
-        nvt = gemm1_f16s_vtiles(d);
-      }
-      prof_end(0, nb);
+      const int nvt = first_gemm(nb, prec);
       prof_begin();
       if (is)
         middle_step(nb, prec, nvt, rp, vp);

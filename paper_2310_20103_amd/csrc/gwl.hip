@@ -103,6 +103,19 @@ double max_row_norm(gwl_ctx* ctx, const double* x, int n_vec) {
   return m;
 }
 
+// out[b][r] = inv_scale * sum_t part[t][b][r] for r < N_r (partial densities
+// of the first GEMM's v tiles, in its working precision).
+template <typename T>
+__global__ void density_out_kernel(const T* __restrict__ part, int nvt, long tstride, long nrp,
+                                   long nr, double inv_scale, double* __restrict__ out) {
+  const int b = blockIdx.y;
+  for (long r = blockIdx.x * (long)blockDim.x + threadIdx.x; r < nr; r += (long)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int t = 0; t < nvt; ++t) s += (double)part[t * tstride + b * nrp + r];
+    out[b * nr + r] = inv_scale * s;
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -502,6 +515,44 @@ gwl_status gwl_apply_c(gwl_ctx* ctx, const double* x, double* y, int n_vec, int 
     for (int i0 = 0; i0 < n_vec; i0 += chunk) {
       const int nb = std::min(chunk, n_vec - i0);
       ctx->apply_c_batch(nb, x + (size_t)i0 * ctx->nvc, y + (size_t)i0 * ctx->nvc, precision);
+    }
+    GWL_HIP(hipStreamSynchronize(ctx->stream));
+    ctx->prof_flush();
+  });
+}
+
+gwl_status gwl_pair_density(gwl_ctx* ctx, const double* x, double* rho, int n_vec,
+                            int precision) {
+  return guarded([&] {
+    check_ctx(ctx);
+    GWL_CHECK(n_vec >= 0, GWL_EINVAL, "n_vec < 0");
+    if (n_vec == 0) return;
+    GWL_CHECK(x && rho, GWL_EINVAL, "null pointer");
+    check_precision(precision);
+    GWL_CHECK(!ctx->isdf_on, GWL_EUNSUPPORTED,
+              "pair densities live on the grid: switch the ISDF product off");
+    ctx->prof_reset();
+    const int chunk = std::min(n_vec, 128);
+    ctx->ensure_work(chunk, 1, false);
+    if (precision != GWL_FP64) ctx->set_u_bound(max_row_norm(ctx, x, n_vec));
+    const GemmDims& d = ctx->gd;
+    for (int i0 = 0; i0 < n_vec; i0 += chunk) {
+      const int nb = std::min(chunk, n_vec - i0);
+      ctx->cast(nb, x + (size_t)i0 * ctx->nvc, precision);
+      const int nvt = ctx->first_gemm(nb, precision);
+      dim3 grid((unsigned)std::min<long>(1024, (ctx->nr + 255) / 256), (unsigned)nb);
+      double* out = rho + (size_t)i0 * ctx->nr;
+      if (precision == GWL_FP64) {
+        density_out_kernel<double><<<grid, 256, 0, ctx->stream>>>(
+            reinterpret_cast<const double*>(ctx->rho.p), nvt, (long)nb * d.nrp, d.nrp, ctx->nr,
+            1.0, out);
+      } else {
+        const double os = ctx->orb16_scale;
+        density_out_kernel<float><<<grid, 256, 0, ctx->stream>>>(
+            reinterpret_cast<const float*>(ctx->rho.p), nvt, (long)nb * d.nrp, d.nrp, ctx->nr,
+            1.0 / (ctx->u_scale * os * os), out);
+      }
+      GWL_HIP(hipGetLastError());
     }
     GWL_HIP(hipStreamSynchronize(ctx->stream));
     ctx->prof_flush();

@@ -142,6 +142,25 @@ def test_apply_c_mixed(request, which):
     assert relerr(gk, dk) <= 2e-2
 
 
+@pytest.mark.parametrize("which", ["small", "ragged"])
+def test_pair_density(request, which):
+    """The first GEMM with its fused row-dot alone (gwl_pair_density):
+    rho_b = (Delta^1/2 x_b) B with B[(v,c), r] = phi_v(r) phi_c(r), the oracle's
+    pair densities.  Mixed: three FP16 factors per term (unit roundoff 2^-11
+    each), FP32 sums."""
+    from oracle import casida as CA
+    case = request.getfixturevalue(which)
+    ctx = request.getfixturevalue("ctx_" + which)
+    _say("pair density", which)
+    x = gi.random_pair_vectors(5, case.wl.n_vc, seed=8)
+    ref = (np.sqrt(case.pr.delta) * x) @ CA.pair_densities(case.sys.phi, case.wl.n_occ)
+    for prec, tol in (("fp64", 1e-12), ("mixed", 2e-3)):
+        got = ctx.pair_density(torch.tensor(x, device="cuda"), prec).cpu().numpy()
+        _say(f"  {prec}: {relerr(got, ref):.2e}")
+        assert got.shape == ref.shape
+        assert relerr(got, ref) <= tol
+
+
 @pytest.mark.parametrize("n_emp", [100, 150, 260])
 def test_apply_c_conduction_k_steps(n_emp):
     """C x with N_c padded to 128, 192 and 320: the K loops of the GEMMs over
