@@ -126,9 +126,47 @@ __device__ inline void fft_stage(const cplx<T>* __restrict__ in, cplx<T>* __rest
 // Transform nl lines of length n held in LDS at buf0 (line stride ls,
 // element stride es).  Returns the buffer that holds the result.  All
 // threads of the block call it.
+// The same stage with the line length, the line count and the span of the
+// stage known at compile time (index arithmetic by shifts and masks); the
+// first stage's twiddles are all 1 and are skipped.
+template <typename T, int R, int N, int NL, int NS>
+__device__ inline void fft_stage_c(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
+                                   int ls, int es, const cplx<T>* __restrict__ tw) {
+  constexpr int m = N / R;
+  constexpr int tstride = N / (NS * R);
+  constexpr int total = NL * m;
+  for (int bf = threadIdx.x; bf < total; bf += blockDim.x) {
+    const int j = bf / NL;
+    const int line = bf - j * NL;
+    const int jq = j / NS;
+    const int k = j - jq * NS;
+    cplx<T> v[R];
+    const cplx<T>* src = in + line * ls + j * es;
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = src[r * m * es];
+    if constexpr (NS > 1) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[r * k * tstride]);
+    }
+    if constexpr (R == 8) dft8(v);
+    cplx<T>* dst = out + line * ls + (jq * NS * R + k) * es;
+#pragma unroll
+    for (int r = 0; r < R; ++r) dst[r * NS * es] = v[r];
+  }
+}
+
 template <typename T, bool LINE_FAST = false>
 __device__ cplx<T>* fft_lines(cplx<T>* buf0, cplx<T>* buf1, int nl, int n, int ls,
                               const FftPlan& plan, const cplx<T>* __restrict__ tw, int es = 1) {
+  if (LINE_FAST && n == 64 && nl == 64 && plan.nstages == 2 && plan.radix[0] == 8 &&
+      plan.radix[1] == 8) {
+    // 64 lines of 64 points, consecutive threads on consecutive lines
+    fft_stage_c<T, 8, 64, 64, 1>(buf0, buf1, ls, es, tw);
+    __syncthreads();
+    fft_stage_c<T, 8, 64, 64, 8>(buf1, buf0, ls, es, tw);
+    __syncthreads();
+    return buf0;
+  }
   cplx<T>* in = buf0;
   cplx<T>* out = buf1;
   int ns = 1;
@@ -282,13 +320,13 @@ fft_pass_yz(cplx<T>* __restrict__ X, const T* __restrict__ rin, T* __restrict__ 
   __syncthreads();
   cplx<T>* res;
   if (!INVERSE) {
-    res = fft_lines<T>(buf0, buf1, ny, nz, ls, pz, twz_s);
+    res = fft_lines<T, true>(buf0, buf1, ny, nz, ls, pz, twz_s);
     cplx<T>* oth = (res == buf0) ? buf1 : buf0;
     res = fft_lines<T, true>(res, oth, nz, ny, 1, py, twy_s, ls);
   } else {
     res = fft_lines<T, true>(buf0, buf1, nz, ny, 1, py, twy_s, ls);
     cplx<T>* oth = (res == buf0) ? buf1 : buf0;
-    res = fft_lines<T>(res, oth, ny, nz, ls, pz, twz_s);
+    res = fft_lines<T, true>(res, oth, ny, nz, ls, pz, twz_s);
   }
   T sc = 1;
   if (INVERSE && vs.xmax) {
@@ -362,7 +400,7 @@ fft_pass_z(cplx<T>* __restrict__ X, const T* __restrict__ rin, T* __restrict__ r
         put);
   }
   __syncthreads();
-  cplx<T>* res = fft_lines<T>(buf0, buf1, nl, nz, ls, plan, tws);
+  cplx<T>* res = fft_lines<T, true>(buf0, buf1, nl, nz, ls, plan, tws);
   T sc = 1;
   if (INVERSE && vs.xmax) {
     const int e = f16_operand_exp(__uint_as_float(vs.xmax[pair]) * (float)(2 * nyz), vs.pexp);
