@@ -490,6 +490,162 @@ fft_pass_strided(cplx<T>* __restrict__ X, int n, long pstride, long outer_stride
   if (MODE == 2 && xmax) block_max_atomic(mx, &xmax[pair]);
 }
 
+// ---------------------------------------------------------------- 64^3 grids
+// Lines of 64 points transformed in place by a block of 512 threads (one
+// radix-8 butterfly per thread and stage): every thread reads its butterfly's
+// eight inputs, the block synchronises, every thread writes its eight outputs
+// into the same buffer, and the block synchronises again.  The arithmetic is
+// that of the ping-pong stages above (same butterflies, same twiddles, same
+// order), so the results are bitwise the same; one buffer instead of two
+// halves a pass's LDS, and four blocks then share a CU (a yz-plane pass of 64
+// field pairs: 48 us against 100 us with two buffers and 1024 threads).
+constexpr int k64Threads = 512;
+
+template <typename T, int NS>
+__device__ inline void stage64_inplace(cplx<T>* buf, int ls, int es, const cplx<T>* tw) {
+  constexpr int R = 8, N = 64, NL = 64, m = N / R, tstride = N / (NS * R);
+  const int bf = threadIdx.x;
+  const int j = bf / NL, line = bf - j * NL, jq = j / NS, k = j - jq * NS;
+  cplx<T> v[R];
+  const cplx<T>* src = buf + line * ls + j * es;
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = src[r * m * es];
+  if constexpr (NS > 1) {
+#pragma unroll
+    for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[r * k * tstride]);
+  }
+  dft8(v);
+  __syncthreads();
+  cplx<T>* dst = buf + line * ls + (jq * NS * R + k) * es;
+#pragma unroll
+  for (int r = 0; r < R; ++r) dst[r * NS * es] = v[r];
+  __syncthreads();
+}
+
+// 64 lines of 64 points (line l at l * ls, element p at p * es)
+template <typename T>
+__device__ inline void fft64_inplace(cplx<T>* buf, int ls, int es, const cplx<T>* tw) {
+  stage64_inplace<T, 1>(buf, ls, es, tw);
+  stage64_inplace<T, 8>(buf, ls, es, tw);
+}
+
+// The yz-plane pass on a 64^3 grid (as fft_pass_yz, in place): one buffer of
+// 64 rows padded to 65 values, then the y and z twiddles.
+template <typename T, bool INVERSE>
+__global__ void __launch_bounds__(k64Threads)
+fft_pass_yz64(cplx<T>* __restrict__ X, const T* __restrict__ rin, T* __restrict__ rout, int nf,
+              long ld_real, long part_stride, int nparts, long nr,
+              const cplx<T>* __restrict__ twy, const cplx<T>* __restrict__ twz, VScale vs) {
+  constexpr int N = 64, LS = N + 1;
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* twy_s = buf + N * LS;
+  cplx<T>* twz_s = twy_s + N;
+  stage_twiddles(twy_s, twy, N);
+  stage_twiddles(twz_s, twz, N);
+  const int pair = blockIdx.y, x = blockIdx.x;
+  const int f0 = 2 * pair, f1 = 2 * pair + 1;
+  const long base = (long)x * N * N;
+  cplx<T>* Xp = X + (long)pair * nr;
+  const long yrow = (long)N * N;  // spectrum row ky of plane x at (ky N + x) N
+  auto put = [&](int e, cplx<T> v) { buf[(e >> 6) * LS + (e & 63)] = v; };
+  if (!INVERSE) {
+    batched_copy<k64Threads, 8, cplx<T>>(
+        N * N,
+        [&](int e) {
+          T a = 0, b = 0;
+          for (int q = 0; q < nparts; ++q) {
+            const T* src = rin + (long)q * part_stride;
+            a += src[(long)f0 * ld_real + base + e];
+            if (f1 < nf) b += src[(long)f1 * ld_real + base + e];
+          }
+          return cplx<T>{a, b};
+        },
+        put);
+  } else {
+    batched_copy<k64Threads, 8, cplx<T>>(
+        N * N,
+        [&](int e) {
+          const cplx<T> v = Xp[(e >> 6) * yrow + (long)x * N + (e & 63)];
+          return cplx<T>{v.x, -v.y};
+        },
+        put);
+  }
+  __syncthreads();
+  if (!INVERSE) {
+    fft64_inplace(buf, LS, 1, twz_s);  // z lines
+    fft64_inplace(buf, 1, LS, twy_s);  // y lines
+  } else {
+    fft64_inplace(buf, 1, LS, twy_s);
+    fft64_inplace(buf, LS, 1, twz_s);
+  }
+  T sc = 1;
+  if (INVERSE && vs.xmax) {
+    const int e = f16_operand_exp(__uint_as_float(vs.xmax[pair]) * (float)(2 * N * N), vs.pexp);
+    sc = (T)ldexpf(1.0f, e);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      vs.vexp[f0] = e;
+      if (f1 < nf) vs.vexp[f1] = e;
+    }
+  }
+  if (!INVERSE && vs.xmax && blockIdx.x == 0 && threadIdx.x == 0) vs.xmax[pair] = 0u;
+  for (int e = threadIdx.x; e < N * N; e += k64Threads) {
+    const int y = e >> 6, z = e & 63;
+    const cplx<T> v = buf[y * LS + z];
+    if (!INVERSE) {
+      Xp[y * yrow + (long)x * N + z] = v;
+    } else {
+      put_v(rout, vs.out16, (long)f0 * ld_real + base + e, sc * v.x);
+      if (f1 < nf) put_v(rout, vs.out16, (long)f1 * ld_real + base + e, -(sc * v.y));
+    }
+  }
+}
+
+// The x pass on a 64^3 grid (as fft_pass_strided MODE 2 over one whole
+// (x, kz) slab of the y-major spectrum, in place): forward along x, multiply
+// by v(G)/N, inverse, record max(|Re|, |Im|) per field pair.
+template <typename T>
+__global__ void __launch_bounds__(k64Threads)
+fft_pass_x64(cplx<T>* __restrict__ X, long nr, const cplx<T>* __restrict__ tw,
+             const T* __restrict__ g2x, const T* __restrict__ g2y, const T* __restrict__ g2z,
+             T vscale, unsigned* __restrict__ xmax) {
+  constexpr int N = 64, ES = N + 1;
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);  // element p (x) of line l (kz) at p ES + l
+  cplx<T>* tws = buf + N * ES;
+  stage_twiddles(tws, tw, N);
+  const int pair = blockIdx.y, ky = blockIdx.x;
+  cplx<T>* Xp = X + (long)pair * nr + (long)ky * N * N;  // the slab is contiguous
+  batched_copy<k64Threads, 8, cplx<T>>(
+      N * N, [&](int e) { return Xp[e]; },
+      [&](int e, cplx<T> v) { buf[(e >> 6) * ES + (e & 63)] = v; });
+  __syncthreads();
+  fft64_inplace(buf, 1, ES, tws);
+  const T gy = g2y[ky];
+  for (int e = threadIdx.x; e < N * N; e += k64Threads) {
+    const int p = e >> 6, l = e & 63;
+    const T g2 = g2x[p] + gy + g2z[l];
+    const T k = (g2 > (T)0) ? vscale / g2 : (T)0;
+    const cplx<T> v = buf[p * ES + l];
+    buf[p * ES + l] = {k * v.x, -k * v.y};  // conjugated for the inverse transform
+  }
+  __syncthreads();
+  fft64_inplace(buf, 1, ES, tws);
+  T mx = 0;
+  for (int e = threadIdx.x; e < N * N; e += k64Threads) {
+    cplx<T> v = buf[(e >> 6) * ES + (e & 63)];
+    v.y = -v.y;
+    Xp[e] = v;
+    mx = fmax(mx, fmax(fabs(v.x), fabs(v.y)));
+  }
+  if (xmax) block_max_atomic(mx, &xmax[pair]);
+}
+
+template <typename T>
+constexpr size_t lds_yz64() { return (64 * 65 + 128) * sizeof(cplx<T>); }
+template <typename T>
+constexpr size_t lds_x64() { return (64 * 65 + 64) * sizeof(cplx<T>); }
+
 // LDS of the yz-plane pass (two planes); larger planes take the five-pass route
 constexpr size_t kYzLdsMax = 80 * 1024;
 
@@ -522,6 +678,12 @@ void poisson_prepare_device() {
   GWL_HIP(hipFuncSetAttribute(
       reinterpret_cast<const void*>(&fft_pass_strided<double, 2, kYzThreads>),
       hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+  GWL_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&fft_pass_yz64<double, false>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+  GWL_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&fft_pass_yz64<double, true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+  GWL_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&fft_pass_x64<double>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lim));
 }
 
 FftPlan make_plan(int n) {
@@ -557,6 +719,19 @@ void poisson_launch(const PoissonGeom<T>& g, const T* rin, long ld_in, long part
   if (lpb < 2) lpb = 2;
   if (lpb > g.nz) lpb = g.nz;
   const int nzb = ceil_div(g.nz, lpb);
+  // 64^3 (and the twiddle tables of a 64-point plan): the in-place passes
+  if (g.nx == 64 && g.ny == 64 && g.nz == 64 && g.px.nstages == 2 && g.px.radix[0] == 8 &&
+      g.px.radix[1] == 8) {
+    dim3 grid(64, npairs);
+    fft_pass_yz64<T, false><<<grid, k64Threads, lds_yz64<T>(), st>>>(
+        scratch, rin, nullptr, nf, ld_in, part_stride, nparts, nr, g.twy, g.twz, vs);
+    fft_pass_x64<T><<<grid, k64Threads, lds_x64<T>(), st>>>(scratch, nr, g.twx, g.g2x, g.g2y,
+                                                            g.g2z, g.vscale, xm);
+    fft_pass_yz64<T, true><<<grid, k64Threads, lds_yz64<T>(), st>>>(
+        scratch, nullptr, rout, nf, ld_out, 0, 1, nr, g.twy, g.twz, vs);
+    GWL_HIP(hipGetLastError());
+    return;
+  }
   // Three HBM round trips when a yz plane and its ping-pong copy fit in LDS:
   // yz forward (+ pack), x forward / kernel / x inverse over (x, kz) slabs of
   // the y-major spectrum, yz inverse (+ unpack)

@@ -65,6 +65,22 @@ def full():
     ctx.close()
 
 
+def test_poisson_full_size(full):
+    """The 64^3 in-place FFT passes against the oracle's Poisson solve, FP64 and
+    FP32, with an odd field count (the last complex field carries one real
+    field)."""
+    wl, phi, eps, qp, ctx, pr = full
+    _say("full size Poisson, 7 fields")
+    f = gi.random_fields(7, wl.n_r, seed=21)
+    ref = oracle.poisson.poisson(f, wl.grid, wl.h)
+    v64 = ctx.poisson(torch.tensor(f, device="cuda"), "fp64").cpu().numpy()
+    v32 = ctx.poisson(torch.tensor(f, dtype=torch.float32, device="cuda"),
+                      "mixed").double().cpu().numpy()
+    _say(f"  fp64 {relerr(v64, ref):.2e}, fp32 {relerr(v32, ref):.2e}")
+    assert relerr(v64, ref) <= 1e-12
+    assert relerr(v32, ref) <= 2e-6
+
+
 def test_apply_c_full_size(full):
     wl, phi, eps, qp, ctx, pr = full
     _say("full size C x, 128 vectors, fp64 and mixed")
