@@ -46,18 +46,25 @@ __device__ inline int xcd_remap(int bid, int total) {
 
 // Tile map of the first GEMM (mt x nt tiles, A = pair vectors is the small
 // operand, B = orbitals the large one).  With mt >= 8 each XCD owns a fixed
-// eighth of the M tiles, so its slice of A stays in that XCD's L2 while the
-// orbital tiles stream past once per XCD; with mt < 8 each XCD owns an eighth
-// of the N tiles instead.  Returns false for the padding blocks of the grid.
+// eighth of the M tiles and walks them in chunks of ch tiles, all N tiles per
+// chunk, so the chunk's slice of A (ch tiles of tile_bytes, sized to 2 MB)
+// stays in that XCD's 4 MB L2 while the orbital tiles stream past once per
+// chunk; with mt < 8 each XCD owns an eighth of the N tiles instead.  Returns
+// false for the padding blocks of the grid.
 __host__ __device__ inline int gemm1_grid(int mt, int nt) {
   return mt >= 8 ? 8 * ((mt + 7) / 8) * nt : 8 * ((nt + 7) / 8) * mt;
 }
-__device__ inline bool gemm1_tile(int bid, int mt, int nt, int& mi, int& ni) {
+__device__ inline bool gemm1_tile(int bid, int mt, int nt, long tile_bytes, int& mi, int& ni) {
   const int x = bid & 7, loc = bid >> 3;
   if (mt >= 8) {
     const int mpx = (mt + 7) / 8;
-    mi = x * mpx + loc % mpx;
-    ni = loc / mpx;
+    long c2 = (2l << 20) / tile_bytes;
+    const int ch = (int)(c2 < 1 ? 1 : (c2 > mpx ? mpx : c2));
+    const int c = loc / (ch * nt);           // chunk (every full chunk holds ch * nt blocks)
+    const int within = loc - c * ch * nt;
+    const int sz = min(ch, mpx - c * ch);    // tiles of this chunk
+    mi = x * mpx + c * ch + within % sz;
+    ni = within / sz;
   } else {
     const int npx = (nt + 7) / 8;
     mi = loc % mt;
@@ -165,7 +172,7 @@ gemm1_f64m_kernel(GemmDims d, int M, int nb, const double* __restrict__ psi_c_rc
   __shared__ double Bs[DN][DLD];
   const int mt = (M + DM - 1) / DM, nt = d.nrp / DN;
   int mi, ni;
-  if (!gemm1_tile(blockIdx.x, mt, nt, mi, ni)) return;
+  if (!gemm1_tile(blockIdx.x, mt, nt, (long)DM * d.ncp * 8, mi, ni)) return;
   const int m0 = mi * DM, n0 = ni * DN;
   d4 acc[4][4];
 #pragma unroll
@@ -550,7 +557,7 @@ __device__ inline void gemm1_f16_body(const GemmDims& d, int M, int nb,
   const int mt = (M + HM - 1) / HM, nt = d.nrp / BN;
   const int ng = (nt + G1_TILES - 1) / G1_TILES;
   int mi, gi;
-  if (!gemm1_tile(blockIdx.x, mt, ng, mi, gi)) return;
+  if (!gemm1_tile(blockIdx.x, mt, ng, (long)HM * d.ncp * 2, mi, gi)) return;
   const int m0 = mi * HM;
   const int nt0 = gi * G1_TILES, nt1 = min(nt, nt0 + G1_TILES);
   const int t = threadIdx.x, l = t & 63, w = t >> 6;
