@@ -532,6 +532,41 @@ def run_density(args):
         "config": {"workload": wl.name, "block": B, "launches": args.steps}}), flush=True)
 
 
+def run_potential(args):
+    """The second GEMM alone (gwl_potential_product, mixed precision) at the
+    headline launch configuration: --block seeded potentials per launch on the
+    headline orbitals, --steps launches timed (the FP16 rounding of the
+    potentials and the partial sum around it included); with --calibrate-copy
+    first, for counter runs."""
+    import torch
+    import gw_inputs as gi
+    import paper_2310_20103_amd as G
+    if args.calibrate_copy:
+        calibration_copy()
+    wl = gi.workload(args.workload)
+    phi = gi.make_orbitals(wl)
+    eps = gi.make_energies(wl)
+    box = tuple(k * wl.h for k in wl.grid)
+    B = min(args.block, wl.n_vc)
+    ctx = G.Context(phi, eps, wl.n_occ, wl.grid, box, precision="mixed",
+                    poly_degree=wl.poly_degree, reorth="full", block=B)
+    v = torch.tensor(np.random.default_rng(4).standard_normal((B, wl.n_r)), device="cuda")
+    ctx.potential_product(v, "mixed")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.potential_product(v, "mixed")
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / max(args.steps, 1)
+    ctx.close()
+    flop = 2.0 * wl.n_r * wl.n_occ * wl.n_emp * B
+    print(json.dumps({
+        "metric": "second GEMM (potential product), mixed", "unit": "ms per launch",
+        "value": round(dt * 1e3, 4), "n_gpus": 1, "higher_is_better": False, "dtype": "f16",
+        "data": "synthetic", "tflops": round(flop / dt / 1e12, 1),
+        "config": {"workload": wl.name, "block": B, "launches": args.steps}}), flush=True)
+
+
 def run_large(args):
     """The 128^3, 512 + 1,024-orbital configuration (FP32 orbitals, pair dim
     524,288): a steady-state window of the mixed-precision path at B vectors,
@@ -693,7 +728,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--mode", choices=("headline", "uneven", "sched", "adjoint", "isdf",
-                                       "isdf_sweep", "libref", "density",
+                                       "isdf_sweep", "libref", "density", "potential",
                                        "large"),
                     default="headline")
     ap.add_argument("--pairs", type=int, default=256, help="uneven mode: pairs measured")
@@ -741,6 +776,8 @@ def main():
         return run_isdf_sweep(args)
     if args.mode == "density":
         return run_density(args)
+    if args.mode == "potential":
+        return run_potential(args)
     if args.mode == "uneven":
         return run_uneven(args)
     if args.mode == "adjoint":

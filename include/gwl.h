@@ -276,6 +276,18 @@ gwl_status gwl_poisson(gwl_ctx* ctx, const void* rho, void* v, int n_fields,
 gwl_status gwl_pair_density(gwl_ctx* ctx, const double* x, double* rho, int n_vec,
                             int precision);
 
+/* The second GEMM alone (the back-projection of Eqs. 2-3): for n_vec
+ * potentials V_b on the grid,
+ *   y_b,vc = dV sum_r phi_v(r) V_b(r) phi_c(r)
+ * (with V_b the Hartree potential of a pair density this is (K u_b)_vc), in
+ * batches of up to 128.  v: device float64 [n_vec][N_r]; y: device float64
+ * [n_vec][N_v*N_c] (the caller's buffers).  GWL_MIXED_F16: each V_b is scaled
+ * by the power of two the Poisson solve would give it and rounded to FP16,
+ * phi_v V_b is formed in FP16, sums in FP32, scales divided out in FP64.
+ * GWL_EUNSUPPORTED while the ISDF product is switched on. */
+gwl_status gwl_potential_product(gwl_ctx* ctx, const double* v, double* y, int n_vec,
+                                 int precision);
+
 /* y = C x for n_vec pair vectors (Eq. 4), factored on the grid.
  * x, y: device float64 [n_vec][N_v*N_c]. */
 gwl_status gwl_apply_c(gwl_ctx* ctx, const double* x, double* y, int n_vec,

@@ -68,6 +68,7 @@ _SIGS = {
     "gwl_poisson": (_I, [_P, _P, _P, _I, _I]),
     "gwl_apply_c": (_I, [_P, _P, _P, _I, _I]),
     "gwl_pair_density": (_I, [_P, _P, _P, _I, _I]),
+    "gwl_potential_product": (_I, [_P, _P, _P, _I, _I]),
     "gwl_apply_d": (_I, [_P, _P, _P, _I, _I]),
     "gwl_coupling": (_I, [_P, _P, _P, _I, _P]),
     "gwl_sigma_x": (_I, [_P, _P, _I, _P]),
@@ -395,6 +396,17 @@ class Context:
         _sync_torch()
         _check(lib().gwl_pair_density(self._h, _dev(x, torch.float64), _dev(out, torch.float64),
                                       int(x.shape[0]), PRECISIONS[precision]))
+        return out
+
+    def potential_product(self, v, precision: str = "fp64"):
+        """y_b,vc = dV sum_r phi_v(r) V_b(r) phi_c(r) for device potentials
+        v [n_vec][N_r] (float64); float64 [n_vec][N_vc]."""
+        import torch
+        out = torch.empty((v.shape[0], self.n_vc), dtype=torch.float64, device=v.device)
+        _sync_torch()
+        _check(lib().gwl_potential_product(self._h, _dev(v, torch.float64),
+                                           _dev(out, torch.float64), int(v.shape[0]),
+                                           PRECISIONS[precision]))
         return out
 
     def apply_c(self, x, precision: str = "fp64"):

@@ -103,6 +103,57 @@ double max_row_norm(gwl_ctx* ctx, const double* x, int n_vec) {
   return m;
 }
 
+// Potentials of the caller into the padded [nb][N_rp] rows of the FP64 product
+// (pads zero).
+__global__ void pot_pad_kernel(const double* __restrict__ v, long nr, long nrp,
+                               double* __restrict__ out) {
+  const int b = blockIdx.y;
+  for (long r = blockIdx.x * (long)blockDim.x + threadIdx.x; r < nrp; r += (long)gridDim.x * blockDim.x)
+    out[b * nrp + r] = r < nr ? v[b * nr + r] : 0.0;
+}
+
+// Mixed product: the power of two of each potential (from its largest |V|, as
+// the Poisson solve chooses it) and the FP16 rows V 2^e (pads zero).  One
+// block per potential for the maximum (fixed order).
+__global__ void pot16_exp_kernel(const double* __restrict__ v, long nr, int pexp,
+                                 int* __restrict__ vexp) {
+  __shared__ float sh[256];
+  const int b = blockIdx.x;
+  float m = 0.0f;
+  for (long r = threadIdx.x; r < nr; r += blockDim.x) m = fmaxf(m, (float)fabs(v[b * nr + r]));
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + st]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) vexp[b] = f16_operand_exp(sh[0], pexp);
+}
+__global__ void pot16_kernel(const double* __restrict__ v, long nr, long nrp,
+                             const int* __restrict__ vexp, f16_t* __restrict__ out) {
+  const int b = blockIdx.y;
+  const float sc = ldexpf(1.0f, vexp[b]);
+  for (long r = blockIdx.x * (long)blockDim.x + threadIdx.x; r < nrp; r += (long)gridDim.x * blockDim.x)
+    out[b * nrp + r] = f32_to_f16(r < nr ? (float)v[b * nr + r] * sc : 0.0f);
+}
+
+// y[b][vc] = scale 2^-vexp[b] sum_s ypart[s][b][v][c] (vexp optional).
+template <typename Y>
+__global__ void potprod_finish_kernel(int nv, int nc, int nvp, int ncp, int nb, int splitk,
+                                      const Y* __restrict__ ypart, const int* __restrict__ vexp,
+                                      double scale, double* __restrict__ y) {
+  const int b = blockIdx.y;
+  const long nvc = (long)nv * nc, stride_s = (long)nb * nvp * ncp;
+  const double sc = vexp ? ldexp(scale, -vexp[b]) : scale;
+  const Y* yb = ypart + (long)b * nvp * ncp;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < nvc; e += (long)gridDim.x * blockDim.x) {
+    const int v = (int)(e / nc), c = (int)(e - (long)v * nc);
+    double t = 0.0;
+    for (int s = 0; s < splitk; ++s) t += (double)yb[s * stride_s + (long)v * ncp + c];
+    y[b * nvc + e] = sc * t;
+  }
+}
+
 // out[b][r] = inv_scale * sum_t part[t][b][r] for r < N_r (partial densities
 // of the first GEMM's v tiles, in its working precision).
 template <typename T>
@@ -556,6 +607,63 @@ gwl_status gwl_pair_density(gwl_ctx* ctx, const double* x, double* rho, int n_ve
     }
     GWL_HIP(hipStreamSynchronize(ctx->stream));
     ctx->prof_flush();
+  });
+}
+
+gwl_status gwl_potential_product(gwl_ctx* ctx, const double* v, double* y, int n_vec,
+                                 int precision) {
+  return guarded([&] {
+    check_ctx(ctx);
+    GWL_CHECK(n_vec >= 0, GWL_EINVAL, "n_vec < 0");
+    if (n_vec == 0) return;
+    GWL_CHECK(v && y, GWL_EINVAL, "null pointer");
+    check_precision(precision);
+    GWL_CHECK(!ctx->isdf_on, GWL_EUNSUPPORTED,
+              "potentials live on the grid: switch the ISDF product off");
+    gwl_ctx& c = *ctx;
+    c.prof_reset();
+    const int chunk = std::min(n_vec, 128);
+    c.ensure_work(chunk, 1, false);
+    const GemmDims& d = c.gd;
+    hipStream_t st = c.stream;
+    for (int i0 = 0; i0 < n_vec; i0 += chunk) {
+      const int nb = std::min(chunk, n_vec - i0);
+      const double* vb = v + (size_t)i0 * c.nr;
+      double* yb = y + (size_t)i0 * c.nvc;
+      const int S = c.auto_splitk(nb, precision);
+      dim3 gr((unsigned)std::min<long>(1024, (d.nrp + 255) / 256), (unsigned)nb);
+      dim3 gy((unsigned)std::min<long>(1024, (c.nvc + 255) / 256), (unsigned)nb);
+      c.prof_begin();
+      if (precision == GWL_FP64) {
+        pot_pad_kernel<<<gr, 256, 0, st>>>(vb, c.nr, d.nrp, c.vpot64.p);
+        const double* pv = c.psi_t.p;
+        const double* pc = c.psi_t.p + (size_t)d.nvp * d.nrp;
+        double* yp = reinterpret_cast<double*>(c.ypart.p);
+        if (c.fp64_kernel)
+          gemm2_f64m(d, nb, S, pv, pc, c.vpot64.p, yp, st);
+        else
+          gemm2_f64(d, nb, S, pv, pc, c.vpot64.p, yp, st);
+        potprod_finish_kernel<double><<<gy, 256, 0, st>>>(c.nv, c.nc, d.nvp, d.ncp, nb, S, yp,
+                                                          nullptr, c.dv, yb);
+      } else {
+        pot16_exp_kernel<<<nb, 256, 0, st>>>(vb, c.nr, c.pv16_exp, c.vexp32.p);
+        pot16_kernel<<<gr, 256, 0, st>>>(vb, c.nr, d.nrp, c.vexp32.p, c.vpot16.p);
+        const f16_t* pt = c.psi_t16.p;
+        const f16_t* pc = pt + orb16_index(d, d.nvp, 0);
+        float* yp = reinterpret_cast<float*>(c.ypart.p);
+        if (c.fp64_kernel)
+          gemm2_f16(d, nb, c.bf16_tile, S, pt, pc, c.vpot16.p, yp, st);
+        else
+          gemm2_f16s(d, nb, S, pt, pc, c.vpot16.p, yp, st);
+        const double os = c.orb16_scale;
+        potprod_finish_kernel<float><<<gy, 256, 0, st>>>(c.nv, c.nc, d.nvp, d.ncp, nb, S, yp,
+                                                         c.vexp32.p, c.dv / (os * os), yb);
+      }
+      c.prof_end(1, nb);
+      GWL_HIP(hipGetLastError());
+    }
+    GWL_HIP(hipStreamSynchronize(st));
+    c.prof_flush();
   });
 }
 

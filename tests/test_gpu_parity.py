@@ -161,6 +161,35 @@ def test_pair_density(request, which):
         assert relerr(got, ref) <= tol
 
 
+@pytest.mark.parametrize("which", ["small", "ragged"])
+def test_potential_product(request, which):
+    """The second GEMM alone (gwl_potential_product) on seeded potentials:
+    y_b,vc = dV sum_r phi_v(r) V_b(r) phi_c(r); and, with V_b the oracle's
+    Hartree potential of the pair density of x_b, y_b = K x_b.  Mixed: FP16
+    phi_v, phi_c and V_b, their product phi_v V_b rounded to FP16 again, FP32
+    sums."""
+    from oracle import casida as CA
+    from oracle import poisson as PO
+    case = request.getfixturevalue(which)
+    ctx = request.getfixturevalue("ctx_" + which)
+    _say("potential product", which)
+    phi, nv = case.sys.phi, case.wl.n_occ
+    dv = case.wl.h ** 3
+    pv, pc = phi[:nv], phi[nv:]
+    v = np.random.default_rng(21).standard_normal((3, phi.shape[1]))
+    x = gi.random_pair_vectors(2, case.wl.n_vc, seed=22)
+    rho = x @ CA.pair_densities(phi, nv)
+    v = np.concatenate([v, PO.poisson(rho, case.wl.grid, case.wl.h)])
+    ref = dv * np.einsum("vr,br,cr->bvc", pv, v, pc).reshape(len(v), -1)
+    kx = CA.apply_k(phi, nv, case.wl.grid, case.wl.h, x)
+    for prec, tol in (("fp64", 1e-12), ("mixed", 3e-3)):
+        got = ctx.potential_product(torch.tensor(v, device="cuda"), prec).cpu().numpy()
+        _say(f"  {prec}: {relerr(got, ref):.2e}  K x: {relerr(got[3:], kx):.2e}")
+        assert got.shape == ref.shape
+        assert relerr(got, ref) <= tol
+        assert relerr(got[3:], kx) <= tol
+
+
 @pytest.mark.parametrize("n_emp", [100, 150, 260])
 def test_apply_c_conduction_k_steps(n_emp):
     """C x with N_c padded to 128, 192 and 320: the K loops of the GEMMs over
