@@ -250,6 +250,27 @@ def run_adjoint(args):
     iterates = "stored" if ctx.query(G.KEY_ADJOINT_STORED) == 1 else "recomputed"
     log(f"adjoint: vjp {t_vjp:.1f}s, iterates {iterates}")
     same = float(np.max(np.abs(sig2 - sig)) / max(np.max(np.abs(sig)), 1e-300))
+    # the split form: forward keeping checkpoints, then the backward alone
+    split = None
+    if not args.adjoint_store:
+        go_one = go.cpu().numpy()
+        del go
+        t = time.perf_counter()
+        sig3 = ctx.sigma_c_vjp_forward(m, omega, wl.eta, L, n_range=(0, n_end))
+        t_sf = time.perf_counter() - t
+        log(f"adjoint: split forward {t_sf:.1f}s")
+        t = time.perf_counter()
+        ge3, go3 = ctx.sigma_c_vjp_backward(cot)
+        torch.cuda.synchronize()
+        t_sb = time.perf_counter() - t
+        log(f"adjoint: split backward {t_sb:.1f}s")
+        split = {"forward_s": round(t_sf, 3), "backward_s": round(t_sb, 3),
+                 "backward_over_forward": round(t_sb / t_fwd, 3),
+                 "forward_plus_backward_over_forward": round((t_sf + t_sb) / t_fwd, 3),
+                 "equals_one_call": bool(np.array_equal(sig3, sig2) and np.array_equal(ge3, ge)
+                                         and np.array_equal(go3.cpu().numpy(), go_one))}
+        go = torch.from_numpy(go_one)
+        del go3
     ctx.set_reorth("full")
     t = time.perf_counter()
     ctx.sigma_c_range(m, 0, n_end, omega, wl.eta, L)
@@ -284,7 +305,7 @@ def run_adjoint(args):
                    "iterates": iterates},
         "forward_s": round(t_fwd, 3), "vjp_s_incl_forward": round(t_vjp, 3),
         "forward_full_reorth_s": round(t_full, 3),
-        "vjp_sigma_vs_forward_rel": same,
+        "vjp_sigma_vs_forward_rel": same, "split": split,
         "fd_check": {"step": h, "energies": {"fd": fd_e, "vjp": an_e,
                                              "rel": abs(fd_e - an_e) / max(abs(fd_e), 1e-300)},
                      "orbitals": {"fd": fd_p, "vjp": an_p,

@@ -232,8 +232,9 @@ gwl_status gwl_sigma_from_coeffs_noalloc(gwl_ctx* ctx, const int* n_idx, int n_p
  * product and the Hartree potentials formed inside it.  By default the
  * forward keeps only (q_{k-1}, q_k) every ceil(sqrt(L)) steps and the
  * backward recomputes one such segment at a time (one more p_g(C) product
- * per step); with GWL_KEY_ADJOINT_STORE = 1 the forward keeps the whole run
- * when it fits in GWL_ADJOINT_STORE_MAX.  The orbital gradient is contracted
+ * per step), except the last, whose iterates the forward keeps as it ends;
+ * with GWL_KEY_ADJOINT_STORE = 1 the forward keeps the whole run when it fits
+ * in GWL_ADJOINT_STORE_MAX.  The orbital gradient is contracted
  * step by step from the outer products of the reverse sweep with the FP64
  * matrix-core kernel (no N_vc x N_vc matrix is formed); device memory
  * beyond the context's is about
@@ -256,6 +257,33 @@ gwl_status gwl_sigma_c_range_vjp(gwl_ctx* ctx, const int* qp_states, int n_qp, i
                                  int n_end, const double* omega_ev, int n_omega, double eta_ev,
                                  int n_lanczos, const double* grad_sigma, double* sigma_out,
                                  double* grad_energies, void* grad_orbitals);
+
+/* The same derivative in two calls, for callers that evaluate Sigma first
+ * and differentiate later (an autograd forward and backward).
+ * gwl_sigma_c_vjp_forward runs the forward of gwl_sigma_c_range_vjp for
+ * qp_states x [n_begin, n_end) (arguments as there; [0, n_orb) is the full
+ * sum), writes the forward Sigma to sigma_out (host [n_qp][n_omega][2], eV,
+ * required) and keeps in the context, per block of start vectors, the
+ * recurrence's checkpoints (q_{k-1}, q_k and the slot state every
+ * ceil(sqrt(L)) steps), the start vectors P_nm and the potentials
+ * V[phi_n phi_m], and per pair the Lanczos coefficients:
+ *   (2 ceil(L / ceil(sqrt(L))) + 1) P N_vc + P N_r + 2 P L  doubles
+ * for P = n_qp (n_end - n_begin) start vectors (GWL_KEY_ADJOINT_STORE does
+ * not apply).  The state is kept until the next gwl_sigma_c_vjp_forward on
+ * the context or gwl_destroy.
+ * gwl_sigma_c_vjp_backward then returns grad_energies and grad_orbitals for
+ * the cotangent grad_sigma ([n_qp][n_omega][2], host) exactly as
+ * gwl_sigma_c_range_vjp would with the same arguments (the same kernels in
+ * the same order), recomputing every segment from the kept checkpoints
+ * instead of running the forward again; it may be called several times.
+ * Errors: as gwl_sigma_c_range_vjp; gwl_sigma_c_vjp_backward returns
+ * GWL_EINVAL when no forward was kept, or when the interval, polynomial
+ * degree or block size of the context changed since. */
+gwl_status gwl_sigma_c_vjp_forward(gwl_ctx* ctx, const int* qp_states, int n_qp, int n_begin,
+                                   int n_end, const double* omega_ev, int n_omega, double eta_ev,
+                                   int n_lanczos, double* sigma_out);
+gwl_status gwl_sigma_c_vjp_backward(gwl_ctx* ctx, const double* grad_sigma,
+                                    double* grad_energies, void* grad_orbitals);
 
 /* ---- component entry points (the steps of the path, for parity checks) ---- */
 

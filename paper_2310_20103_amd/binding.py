@@ -64,6 +64,8 @@ _SIGS = {
     "gwl_sigma_from_coeffs": (_I, [_P, _P, _I, _P, _P, _P, _P, _I, _P, _I, _D, _P]),
     "gwl_sigma_from_coeffs_noalloc": (_I, [_P, _P, _I, _P, _P, _P, _P, _I, _P, _I, _D, _P]),
     "gwl_sigma_c_vjp": (_I, [_P, _P, _I, _P, _I, _D, _I, _P, _P, _P, _P]),
+    "gwl_sigma_c_vjp_forward": (_I, [_P, _P, _I, _I, _I, _P, _I, _D, _I, _P]),
+    "gwl_sigma_c_vjp_backward": (_I, [_P, _P, _P, _P]),
     "gwl_sigma_c_range_vjp": (_I, [_P, _P, _I, _I, _I, _P, _I, _D, _I, _P, _P, _P, _P]),
     "gwl_poisson": (_I, [_P, _P, _P, _I, _I]),
     "gwl_apply_c": (_I, [_P, _P, _P, _I, _I]),
@@ -339,6 +341,37 @@ class Context:
                                                float(eta_ev), int(n_lanczos), _ptr(g2),
                                                _ptr(sig), _ptr(ge), _dev(go, gdt)))
         return sig[..., 0] + 1j * sig[..., 1], ge, go
+
+    def sigma_c_vjp_forward(self, qp_states, omega_ev, eta_ev: float, n_lanczos: int,
+                            n_range=None):
+        """The forward of sigma_c_vjp alone: returns Sigma [n_qp, n_omega]
+        complex eV and keeps the recurrence's checkpoints in the context for
+        sigma_c_vjp_backward."""
+        q = _i32(qp_states)
+        om = _f64(omega_ev)
+        n0, n1 = (0, self.n_orb) if n_range is None else (int(n_range[0]), int(n_range[1]))
+        sig = np.zeros((len(q), len(om), 2))
+        _sync_torch()
+        _check(lib().gwl_sigma_c_vjp_forward(self._h, _ptr(q), len(q), n0, n1, _ptr(om),
+                                             len(om), float(eta_ev), int(n_lanczos), _ptr(sig)))
+        self._vjp_shape = (len(q), len(om))
+        return sig[..., 0] + 1j * sig[..., 1]
+
+    def sigma_c_vjp_backward(self, grad_sigma, device="cuda"):
+        """(dl/d energies [n_orb] per eV, dl/d orbitals [n_orb, N_r] on the
+        device) for the cotangent grad_sigma of the last sigma_c_vjp_forward."""
+        import torch
+        G = np.asarray(grad_sigma, dtype=np.complex128)
+        shape = getattr(self, "_vjp_shape", None)
+        if shape is not None:  # (without a saved forward the library reports the error)
+            G = G.reshape(shape)
+        g2 = np.ascontiguousarray(np.stack([G.real, G.imag], axis=-1))
+        ge = np.zeros(self.n_orb)
+        gdt = torch.float64 if self.orb_itemsize == 8 else torch.float32
+        go = torch.empty((self.n_orb, self.n_r), dtype=gdt, device=device)
+        _sync_torch()
+        _check(lib().gwl_sigma_c_vjp_backward(self._h, _ptr(g2), _ptr(ge), _dev(go, gdt)))
+        return ge, go
 
     def lanczos_pairs(self, m_idx, n_idx, lengths, ld: Optional[int] = None):
         """(alpha [P, ld], beta [P, ld], norm2 [P], out_len [P]) in hartree units."""

@@ -140,6 +140,7 @@ struct gwl_ctx {
   int adjoint_store = 0;     // 1: the adjoint keeps the forward's iterates when they fit
   int orb_dtype = 8;         // 8 = FP64 orbitals were given, 4 = FP32
   int adjoint_stored = -1;   // what the last adjoint call did (-1: no call yet)
+  std::shared_ptr<void> vjp_saved;  // state of the last gwl_sigma_c_vjp_forward
   bool poly_hi_auto = false;  // the interval's upper end is estimated (re-done for ISDF)
   double hi_resid = 0.0;      // residual bound of the last estimate's largest Ritz value
   DevBuf<int> ivbad;          // per-run flags of the interval check

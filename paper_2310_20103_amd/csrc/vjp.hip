@@ -8,7 +8,16 @@
 // iterates t_0..t_g of p_g(C) q_k, their coupling parts K Delta^1/2 t_j, the
 // product w_k and the Hartree potentials V[rho(Delta^1/2 t_j)] that the FFT
 // Poisson solve forms inside each C-product.  With GWL_KEY_ADJOINT_STORE the
-// whole run is one segment kept by the forward itself when it fits.
+// whole run is one segment kept by the forward itself when it fits; else the
+// forward keeps the last segment's iterates itself (it ends there), so the
+// backward recomputes every segment but the last.
+//
+// Split form (gwl_sigma_c_vjp_forward, then gwl_sigma_c_vjp_backward): the
+// forward runs every block of start vectors, returns Sigma and keeps each
+// block's checkpoints, start vectors, V[phi_n phi_m] and Lanczos coefficients
+// in the context; the backward takes them up for any cotangent without
+// running the forward again (an autograd forward and backward then run the
+// recurrence once forward and once in the recompute).
 //
 // Backward, per block of start vectors: continued-fraction adjoint; then for
 // each step k (last first) the reverse Lanczos step gives w_bar_k, and the
@@ -26,26 +35,63 @@ using namespace gwl;
 
 namespace {
 
-gwl_status vjp_range(gwl_ctx* ctx, const int* qp_states, int n_qp, int n_begin, int n_end,
-                     const double* omega_ev, int n_omega, double eta_ev, int n_lanczos,
-                     const double* grad_sigma, double* sigma_out, double* grad_energies,
-                     void* grad_orbitals) {
+enum class VjpMode { Full, Forward, Backward };
+
+// What gwl_sigma_c_vjp_forward keeps for the backward calls that follow it:
+// the call's arguments, the options it ran with, and per block of start
+// vectors the segment checkpoints, the start vectors P_nm and V[phi_n phi_m];
+// per pair the Lanczos coefficients and final lengths.
+struct VjpSaved {
+  std::vector<int> qp;
+  std::vector<double> omega;
+  int n_begin = 0, n_end = 0, L = 0, B = 0, g = 0, S = 0, kernels = 0;
+  double eta_ev = 0, lo = 0, hi = 0;
+  long nvc = 0, nrp = 0;
+  DevBuf<double> ckq, ckqp, ck_amax, ck_bprev, Pb, Vnm, coef_a, coef_b, norm2;
+  DevBuf<int> ck_state, out_len, flen;
+};
+
+gwl_status vjp_run(gwl_ctx* ctx, VjpMode mode, const int* qp_states, int n_qp, int n_begin,
+                   int n_end, const double* omega_ev, int n_omega, double eta_ev, int n_lanczos,
+                   const double* grad_sigma, double* sigma_out, double* grad_energies,
+                   void* grad_orbitals) {
   try {
     GWL_CHECK(ctx != nullptr, GWL_EINVAL, "null context");
     gwl_ctx& c = *ctx;
+    const bool fwd_only = mode == VjpMode::Forward, bwd_only = mode == VjpMode::Backward;
+    const bool persist = mode != VjpMode::Full;  // checkpoints of every block kept
+    std::shared_ptr<VjpSaved> sv;
+    if (bwd_only) {
+      sv = std::static_pointer_cast<VjpSaved>(c.vjp_saved);
+      GWL_CHECK(sv != nullptr, GWL_EINVAL,
+                "no saved forward: call gwl_sigma_c_vjp_forward on this context first");
+      GWL_CHECK(sv->lo == c.poly_lo && sv->hi == c.poly_hi && sv->g == c.poly_degree &&
+                    sv->nvc == c.nvc && sv->nrp == c.gd.nrp && sv->kernels == c.fp64_kernel,
+                GWL_EINVAL, "the context's options changed since the saved forward");
+      qp_states = sv->qp.data();
+      n_qp = (int)sv->qp.size();
+      n_begin = sv->n_begin;
+      n_end = sv->n_end;
+      omega_ev = sv->omega.data();
+      n_omega = (int)sv->omega.size();
+      eta_ev = sv->eta_ev;
+      n_lanczos = sv->L;
+    }
     GWL_CHECK(0 <= n_begin && n_begin < n_end && n_end <= c.n_orb, GWL_EINVAL,
               "need 0 <= n_begin < n_end <= n_orb");
     GWL_CHECK(!c.tda && !c.quadrature && !c.isdf_on, GWL_EUNSUPPORTED,
               "the adjoint covers the polynomial method on the grid only (not Tamm-Dancoff, "
               "quadrature or ISDF)");
     GWL_CHECK(n_qp >= 1 && n_omega >= 1, GWL_EINVAL, "need n_qp >= 1 and n_omega >= 1");
-    GWL_CHECK(qp_states && omega_ev && grad_sigma && grad_energies && grad_orbitals, GWL_EINVAL,
-              "null pointer");
+    GWL_CHECK(qp_states && omega_ev, GWL_EINVAL, "null pointer");
+    GWL_CHECK(fwd_only ? sigma_out != nullptr
+                       : (grad_sigma && grad_energies && grad_orbitals),
+              GWL_EINVAL, "null pointer");
     GWL_CHECK(std::isfinite(eta_ev) && eta_ev > 0, GWL_EINVAL, "eta must be > 0");
     GWL_CHECK(n_lanczos >= 1 && n_lanczos <= 1024, GWL_EINVAL,
               "n_lanczos must be in [1, 1024] for the adjoint");
     GWL_CHECK(finite_all(omega_ev, n_omega), GWL_EINVAL, "non-finite frequency");
-    GWL_CHECK(finite_all(grad_sigma, (size_t)n_qp * n_omega * 2), GWL_EINVAL,
+    GWL_CHECK(fwd_only || finite_all(grad_sigma, (size_t)n_qp * n_omega * 2), GWL_EINVAL,
               "non-finite cotangent");
     for (int i = 0; i < n_qp; ++i)
       GWL_CHECK(qp_states[i] >= 0 && qp_states[i] < c.n_orb, GWL_EINVAL, "qp state out of range");
@@ -68,8 +114,12 @@ gwl_status vjp_range(gwl_ctx* ctx, const int* qp_states, int n_qp, int n_begin, 
     } restore{c, saved_prec, saved_reorth};
 
     const int B = std::max(1, std::min(P, c.block > 0 ? c.block : 64));
+    const int nblk = (P + B - 1) / B;
     c.ensure_work(B, L, false);
     const int S = c.auto_splitk(B, GWL_FP64);
+    // (the recompute must repeat the forward's arithmetic exactly)
+    GWL_CHECK(!bwd_only || (B == sv->B && S == sv->S), GWL_EINVAL,
+              "the context's options changed since the saved forward");
     PairGeom pg = c.pair_geom();
     const GemmDims& d = c.kd();
     const double lo = c.poly_lo, hi = c.poly_hi;
@@ -99,7 +149,7 @@ gwl_status vjp_range(gwl_ctx* ctx, const int* qp_states, int n_qp, int n_begin, 
     int seg = std::max(1, (int)std::ceil(std::sqrt((double)L)));
     DevBuf<double> store;
     bool whole = false;
-    if (c.adjoint_store && seg < L &&
+    if (!persist && c.adjoint_store && seg < L &&
         ((size_t)L * per_step + 2 * vec) * sizeof(double) <= GWL_ADJOINT_STORE_MAX) {
       try {
         store.ensure((size_t)L * per_step + 2 * vec);
@@ -111,42 +161,67 @@ gwl_status vjp_range(gwl_ctx* ctx, const int* qp_states, int n_qp, int n_begin, 
         (void)hipGetLastError();
       }
     }
-    if (seg >= L) whole = true, seg = L;
-    if (!store.p) store.ensure((size_t)seg * per_step + 2 * vec);
+    if (seg >= L) whole = !persist, seg = L;
+    if (!store.p && !fwd_only) store.ensure((size_t)seg * per_step + 2 * vec);
     c.adjoint_stored = whole ? 1 : 0;
     const int nseg = (L + seg - 1) / seg;
-    double* const sq_end = store.p + (size_t)seg * per_step;  // q after the segment's last step
-    double* const sq_prev0 = sq_end + vec;                     // q_{k0-1} of the segment
+    // Full: the forward of a block ends by keeping its last segment's
+    // iterates, so only the earlier segments need checkpoints and a recompute
+    const int nck = persist ? nseg : nseg - 1;  // checkpoints per block
+    // q after the segment's last step, q_{k0-1} of the segment (no store in a
+    // forward-only call)
+    double* const sq_end = store.p ? store.p + (size_t)seg * per_step : nullptr;
+    double* const sq_prev0 = store.p ? sq_end + vec : nullptr;
     auto step_ptr = [&](int kk) { return store.p + (size_t)kk * per_step; };
 
     // buffers
-    DevBuf<double> Pb, Vnm, ckq, ckqp, Sv, KS, VS, US, UT, wbar, qb0, qb1, qb2, pend, dbar,
-        dbar_tot, kbar, abar, bbar, nbar, ebar, sig, Gd, e_d, eta_d, om_d, grad_int, gvpart;
-    DevBuf<int> ck_state, qidx_d, slot_pair, mrow_d, nrow_d, flen;
-    DevBuf<double> ck_amax, ck_bprev;
-    DevBuf<unsigned char> tscr;
-    Pb.ensure(vec);
-    Vnm.ensure(fld);
-    if (nseg > 1) {
-      ckq.ensure((size_t)nseg * vec);
-      ckqp.ensure((size_t)nseg * vec);
-      ck_state.ensure((size_t)nseg * 2 * B);
-      ck_amax.ensure((size_t)nseg * B);
-      ck_bprev.ensure((size_t)nseg * B);
+    // kept state: in a new VjpSaved (Forward), the saved one (Backward), or a
+    // local one for one block at a time (Full)
+    std::shared_ptr<VjpSaved> own;
+    if (!bwd_only) {
+      own = std::make_shared<VjpSaved>();
+      sv = own;
+      const int nb_keep = persist ? nblk : 1;
+      sv->Pb.ensure((size_t)nb_keep * vec);
+      sv->Vnm.ensure((size_t)nb_keep * fld);
+      if (nck > 0) {
+        sv->ckq.ensure((size_t)nb_keep * nck * vec);
+        sv->ckqp.ensure((size_t)nb_keep * nck * vec);
+        sv->ck_state.ensure((size_t)nb_keep * nck * 2 * B);
+        sv->ck_amax.ensure((size_t)nb_keep * nck * B);
+        sv->ck_bprev.ensure((size_t)nb_keep * nck * B);
+      }
+      sv->flen.ensure(P);
+      if (persist) {
+        sv->coef_a.ensure((size_t)P * L);
+        sv->coef_b.ensure((size_t)P * L);
+        sv->norm2.ensure(P);
+        sv->out_len.ensure(P);
+      }
     }
-    Sv.ensure((size_t)(g + 1) * vec);
-    KS.ensure((size_t)(g + 1) * vec);
-    VS.ensure((size_t)g * fld);
-    US.ensure((size_t)g * uvp);
-    UT.ensure((size_t)g * uvp);
-    wbar.ensure(vec);
-    qb0.ensure(vec);
-    qb1.ensure(vec);
-    qb2.ensure(vec);
-    pend.ensure(B);
-    dbar.ensure(vec);
-    dbar_tot.ensure(nvc);
-    kbar.ensure(vec);
+    // block bi's slot in the kept state
+    auto kb = [&](int bi) { return persist ? (size_t)bi : (size_t)0; };
+    DevBuf<double> Sv, KS, VS, US, UT, wbar, qb0, qb1, qb2, pend, dbar, dbar_tot, kbar, abar,
+        bbar, nbar, ebar, sig, Gd, e_d, eta_d, om_d, grad_int, gvpart;
+    DevBuf<int> qidx_d, slot_pair, mrow_d, nrow_d;
+    DevBuf<unsigned char> tscr;
+    if (!fwd_only) {
+      Sv.ensure((size_t)(g + 1) * vec);
+      KS.ensure((size_t)(g + 1) * vec);
+      VS.ensure((size_t)g * fld);
+      US.ensure((size_t)g * uvp);
+      UT.ensure((size_t)g * uvp);
+      wbar.ensure(vec);
+      qb0.ensure(vec);
+      qb1.ensure(vec);
+      qb2.ensure(vec);
+      pend.ensure(B);
+      dbar.ensure(vec);
+      dbar_tot.ensure(nvc);
+      kbar.ensure(vec);
+      grad_int.ensure((size_t)(d.nvp + d.ncp) * d.nrp);
+      gvpart.ensure((size_t)nct * c.nv * d.nrp);
+    }
     abar.ensure((size_t)P * L);
     bbar.ensure((size_t)P * L);
     nbar.ensure(P);
@@ -157,19 +232,20 @@ gwl_status vjp_range(gwl_ctx* ctx, const int* qp_states, int n_qp, int n_begin, 
     eta_d.ensure(P);
     om_d.ensure(n_omega);
     qidx_d.ensure(P);
-    flen.ensure(P);
     slot_pair.ensure(B);
     mrow_d.ensure(P);
     nrow_d.ensure(P);
     tscr.ensure((size_t)B * L * n_omega * 16);
-    grad_int.ensure((size_t)(d.nvp + d.ncp) * d.nrp);
-    gvpart.ensure((size_t)nct * c.nv * d.nrp);
     std::vector<int> mr(P), nr_(P);
     for (int p = 0; p < P; ++p) {
       mr[p] = c.orb_row(m[p]);
       nr_[p] = c.orb_row(n[p]);
     }
-    GWL_HIP(hipMemcpy(Gd.p, grad_sigma, sizeof(double) * n_qp * n_omega * 2, hipMemcpyHostToDevice));
+    // (the forward-only call runs the continued-fraction adjoint for Sigma alone,
+    // with a zero cotangent)
+    if (!fwd_only)
+      GWL_HIP(hipMemcpy(Gd.p, grad_sigma, sizeof(double) * n_qp * n_omega * 2,
+                        hipMemcpyHostToDevice));
     GWL_HIP(hipMemcpy(e_d.p, en.data(), sizeof(double) * P, hipMemcpyHostToDevice));
     GWL_HIP(hipMemcpy(eta_d.p, et.data(), sizeof(double) * P, hipMemcpyHostToDevice));
     GWL_HIP(hipMemcpy(om_d.p, om.data(), sizeof(double) * n_omega, hipMemcpyHostToDevice));
@@ -177,12 +253,28 @@ gwl_status vjp_range(gwl_ctx* ctx, const int* qp_states, int n_qp, int n_begin, 
     GWL_HIP(hipMemcpy(mrow_d.p, mr.data(), sizeof(int) * P, hipMemcpyHostToDevice));
     GWL_HIP(hipMemcpy(nrow_d.p, nr_.data(), sizeof(int) * P, hipMemcpyHostToDevice));
 
-    c.coef_a.ensure((size_t)P * L);
-    c.coef_b.ensure((size_t)P * L);
-    c.norm2.ensure(P);
-    c.out_len.ensure(P);
-    GWL_HIP(hipMemsetAsync(c.coef_a.p, 0, sizeof(double) * (size_t)P * L, st));
-    GWL_HIP(hipMemsetAsync(c.coef_b.p, 0, sizeof(double) * (size_t)P * L, st));
+    double *coef_a, *coef_b, *norm2;
+    int* out_len;
+    if (persist) {
+      coef_a = sv->coef_a.p;
+      coef_b = sv->coef_b.p;
+      norm2 = sv->norm2.p;
+      out_len = sv->out_len.p;
+    } else {
+      c.coef_a.ensure((size_t)P * L);
+      c.coef_b.ensure((size_t)P * L);
+      c.norm2.ensure(P);
+      c.out_len.ensure(P);
+      coef_a = c.coef_a.p;
+      coef_b = c.coef_b.p;
+      norm2 = c.norm2.p;
+      out_len = c.out_len.p;
+    }
+    int* const flen = sv->flen.p;
+    if (!bwd_only) {
+      GWL_HIP(hipMemsetAsync(coef_a, 0, sizeof(double) * (size_t)P * L, st));
+      GWL_HIP(hipMemsetAsync(coef_b, 0, sizeof(double) * (size_t)P * L, st));
+    }
     SlotState ss;
     ss.pair = c.s_pair.p;
     ss.k = c.s_k.p;
@@ -190,10 +282,10 @@ gwl_status vjp_range(gwl_ctx* ctx, const int* qp_states, int n_qp, int n_begin, 
     ss.dead = c.s_dead.p;
     ss.amax = c.s_amax.p;
     ss.bprev = c.s_bprev.p;
-    ss.coef_a = c.coef_a.p;
-    ss.coef_b = c.coef_b.p;
-    ss.out_len = c.out_len.p;
-    ss.norm2 = c.norm2.p;
+    ss.coef_a = coef_a;
+    ss.coef_b = coef_b;
+    ss.out_len = out_len;
+    ss.norm2 = norm2;
     ss.ld = L;
 
     // one Lanczos step (no reorthogonalisation) of all slots from q, qprev
@@ -233,21 +325,24 @@ gwl_status vjp_range(gwl_ctx* ctx, const int* qp_states, int n_qp, int n_begin, 
       }
       GWL_HIP(hipMemcpyAsync(sq_end, c.q.p, vec * 8, hipMemcpyDeviceToDevice, st));
     };
-    auto save_state = [&](int sgi) {
-      GWL_HIP(hipMemcpyAsync(ckq.p + (size_t)sgi * vec, c.q.p, vec * 8, hipMemcpyDeviceToDevice, st));
-      GWL_HIP(hipMemcpyAsync(ckqp.p + (size_t)sgi * vec, c.qprev.p, vec * 8, hipMemcpyDeviceToDevice, st));
-      GWL_HIP(hipMemcpyAsync(ck_state.p + (size_t)sgi * 2 * B, c.s_k.p, B * 4, hipMemcpyDeviceToDevice, st));
-      GWL_HIP(hipMemcpyAsync(ck_state.p + (size_t)sgi * 2 * B + B, c.s_dead.p, B * 4, hipMemcpyDeviceToDevice, st));
-      GWL_HIP(hipMemcpyAsync(ck_amax.p + (size_t)sgi * B, c.s_amax.p, B * 8, hipMemcpyDeviceToDevice, st));
-      GWL_HIP(hipMemcpyAsync(ck_bprev.p + (size_t)sgi * B, c.s_bprev.p, B * 8, hipMemcpyDeviceToDevice, st));
+    // checkpoint sgi of block bi: (q, q_prev) and the slot state
+    auto save_state = [&](int bi, int sgi) {
+      const size_t i = kb(bi) * nck + sgi;
+      GWL_HIP(hipMemcpyAsync(sv->ckq.p + i * vec, c.q.p, vec * 8, hipMemcpyDeviceToDevice, st));
+      GWL_HIP(hipMemcpyAsync(sv->ckqp.p + i * vec, c.qprev.p, vec * 8, hipMemcpyDeviceToDevice, st));
+      GWL_HIP(hipMemcpyAsync(sv->ck_state.p + i * 2 * B, c.s_k.p, B * 4, hipMemcpyDeviceToDevice, st));
+      GWL_HIP(hipMemcpyAsync(sv->ck_state.p + i * 2 * B + B, c.s_dead.p, B * 4, hipMemcpyDeviceToDevice, st));
+      GWL_HIP(hipMemcpyAsync(sv->ck_amax.p + i * B, c.s_amax.p, B * 8, hipMemcpyDeviceToDevice, st));
+      GWL_HIP(hipMemcpyAsync(sv->ck_bprev.p + i * B, c.s_bprev.p, B * 8, hipMemcpyDeviceToDevice, st));
     };
-    auto load_state = [&](int sgi) {
-      GWL_HIP(hipMemcpyAsync(c.q.p, ckq.p + (size_t)sgi * vec, vec * 8, hipMemcpyDeviceToDevice, st));
-      GWL_HIP(hipMemcpyAsync(c.qprev.p, ckqp.p + (size_t)sgi * vec, vec * 8, hipMemcpyDeviceToDevice, st));
-      GWL_HIP(hipMemcpyAsync(c.s_k.p, ck_state.p + (size_t)sgi * 2 * B, B * 4, hipMemcpyDeviceToDevice, st));
-      GWL_HIP(hipMemcpyAsync(c.s_dead.p, ck_state.p + (size_t)sgi * 2 * B + B, B * 4, hipMemcpyDeviceToDevice, st));
-      GWL_HIP(hipMemcpyAsync(c.s_amax.p, ck_amax.p + (size_t)sgi * B, B * 8, hipMemcpyDeviceToDevice, st));
-      GWL_HIP(hipMemcpyAsync(c.s_bprev.p, ck_bprev.p + (size_t)sgi * B, B * 8, hipMemcpyDeviceToDevice, st));
+    auto load_state = [&](int bi, int sgi) {
+      const size_t i = kb(bi) * nck + sgi;
+      GWL_HIP(hipMemcpyAsync(c.q.p, sv->ckq.p + i * vec, vec * 8, hipMemcpyDeviceToDevice, st));
+      GWL_HIP(hipMemcpyAsync(c.qprev.p, sv->ckqp.p + i * vec, vec * 8, hipMemcpyDeviceToDevice, st));
+      GWL_HIP(hipMemcpyAsync(c.s_k.p, sv->ck_state.p + i * 2 * B, B * 4, hipMemcpyDeviceToDevice, st));
+      GWL_HIP(hipMemcpyAsync(c.s_dead.p, sv->ck_state.p + i * 2 * B + B, B * 4, hipMemcpyDeviceToDevice, st));
+      GWL_HIP(hipMemcpyAsync(c.s_amax.p, sv->ck_amax.p + i * B, B * 8, hipMemcpyDeviceToDevice, st));
+      GWL_HIP(hipMemcpyAsync(c.s_bprev.p, sv->ck_bprev.p + i * B, B * 8, hipMemcpyDeviceToDevice, st));
     };
     const double* psi_c_rc = c.psi_c_rc64.p;
     const double* psi_v_rv = c.psi_v_rv64.p;
@@ -255,6 +350,9 @@ gwl_status vjp_range(gwl_ctx* ctx, const int* qp_states, int n_qp, int n_begin, 
 
     for (int p0 = 0; p0 < P; p0 += B) {
       const int nbk = std::min(B, P - p0);
+      const int bi = p0 / B;
+      double* const Pb = sv->Pb.p + kb(bi) * vec;
+      double* const Vnm = sv->Vnm.p + kb(bi) * fld;
       // slot -> pair map; unused slots carry pair -1
       std::vector<int> hp(B, -1), hl(B, 0), sl(B);
       for (int b = 0; b < nbk; ++b) {
@@ -267,29 +365,34 @@ gwl_status vjp_range(gwl_ctx* ctx, const int* qp_states, int n_qp, int n_begin, 
       GWL_HIP(hipMemcpy(slot_pair.p, hp.data(), B * 4, hipMemcpyHostToDevice));
       GWL_HIP(hipMemcpy(c.s_len.p, hl.data(), B * 4, hipMemcpyHostToDevice));
       GWL_HIP(hipMemcpy(c.s_slots.p, sl.data(), B * 4, hipMemcpyHostToDevice));
-      GWL_HIP(hipMemsetAsync(c.q.p, 0, vec * 8, st));
-      // ---- forward
-      c.coupling_batch(nbk, m.data() + p0, n.data() + p0, c.q.p, nvc);
-      // the coupling build leaves V[phi_n phi_m] of the block in vpot64
-      GWL_HIP(hipMemcpyAsync(Vnm.p, c.vpot64.p, (size_t)nbk * d.nrp * 8, hipMemcpyDeviceToDevice, st));
-      GWL_HIP(hipMemcpyAsync(Pb.p, c.q.p, vec * 8, hipMemcpyDeviceToDevice, st));
-      lz_start(ss, B, c.s_slots.p, nbk, c.q.p, c.qprev.p, nullptr, 0, nvc, st);
-      if (nseg == 1) {
-        fwd_segment_store(0, L);
-      } else {
+      if (!bwd_only) {
+        // ---- forward
+        GWL_HIP(hipMemsetAsync(c.q.p, 0, vec * 8, st));
+        c.coupling_batch(nbk, m.data() + p0, n.data() + p0, c.q.p, nvc);
+        // the coupling build leaves V[phi_n phi_m] of the block in vpot64
+        GWL_HIP(hipMemcpyAsync(Vnm, c.vpot64.p, (size_t)nbk * d.nrp * 8, hipMemcpyDeviceToDevice, st));
+        GWL_HIP(hipMemcpyAsync(Pb, c.q.p, vec * 8, hipMemcpyDeviceToDevice, st));
+        lz_start(ss, B, c.s_slots.p, nbk, c.q.p, c.qprev.p, nullptr, 0, nvc, st);
         for (int k = 0; k < L; ++k) {
-          if (k % seg == 0) save_state(k / seg);
+          if (k % seg == 0) {
+            const int sgi = k / seg;
+            if (!persist && sgi == nseg - 1) {  // the last segment: kept, not recomputed
+              fwd_segment_store(k, L);
+              break;
+            }
+            save_state(bi, sgi);
+          }
           fwd_step();
         }
+        // final lengths (the segment recompute below rewrites out_len step by step)
+        GWL_HIP(hipMemcpyAsync(flen + p0, out_len + p0, nbk * 4, hipMemcpyDeviceToDevice, st));
       }
-      // final lengths (the segment recompute below rewrites out_len step by step)
-      GWL_HIP(hipMemcpyAsync(flen.p + p0, c.out_len.p + p0, nbk * 4, hipMemcpyDeviceToDevice, st));
       // ---- continued-fraction adjoint (and the forward Sigma per pair)
-      adj_cfrac(nbk, c.coef_a.p + (size_t)p0 * L, c.coef_b.p + (size_t)p0 * L,
-                flen.p + p0, c.norm2.p + p0, L, e_d.p + p0, eta_d.p + p0, qidx_d.p + p0,
-                om_d.p, n_omega, eta_ev / kHartreeEv, Gd.p, tscr.p, abar.p + (size_t)p0 * L,
-                bbar.p + (size_t)p0 * L, nbar.p + p0, ebar.p + p0, sig.p + (size_t)p0 * n_omega * 2,
-                st);
+      adj_cfrac(nbk, coef_a + (size_t)p0 * L, coef_b + (size_t)p0 * L, flen + p0, norm2 + p0, L,
+                e_d.p + p0, eta_d.p + p0, qidx_d.p + p0, om_d.p, n_omega, eta_ev / kHartreeEv,
+                Gd.p, tscr.p, abar.p + (size_t)p0 * L, bbar.p + (size_t)p0 * L, nbar.p + p0,
+                ebar.p + p0, sig.p + (size_t)p0 * n_omega * 2, st);
+      if (fwd_only) continue;
       // ---- backward
       double* qbn = qb0.p;  // q_bar_{k+1}
       double* qbc = qb1.p;  // q_bar_k
@@ -304,7 +407,7 @@ gwl_status vjp_range(gwl_ctx* ctx, const int* qp_states, int n_qp, int n_begin, 
                               const double* Ti, const double* KTi, const double* Wi,
                               const double* VTi) {
         // reverse Lanczos step k
-        adj_lanczos_step(k, B, slot_pair.p, flen.p, L, c.coef_a.p, c.coef_b.p, abar.p,
+        adj_lanczos_step(k, B, slot_pair.p, flen, L, coef_a, coef_b, abar.p,
                          bbar.p, qn, qk, qpv, Wi, qbn, qbc, qbp, wbar.p, pend.p, nvc, st);
         // reverse Chebyshev recurrence on x = w_bar_k; the product on s_j leaves
         // V[rho(Delta^1/2 s_j)] in VS[j - 1]
@@ -341,8 +444,8 @@ gwl_status vjp_range(gwl_ctx* ctx, const int* qp_states, int n_qp, int n_begin, 
       };
       for (int sgi = nseg - 1; sgi >= 0; --sgi) {
         const int k0 = sgi * seg, k1 = std::min(L, k0 + seg);
-        if (nseg > 1) {
-          load_state(sgi);
+        if (persist || sgi < nseg - 1) {
+          load_state(bi, sgi);
           fwd_segment_store(k0, k1);
         }
         for (int k = k1 - 1; k >= k0; --k) {
@@ -354,18 +457,41 @@ gwl_status vjp_range(gwl_ctx* ctx, const int* qp_states, int n_qp, int n_begin, 
         }
       }
       // start vector adjoint: q_bar_0 is now in qbn; k_bar per slot
-      adj_start(B, slot_pair.p, c.norm2.p, nbar.p, Pb.p, qbn, c.sdelta.p, dbar.p, kbar.p, nvc,
-                st);
+      adj_start(B, slot_pair.p, norm2, nbar.p, Pb, qbn, c.sdelta.p, dbar.p, kbar.p, nvc, st);
       adj_sum_rows(dbar_tot.p, dbar.p, B, nvc, st);
       // orbital terms of the coupling integrals (nm|vc) = dV sum_r rho_vc V[phi_n phi_m]:
       // k_bar with V[phi_n phi_m] through the contraction, and the potential of
       // rho(k_bar) with phi_m (for phi_n) and phi_n (for phi_m)
       c.cast(B, kbar.p, GWL_FP64, true);
-      adj_zgemm(d, c.nv, ZSeg{Vnm.p, c.u64.p, nbk}, ZSeg{nullptr, nullptr, 0}, psi_c_rc,
+      adj_zgemm(d, c.nv, ZSeg{Vnm, c.u64.p, nbk}, ZSeg{nullptr, nullptr, 0}, psi_c_rc,
                 psi_v_rv, c.dv, grad_c, gvpart.p, st);
       c.potential64(nbk, c.vpot64.p);
       adj_orb_grad_nm(c.psi_t.p, c.vpot64.p, d.nrp, (int)c.nr, mrow_d.p + p0, nrow_d.p + p0, nbk,
                       c.dv, grad_int.p, st);
+    }
+    if (fwd_only) {
+      c.sig_sum.ensure((size_t)n_qp * n_omega * 2);
+      sum_groups(sig.p, n_qp, nn, n_omega, c.sig_sum.p, st);
+      GWL_HIP(hipMemcpyAsync(sigma_out, c.sig_sum.p, sizeof(double) * n_qp * n_omega * 2,
+                             hipMemcpyDeviceToHost, st));
+      GWL_HIP(hipStreamSynchronize(st));
+      sv->qp.assign(qp_states, qp_states + n_qp);
+      sv->omega.assign(omega_ev, omega_ev + n_omega);
+      sv->n_begin = n_begin;
+      sv->n_end = n_end;
+      sv->L = L;
+      sv->B = B;
+      sv->S = S;
+      sv->kernels = c.fp64_kernel;
+      sv->g = g;
+      sv->eta_ev = eta_ev;
+      sv->lo = lo;
+      sv->hi = hi;
+      sv->nvc = nvc;
+      sv->nrp = d.nrp;
+      c.vjp_saved = sv;
+      set_error("");
+      return GWL_OK;
     }
     adj_gv_reduce(gvpart.p, nct, c.nv, d.nrp, grad_int.p, st);
 
@@ -417,7 +543,8 @@ extern "C" gwl_status gwl_sigma_c_vjp(gwl_ctx* ctx, const int* qp_states, int n_
     set_error("null context");
     return GWL_EINVAL;
   }
-  return vjp_range(ctx, qp_states, n_qp, 0, ctx->n_orb, omega_ev, n_omega, eta_ev, n_lanczos,
+  return vjp_run(ctx, VjpMode::Full, qp_states, n_qp, 0, ctx->n_orb, omega_ev, n_omega, eta_ev,
+                 n_lanczos,
                    grad_sigma, sigma_out, grad_energies, grad_orbitals);
 }
 
@@ -426,6 +553,22 @@ extern "C" gwl_status gwl_sigma_c_range_vjp(gwl_ctx* ctx, const int* qp_states, 
                                             int n_omega, double eta_ev, int n_lanczos,
                                             const double* grad_sigma, double* sigma_out,
                                             double* grad_energies, void* grad_orbitals) {
-  return vjp_range(ctx, qp_states, n_qp, n_begin, n_end, omega_ev, n_omega, eta_ev, n_lanczos,
+  return vjp_run(ctx, VjpMode::Full, qp_states, n_qp, n_begin, n_end, omega_ev, n_omega, eta_ev,
+                 n_lanczos,
                    grad_sigma, sigma_out, grad_energies, grad_orbitals);
+}
+
+extern "C" gwl_status gwl_sigma_c_vjp_forward(gwl_ctx* ctx, const int* qp_states, int n_qp,
+                                              int n_begin, int n_end, const double* omega_ev,
+                                              int n_omega, double eta_ev, int n_lanczos,
+                                              double* sigma_out) {
+  if (ctx) ctx->vjp_saved.reset();  // the previous forward's state goes first
+  return vjp_run(ctx, VjpMode::Forward, qp_states, n_qp, n_begin, n_end, omega_ev, n_omega,
+                 eta_ev, n_lanczos, nullptr, sigma_out, nullptr, nullptr);
+}
+
+extern "C" gwl_status gwl_sigma_c_vjp_backward(gwl_ctx* ctx, const double* grad_sigma,
+                                               double* grad_energies, void* grad_orbitals) {
+  return vjp_run(ctx, VjpMode::Backward, nullptr, 0, 0, 0, nullptr, 0, 0.0, 0, grad_sigma,
+                 nullptr, grad_energies, grad_orbitals);
 }

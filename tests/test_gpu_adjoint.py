@@ -18,7 +18,12 @@
   start vectors): directional derivatives against central differences of
   the GPU forward (<= 1e-6) and sampled entries against the oracle's;
 * FP32 orbitals: the gradient comes back in FP32, equal to the FP64
-  context's gradient on the same (rounded) orbitals, rounded.
+  context's gradient on the same (rounded) orbitals, rounded;
+* the split form (gwl_sigma_c_vjp_forward, then gwl_sigma_c_vjp_backward,
+  twice, with two cotangents) equals the one-call VJP bitwise, over several
+  blocks of start vectors, with one and with several checkpoint segments,
+  for the full n-sum and a partial one; a backward with no kept forward, or
+  after the block size changed, is an error.
 """
 import numpy as np
 import pytest
@@ -294,3 +299,40 @@ def test_vjp_range_adds_up(tiny):
     h = 1e-5
     fd = (loss1(s.energies_ev + h * de) - loss1(s.energies_ev - h * de)) / (2 * h)
     assert abs(fd - ge1 @ de) <= 1e-6 * abs(fd) + 1e-12, (fd, ge1 @ de)
+
+
+@pytest.mark.parametrize("n_lanczos,n_range", [(1, None), (7, None), (17, None), (10, (2, 7))])
+def test_vjp_split_equals_one_call(tiny, n_lanczos, n_range):
+    """Forward-then-backward against the one-call VJP (block 4: four blocks of
+    start vectors; L = 1: one segment; L = 7, 10, 17: ragged segments; a
+    partial n-sum)."""
+    s, wl, lo, hi, om, G = tiny
+    _say(f"vjp split vs one call, L={n_lanczos}, n_range={n_range}")
+    G2 = np.conj(G[:, ::-1]) * 0.7
+    with _ctx(s.phi, s.energies_ev, wl, lo, hi, block=4) as c:
+        one = [c.sigma_c_vjp(s.qp_states, om, wl.eta, n_lanczos, g, n_range=n_range)
+               for g in (G, G2)]
+    with _ctx(s.phi, s.energies_ev, wl, lo, hi, block=4) as c:
+        sig = c.sigma_c_vjp_forward(s.qp_states, om, wl.eta, n_lanczos, n_range=n_range)
+        assert np.array_equal(sig, one[0][0])
+        for g, (_, ge1, go1) in zip((G, G2), one):
+            ge, go = c.sigma_c_vjp_backward(g)
+            assert np.all(np.isfinite(ge))
+            assert np.array_equal(ge, ge1)
+            assert torch.equal(go, go1)
+
+
+def test_vjp_backward_errors(tiny):
+    import paper_2310_20103_amd as GW
+    s, wl, lo, hi, om, G = tiny
+    _say("vjp backward without a kept forward / after the block size changed")
+    with _ctx(s.phi, s.energies_ev, wl, lo, hi) as c:
+        with pytest.raises(GW.GwlError, match="no saved forward"):
+            c.sigma_c_vjp_backward(G)
+        c.sigma_c_vjp_forward(s.qp_states, om, wl.eta, wl.n_lanczos)
+        c.set_option(GW.KEY_BLOCK, 4)
+        with pytest.raises(GW.GwlError, match="changed since the saved forward"):
+            c.sigma_c_vjp_backward(G)
+        c.set_option(GW.KEY_BLOCK, 0)
+        ge, _ = c.sigma_c_vjp_backward(G)
+        assert np.all(np.isfinite(ge))

@@ -1,7 +1,10 @@
 """torch.autograd binding of Sigma_c (paper_2310_20103_amd.autograd.sigma_c).
 
-* the forward equals gwl_sigma_c (FP64, no reorthogonalisation);
-* loss.backward() gives the library VJP's gradients for grad_output =
+* the forward with gradients runs gwl_sigma_c_vjp_forward: its Sigma equals
+  the one gwl_sigma_c_vjp returns (bitwise) and gwl_sigma_c's (FP64, no
+  reorthogonalisation) to 1e-12; without gradients it is gwl_sigma_c itself;
+* loss.backward() (gwl_sigma_c_vjp_backward on the kept checkpoints) gives
+  the one-call VJP's gradients bitwise for grad_output =
   dl/dRe Sigma + i dl/dIm Sigma;
 * central finite differences of the autograd forward along seeded random
   directions in the energies and the orbital grid values: <= 1e-6 relative.
@@ -57,10 +60,15 @@ def test_forward_and_backward_match_library(tiny):
     with P.Context(s.phi, s.energies_ev, wl.n_occ, wl.grid, tuple(n * wl.h for n in wl.grid),
                    poly_lo=lo, poly_hi=hi, poly_degree=wl.poly_degree, reorth="none") as c:
         ref = c.sigma_c(s.qp_states, om, wl.eta, wl.n_lanczos)
-        _, ge, go = c.sigma_c_vjp(s.qp_states, om, wl.eta, wl.n_lanczos, G)
-    assert np.array_equal(sig.detach().cpu().numpy(), ref)
+        sig1, ge, go = c.sigma_c_vjp(s.qp_states, om, wl.eta, wl.n_lanczos, G)
+    got = sig.detach().cpu().numpy()
+    assert np.array_equal(got, sig1)
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
     assert np.array_equal(e.grad.numpy(), ge)
     assert torch.equal(phi.grad, go)
+    with torch.no_grad():
+        sig0 = _call(s, wl, lo, hi, om, e, phi)
+    assert np.array_equal(sig0.cpu().numpy(), ref)
 
 
 def test_gradients_against_finite_differences(tiny):
