@@ -14,6 +14,16 @@ namespace gwl {
 namespace {
 
 constexpr int NT = 256;
+// a_k and b_k run one block per slot: 1,024 threads keep a slot's whole
+// vector in flight from one CU
+constexpr int NTS = 1024;
+
+// Pair-space rows are read as 16-byte pairs when every row starts 16 bytes
+// apart (N_v N_c even; basis rows are whole multiples of a pair vector).
+__device__ inline const double2* as_d2(const double* p) {
+  return reinterpret_cast<const double2*>(p);
+}
+__device__ inline double2* as_d2(double* p) { return reinterpret_cast<double2*>(p); }
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -160,20 +170,40 @@ lz_start_kernel(SlotState s, const int* __restrict__ slot_list, double* __restri
   }
 }
 
-__global__ void __launch_bounds__(NT)
+__global__ void __launch_bounds__(NTS)
 lz_alpha_kernel(SlotState s, const double* __restrict__ q, const double* __restrict__ qprev,
                 double* __restrict__ w, long nvc) {
-  __shared__ double sh[NT / 64];
+  __shared__ double sh[NTS / 64];
   const int b = blockIdx.x;
   if (!slot_active(s, b)) return;
   const double* qb = q + (long)b * nvc;
   const double* pb = qprev + (long)b * nvc;
   double* wb = w + (long)b * nvc;
+  const bool pairs = (nvc & 1) == 0;
+  const long n2 = nvc >> 1;
   double part = 0.0;
-  for (long i = threadIdx.x; i < nvc; i += NT) part += qb[i] * wb[i];
+  if (pairs) {
+    for (long i = threadIdx.x; i < n2; i += NTS) {
+      const double2 x = as_d2(qb)[i], y = as_d2(wb)[i];
+      part += x.x * y.x;
+      part += x.y * y.y;
+    }
+  } else {
+    for (long i = threadIdx.x; i < nvc; i += NTS) part += qb[i] * wb[i];
+  }
   const double a = block_sum(part, sh);
   const double bp = s.bprev[b];
-  for (long i = threadIdx.x; i < nvc; i += NT) wb[i] = wb[i] - a * qb[i] - bp * pb[i];
+  if (pairs) {
+    for (long i = threadIdx.x; i < n2; i += NTS) {
+      const double2 x = as_d2(qb)[i], y = as_d2(pb)[i];
+      double2 z = as_d2(wb)[i];
+      z.x = z.x - a * x.x - bp * y.x;
+      z.y = z.y - a * x.y - bp * y.y;
+      as_d2(wb)[i] = z;
+    }
+  } else {
+    for (long i = threadIdx.x; i < nvc; i += NTS) wb[i] = wb[i] - a * qb[i] - bp * pb[i];
+  }
   if (threadIdx.x == 0) {
     const int pair = s.pair[b], k = s.k[b];
     s.coef_a[(long)pair * s.ld + k] = a;
@@ -213,10 +243,23 @@ lz_dots_kernel(SlotState s, int mode, const double* __restrict__ basis, long bst
   const double* wb = w + (long)b * nvc;
   double part = 0.0, ww = 0.0;
   const bool norm = wn0 && j == 0;
-  for (long i = threadIdx.x; i < nvc; i += NT) {
-    const double x = wb[i];
-    part += vb[i] * x;
-    if (norm) ww += x * x;
+  if ((nvc & 1) == 0) {
+    const long n2 = nvc >> 1;
+    double p1 = 0.0;
+#pragma unroll 4
+    for (long i = threadIdx.x; i < n2; i += NT) {
+      const double2 x = as_d2(wb)[i], y = as_d2(vb)[i];
+      part += y.x * x.x;
+      p1 += y.y * x.y;
+      if (norm) ww += x.x * x.x + x.y * x.y;
+    }
+    part += p1;
+  } else {
+    for (long i = threadIdx.x; i < nvc; i += NT) {
+      const double x = wb[i];
+      part += vb[i] * x;
+      if (norm) ww += x * x;
+    }
   }
   const double t = block_sum(part, sh);
   if (threadIdx.x == 0) h[(long)b * hld + j] = t;
@@ -241,18 +284,51 @@ lz_project_kernel(SlotState s, int mode, const double* __restrict__ basis, long 
   const double* hb = h + (long)b * hld;
   double* wb = w + (long)b * nvc;
   double ww = 0.0;
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < nvc; i += (long)gridDim.x * blockDim.x) {
-    double acc = 0.0;
-    if (mode == GWL_REORTH_FULL) {
-      const double* bb = basis + (long)b * bstride + i;
-      for (int j = 0; j <= k; ++j) acc += hb[j] * bb[(long)j * nvc];
-    } else {
-      acc = hb[0] * q[(long)b * nvc + i];
-      if (k > 0) acc += hb[1] * qprev[(long)b * nvc + i];
+  if ((nvc & 1) == 0) {
+    const long n2 = nvc >> 1;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n2;
+         i += (long)gridDim.x * blockDim.x) {
+      double2 acc = {0.0, 0.0};
+      if (mode == GWL_REORTH_FULL) {
+        const double2* bb = as_d2(basis + (long)b * bstride) + i;
+#pragma unroll 4
+        for (int j = 0; j <= k; ++j) {
+          const double2 v = bb[(long)j * n2];
+          acc.x += hb[j] * v.x;
+          acc.y += hb[j] * v.y;
+        }
+      } else {
+        const double2 v = as_d2(q + (long)b * nvc)[i];
+        acc.x = hb[0] * v.x;
+        acc.y = hb[0] * v.y;
+        if (k > 0) {
+          const double2 u = as_d2(qprev + (long)b * nvc)[i];
+          acc.x += hb[1] * u.x;
+          acc.y += hb[1] * u.y;
+        }
+      }
+      double2 x = as_d2(wb)[i];
+      x.x -= acc.x;
+      x.y -= acc.y;
+      as_d2(wb)[i] = x;
+      ww += x.x * x.x;
+      ww += x.y * x.y;
     }
-    const double x = wb[i] - acc;
-    wb[i] = x;
-    ww += x * x;
+  } else {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < nvc;
+         i += (long)gridDim.x * blockDim.x) {
+      double acc = 0.0;
+      if (mode == GWL_REORTH_FULL) {
+        const double* bb = basis + (long)b * bstride + i;
+        for (int j = 0; j <= k; ++j) acc += hb[j] * bb[(long)j * nvc];
+      } else {
+        acc = hb[0] * q[(long)b * nvc + i];
+        if (k > 0) acc += hb[1] * qprev[(long)b * nvc + i];
+      }
+      const double x = wb[i] - acc;
+      wb[i] = x;
+      ww += x * x;
+    }
   }
   if (part) {
     const double t = block_sum(ww, sh);
@@ -279,11 +355,11 @@ lz_dgks_kernel(SlotState s, const double* __restrict__ part, int nblk,
   if (threadIdx.x == 0) skip[b] = (n1 >= 0.5 * wn0[b]) ? 1 : 0;
 }
 
-__global__ void __launch_bounds__(NT)
+__global__ void __launch_bounds__(NTS)
 lz_beta_kernel(SlotState s, double* __restrict__ q, double* __restrict__ qprev,
                double* __restrict__ w, double* __restrict__ basis, long bstride,
                int store_basis, long nvc) {
-  __shared__ double sh[NT / 64];
+  __shared__ double sh[NTS / 64];
   const int b = blockIdx.x;
   if (!slot_active(s, b)) return;
   const int k = s.k[b];
@@ -293,8 +369,18 @@ lz_beta_kernel(SlotState s, double* __restrict__ q, double* __restrict__ qprev,
     return;
   }
   double* wb = w + (long)b * nvc;
+  const bool pairs = (nvc & 1) == 0;
+  const long n2 = nvc >> 1;
   double part = 0.0;
-  for (long i = threadIdx.x; i < nvc; i += NT) part += wb[i] * wb[i];
+  if (pairs) {
+    for (long i = threadIdx.x; i < n2; i += NTS) {
+      const double2 x = as_d2(wb)[i];
+      part += x.x * x.x;
+      part += x.y * x.y;
+    }
+  } else {
+    for (long i = threadIdx.x; i < nvc; i += NTS) part += wb[i] * wb[i];
+  }
   const double bn = sqrt(block_sum(part, sh));
   const int pair = s.pair[b];
   if (!(bn > 1e-12 * s.amax[b])) {
@@ -309,11 +395,21 @@ lz_beta_kernel(SlotState s, double* __restrict__ q, double* __restrict__ qprev,
   double* qb = q + (long)b * nvc;
   double* pb = qprev + (long)b * nvc;
   double* bb = store_basis ? basis + (long)b * bstride + (long)(k + 1) * nvc : nullptr;
-  for (long i = threadIdx.x; i < nvc; i += NT) {
-    const double nq = wb[i] * inv;
-    pb[i] = qb[i];
-    qb[i] = nq;
-    if (bb) bb[i] = nq;
+  if (pairs) {
+    for (long i = threadIdx.x; i < n2; i += NTS) {
+      const double2 x = as_d2(wb)[i];
+      const double2 nq = {x.x * inv, x.y * inv};
+      as_d2(pb)[i] = as_d2(qb)[i];
+      as_d2(qb)[i] = nq;
+      if (bb) as_d2(bb)[i] = nq;
+    }
+  } else {
+    for (long i = threadIdx.x; i < nvc; i += NTS) {
+      const double nq = wb[i] * inv;
+      pb[i] = qb[i];
+      qb[i] = nq;
+      if (bb) bb[i] = nq;
+    }
   }
   if (threadIdx.x == 0) {
     s.coef_b[(long)pair * s.ld + k] = bn;
@@ -454,7 +550,7 @@ void lz_start(const SlotState& s, int nb_slots, const int* slot_list, int cnt, d
 
 void lz_alpha(const SlotState& s, int nb, const double* q, const double* qprev, double* w,
               long nvc, hipStream_t st) {
-  lz_alpha_kernel<<<nb, NT, 0, st>>>(s, q, qprev, w, nvc);
+  lz_alpha_kernel<<<nb, NTS, 0, st>>>(s, q, qprev, w, nvc);
   GWL_HIP(hipGetLastError());
 }
 
@@ -465,7 +561,9 @@ void lz_reorth(const SlotState& s, int nb, int kmax, int mode, const double* bas
   const bool full = (mode == GWL_REORTH_FULL);
   const int nd = full ? kmax + 1 : 2;
   const int hld = full ? s.ld + 1 : 2;
-  const int ge = grid_elems(nvc);
+  // (the projection runs over element pairs when N_v N_c is even; the
+  // partial-norm buffer holds grid_elems(nvc) entries per slot)
+  const int ge = grid_elems((nvc & 1) == 0 ? nvc / 2 : nvc);
   // FULL: classical Gram-Schmidt, the second pass only where the first
   // removed more than half of ||w||^2; LOCAL: always two passes
   lz_dots_kernel<<<dim3(nd, nb), NT, 0, st>>>(s, mode, basis, bstride, q, qprev, w, hbuf, hld,
@@ -485,7 +583,7 @@ long reorth_part_len(long nvc) { return grid_elems(nvc); }
 
 void lz_beta(const SlotState& s, int nb, double* q, double* qprev, double* w, double* basis,
              long bstride, int store_basis, long nvc, hipStream_t st) {
-  lz_beta_kernel<<<nb, NT, 0, st>>>(s, q, qprev, w, basis, bstride, store_basis, nvc);
+  lz_beta_kernel<<<nb, NTS, 0, st>>>(s, q, qprev, w, basis, bstride, store_basis, nvc);
   GWL_HIP(hipGetLastError());
 }
 
