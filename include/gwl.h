@@ -121,7 +121,8 @@ void gwl_default_options(gwl_options* opts);
  *   grid, opts    host structs; opts may be NULL for the defaults.
  *   out           receives the context; unchanged on failure.
  * Errors: GWL_EINVAL (n_occ not in [1, n_orb-1], NaN, Delta <= 0, null
- * pointers), GWL_EUNSUPPORTED (grid), GWL_ENOMEM, GWL_EDEVICE. */
+ * pointers), GWL_EUNSUPPORTED (grid, or N_v N_c >= 2^31), GWL_ENOMEM,
+ * GWL_EDEVICE. */
 gwl_status gwl_setup(const void* orbitals, int orb_dtype, int orb_on_device,
                      int n_orb, int n_occ, const double* energies_ev,
                      const gwl_grid* grid, const gwl_options* opts,

@@ -218,7 +218,7 @@ __global__ void dbar_zops_kernel(PairGeom g, const double* __restrict__ s,
   const int b = blockIdx.y;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < g.nvc; i += (long)gridDim.x * blockDim.x) {
     const long o = (long)b * g.nvc + i;
-    const int v = (int)(i / g.nc), c = (int)(i - (long)v * g.nc);
+    const int v = (int)i / g.nc, c = (int)i - v * g.nc;  // (N_v N_c < 2^31)
     const long op = ((long)b * g.nvp + v) * g.ncp + c;
     const double sd = g.sdelta[i];
     const double si = s[o], ti = t[o];

@@ -280,7 +280,7 @@ __global__ void combine_adj_kernel(PairGeom g, int nb, int splitk, const double*
   const double* yb = ypart + (long)b * g.nvp * g.ncp;
   const double inv = 1.0 / (hi - lo);
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < g.nvc; i += (long)gridDim.x * blockDim.x) {
-    const int v = (int)(i / g.nc), c = (int)(i - (long)v * g.nc);
+    const int v = (int)i / g.nc, c = (int)i - v * g.nc;  // (N_v N_c < 2^31)
     const long off = (long)v * g.ncp + c;
     double y = 0.0;
     for (int s = 0; s < splitk; ++s) y += yb[s * stride_s + off];

@@ -193,6 +193,8 @@ gwl_status gwl_setup(const void* orbitals, int orb_dtype, int orb_on_device, int
     GWL_CHECK(orb_dtype == 8 || orb_dtype == 4, GWL_EINVAL, "orb_dtype must be 8 or 4");
     GWL_CHECK(n_orb >= 2 && n_occ >= 1 && n_occ < n_orb, GWL_EINVAL,
               "need 1 <= n_occ < n_orb");
+    GWL_CHECK((long)n_occ * (n_orb - n_occ) < (1L << 31), GWL_EUNSUPPORTED,
+              "the pair dimension N_v N_c must be below 2^31");
     GWL_CHECK(grid->nx >= 2 && grid->ny >= 2 && grid->nz >= 2 && grid->nx <= 256 &&
                   grid->ny <= 256 && grid->nz <= 256,
               GWL_EUNSUPPORTED, "grid edges must be in [2, 256]");
@@ -279,85 +281,55 @@ gwl_status gwl_setup(const void* orbitals, int orb_dtype, int orb_on_device, int
     GWL_HIP(hipMemcpy(c.delta2.p, d2.data(), c.nvc * 8, hipMemcpyHostToDevice));
     GWL_HIP(hipMemcpy(c.sdelta.p, sd.data(), c.nvc * 8, hipMemcpyHostToDevice));
 
-    // orbitals -> FP64 host staging in the padded transposed layout
+    // orbitals -> the kernels' layouts, packed on the GPU from one upload
     const long nrp = c.gd.nrp;
     const int nvp = c.gd.nvp, ncp = c.gd.ncp;
-    std::vector<double> host((size_t)(nvp + ncp) * nrp, 0.0);
     {
-      std::vector<unsigned char> raw;
-      const unsigned char* src = static_cast<const unsigned char*>(orbitals);
-      const size_t bytes = (size_t)n_orb * c.nr * orb_dtype;
-      if (orb_on_device) {
-        raw.resize(bytes);
-        GWL_HIP(hipMemcpy(raw.data(), orbitals, bytes, hipMemcpyDeviceToHost));
-        src = raw.data();
+      DevBuf<unsigned char> raw;
+      const void* src = orbitals;
+      if (!orb_on_device) {
+        const size_t bytes = (size_t)n_orb * c.nr * orb_dtype;
+        raw.ensure(bytes);
+        GWL_HIP(hipMemcpy(raw.p, orbitals, bytes, hipMemcpyHostToDevice));
+        src = raw.p;
       }
-      for (int n = 0; n < n_orb; ++n) {
-        double* dst = host.data() + (size_t)c.orb_row(n) * nrp;
-        if (orb_dtype == 8) {
-          const double* s = reinterpret_cast<const double*>(src) + (size_t)n * c.nr;
-          for (long r = 0; r < c.nr; ++r) dst[r] = s[r];
-        } else {
-          const float* s = reinterpret_cast<const float*>(src) + (size_t)n * c.nr;
-          for (long r = 0; r < c.nr; ++r) dst[r] = s[r];
-        }
-      }
-      GWL_CHECK(finite_all(host.data(), host.size()), GWL_EINVAL, "non-finite orbital value");
-    }
-    c.psi_t.ensure(host.size());
-    GWL_HIP(hipMemcpy(c.psi_t.p, host.data(), host.size() * 8, hipMemcpyHostToDevice));
-    {
-      std::vector<double> crc((size_t)nrp * ncp, 0.0), vrv((size_t)nrp * nvp, 0.0);
-      for (int cc = 0; cc < ncp; ++cc) {
-        const double* s = host.data() + (size_t)(nvp + cc) * nrp;
-        for (long r = 0; r < nrp; ++r) crc[(size_t)r * ncp + cc] = s[r];
-      }
-      for (int v = 0; v < nvp; ++v) {
-        const double* s = host.data() + (size_t)v * nrp;
-        for (long r = 0; r < nrp; ++r) vrv[(size_t)r * nvp + v] = s[r];
-      }
-      c.psi_c_rc64.ensure(crc.size());
-      c.psi_v_rv64.ensure(vrv.size());
-      GWL_HIP(hipMemcpy(c.psi_c_rc64.p, crc.data(), crc.size() * 8, hipMemcpyHostToDevice));
-      GWL_HIP(hipMemcpy(c.psi_v_rv64.p, vrv.data(), vrv.size() * 8, hipMemcpyHostToDevice));
+      DevBuf<unsigned long long> flags;  // [0] non-finite seen, [1] max |phi|, [2] max |f16 phi_v|
+      flags.ensure(3);
+      c.psi_t.ensure((size_t)(nvp + ncp) * nrp);
+      c.psi_c_rc64.ensure((size_t)nrp * ncp);
+      c.psi_v_rv64.ensure((size_t)nrp * nvp);
+      pack_orbitals64(c.gd, src, orb_dtype, n_orb, c.nr, c.psi_t.p, c.psi_c_rc64.p,
+                      c.psi_v_rv64.p, reinterpret_cast<int*>(flags.p), flags.p + 1, c.stream);
+      unsigned long long h[3];
+      GWL_HIP(hipMemcpyAsync(h, flags.p, sizeof(h), hipMemcpyDeviceToHost, c.stream));
+      GWL_HIP(hipStreamSynchronize(c.stream));
+      raw.release();
+      GWL_CHECK((unsigned)h[0] == 0, GWL_EINVAL, "non-finite orbital value");
       // mixed-precision copies in FP16 (both GEMMs' orbital operands and the
       // first GEMM's row-dot weights), scaled by a power of two that puts the
       // largest orbital value near 2^11
-      double omax = 0.0;
-      for (double v : host) omax = std::max(omax, std::fabs(v));
+      double omax;
+      std::memcpy(&omax, &h[1], 8);
       {
         int e = omax > 0.0 ? (int)std::floor(std::log2(2048.0 / omax)) : 0;
         e = std::max(-60, std::min(60, e));
         c.orb16_scale = std::ldexp(1.0, e);
       }
-      const double os = c.orb16_scale;
-      // the second GEMM's orbitals, in rows or K panels (orb16_index)
-      std::vector<f16_t> t16((size_t)panel_rows(c.gd) * nrp, f16_t{0});
-      std::vector<f16_t> c16(crc.size());
-      float pvmax = 0.0f;
-      for (size_t i = 0; i < host.size(); ++i) {
-        const long row = (long)(i / nrp), r = (long)(i % nrp);
-        const f16_t h = f32_to_f16((float)(os * host[i]));
-        t16[(size_t)orb16_index(c.gd, row, r)] = h;
-        if (row < nvp) pvmax = std::max(pvmax, std::fabs(f16_to_f32(h)));
-      }
+      // the second GEMM's orbitals in rows or K panels (orb16_index)
+      c.psi_t16.ensure((size_t)panel_rows(c.gd) * nrp);
+      c.psi_c_rc16.ensure((size_t)nrp * ncp);
+      c.psi_v_rv32.ensure((size_t)nrp * nvp);
+      c.psi_v_rv16.ensure((size_t)nrp * nvp);
+      pack_orbitals16(c.gd, c.psi_t.p, c.psi_c_rc64.p, c.psi_v_rv64.p, c.orb16_scale,
+                      c.psi_t16.p, c.psi_c_rc16.p, c.psi_v_rv32.p, c.psi_v_rv16.p, flags.p + 2,
+                      c.stream);
+      GWL_HIP(hipMemcpyAsync(h, flags.p, sizeof(h), hipMemcpyDeviceToHost, c.stream));
+      GWL_HIP(hipStreamSynchronize(c.stream));
+      float pvmax;
+      const unsigned pvb = (unsigned)h[2];
+      std::memcpy(&pvmax, &pvb, 4);
       c.pv16_exp = 0;
       if (pvmax > 0.0f) (void)std::frexp(pvmax, &c.pv16_exp);
-      for (size_t i = 0; i < crc.size(); ++i) c16[i] = f32_to_f16((float)(os * crc[i]));
-      std::vector<float> v32(vrv.size());
-      std::vector<f16_t> v16(vrv.size());
-      for (size_t i = 0; i < vrv.size(); ++i) {
-        v32[i] = (float)(os * vrv[i]);
-        v16[i] = f32_to_f16(v32[i]);
-      }
-      c.psi_t16.ensure(t16.size());
-      c.psi_c_rc16.ensure(c16.size());
-      c.psi_v_rv32.ensure(v32.size());
-      c.psi_v_rv16.ensure(v16.size());
-      GWL_HIP(hipMemcpy(c.psi_v_rv16.p, v16.data(), v16.size() * 2, hipMemcpyHostToDevice));
-      GWL_HIP(hipMemcpy(c.psi_t16.p, t16.data(), t16.size() * 2, hipMemcpyHostToDevice));
-      GWL_HIP(hipMemcpy(c.psi_c_rc16.p, c16.data(), c16.size() * 2, hipMemcpyHostToDevice));
-      GWL_HIP(hipMemcpy(c.psi_v_rv32.p, v32.data(), v32.size() * 4, hipMemcpyHostToDevice));
     }
 
     // FFT tables

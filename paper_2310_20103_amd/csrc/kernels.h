@@ -304,6 +304,18 @@ void adj_dbar_zops(const PairGeom& g, int nb, const double* s, const double* ks,
 // ---------------------------------------------------------------- allocation-free entry
 // Takes the device address of the static scratch array of the allocation-free
 // entry point for the current device (once per device).
+// Setup: the caller's orbitals (device, FP64 or FP32 rows of nr values) into
+// psi_t and its FP64 transposes; *bad set if a value is not finite, and
+// *omax_bits raised to the bits of max |phi| (both cleared by the caller).
+void pack_orbitals64(const GemmDims& d, const void* src, int orb_dtype, int n_orb, long nr,
+                     double* psi_t, double* psi_c_rc64, double* psi_v_rv64, int* bad,
+                     unsigned long long* omax_bits, hipStream_t st);
+// The scaled 16- and 32-bit copies (scale os); *pvmax_bits raised to the bits
+// (as float) of the largest |FP16 value| of the occupied rows.
+void pack_orbitals16(const GemmDims& d, const double* psi_t, const double* psi_c_rc64,
+                     const double* psi_v_rv64, double os, f16_t* psi_t16, f16_t* psi_c_rc16,
+                     float* psi_v_rv32, f16_t* psi_v_rv16, unsigned long long* pvmax_bits,
+                     hipStream_t st);
 void noalloc_bind_current_device();
 
 }  // namespace gwl

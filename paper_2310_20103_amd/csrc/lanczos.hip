@@ -69,7 +69,7 @@ __global__ void cast_u_kernel(PairGeom g, const double* __restrict__ x, long ldx
   const double* xb = x + (long)slot * ldx;
   U* ub = u + (long)b * g.nvp * g.ncp;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < g.nvc; i += (long)gridDim.x * blockDim.x) {
-    const int v = (int)(i / g.nc), c = (int)(i - (long)v * g.nc);
+    const int v = (int)i / g.nc, c = (int)i - v * g.nc;  // (N_v N_c < 2^31)
     ub[(long)v * g.ncp + c] = to_op<U>(g.uscale * (g.tda ? xb[i] : g.sdelta[i] * xb[i]));
   }
 }
@@ -89,7 +89,7 @@ __global__ void combine_kernel(PairGeom g, int nb, int splitk, const Y* __restri
   // the potential's scale of the mixed product is divided out with the others
   const double ysc = g.vexp ? ldexp(g.yscale, -g.vexp[b]) : g.yscale;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < g.nvc; i += (long)gridDim.x * blockDim.x) {
-    const int v = (int)(i / g.nc), c = (int)(i - (long)v * g.nc);
+    const int v = (int)i / g.nc, c = (int)i - v * g.nc;  // (N_v N_c < 2^31)
     const long off = (long)v * g.ncp + c;
     double y = 0.0;
     for (int s = 0; s < splitk; ++s) y += (double)yb[s * stride_s + off];
@@ -128,7 +128,7 @@ __global__ void coupling_finish_kernel(PairGeom g, int cnt, int splitk, const Y*
   const long stride_s = (long)cnt * g.nvp * g.ncp;
   const Y* yb = ypart + (long)i * g.nvp * g.ncp;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < g.nvc; e += (long)gridDim.x * blockDim.x) {
-    const int v = (int)(e / g.nc), c = (int)(e - (long)v * g.nc);
+    const int v = (int)e / g.nc, c = (int)e - v * g.nc;  // (N_v N_c < 2^31)
     const long off = (long)v * g.ncp + c;
     double y = 0.0;
     for (int s = 0; s < splitk; ++s) y += (double)yb[s * stride_s + off];

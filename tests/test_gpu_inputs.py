@@ -13,6 +13,8 @@ headline-shaped case, each against the FP64 CPU oracle element by element.
   (N_vc = 4096), where Sigma is eV-sized and the 1 meV bar on the mixed path
   binds; FP64 <= 1e-8 relative and mixed <= 1e-3 eV against the oracle's
   Lanczos Sigma (its spectral-measure route) for all four QP states.
+* A NaN or an infinity among the orbital values (FP64 or FP32, host or
+  device) is refused at setup, where the orbitals are packed on the GPU.
 """
 import numpy as np
 import pytest
@@ -52,6 +54,20 @@ def f32case():
     pr = oracle.Problem(phi32.astype(np.float64), s.energies_ev, wl.n_occ, wl.grid, wl.h)
     lo, hi = oracle.default_interval(pr)
     return wl, s, phi32, pr, lo, hi
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("where", ["host", "device"])
+def test_non_finite_orbitals_refused(f32case, dtype, where):
+    import paper_2310_20103_amd as G
+    wl, s, phi32, pr, lo, hi = f32case
+    _say("non-finite orbital values refused,", np.dtype(dtype).name, where)
+    for bad in (np.nan, np.inf):
+        phi = s.phi.astype(dtype)
+        phi[wl.n_occ + 3, 1234] = bad  # a conduction orbital, away from the row ends
+        src = phi if where == "host" else torch.from_numpy(phi).cuda()
+        with pytest.raises(G.GwlError, match="non-finite orbital value"):
+            _ctx(src, s.energies_ev, wl, lo, hi)
 
 
 @pytest.mark.parametrize("where", ["host", "device"])
