@@ -229,6 +229,16 @@ gwl_status gwl_setup(const void* orbitals, int orb_dtype, int orb_on_device, int
       GWL_HIP(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
       c.own_stream = true;
     }
+    // a setup that fails after this point destroys the stream it created
+    struct StreamGuard {
+      std::unique_ptr<gwl_ctx>& ctx;
+      ~StreamGuard() {
+        if (ctx && ctx->own_stream) {
+          (void)hipStreamSynchronize(ctx->stream);
+          (void)hipStreamDestroy(ctx->stream);
+        }
+      }
+    } stream_guard{ctx};
     c.nx = grid->nx;
     c.ny = grid->ny;
     c.nz = grid->nz;
