@@ -279,7 +279,8 @@ gwl_status gwl_sigma_c_range_vjp(gwl_ctx* ctx, const int* qp_states, int n_qp, i
  * instead of running the forward again; it may be called several times.
  * Errors: as gwl_sigma_c_range_vjp; gwl_sigma_c_vjp_backward returns
  * GWL_EINVAL when no forward was kept, or when the interval, polynomial
- * degree or block size of the context changed since. */
+ * degree, block size, GEMM split or kernel choice of the context changed
+ * since (the recompute must repeat the forward's arithmetic). */
 gwl_status gwl_sigma_c_vjp_forward(gwl_ctx* ctx, const int* qp_states, int n_qp, int n_begin,
                                    int n_end, const double* omega_ev, int n_omega, double eta_ev,
                                    int n_lanczos, double* sigma_out);
