@@ -740,7 +740,7 @@ def run_libref(args):
         "ours_tflops": {k: tf(v) for k, v in ours.items() if k.startswith("gemm")},
         "hipblaslt_ms": {k: round(v, 4) for k, v in lib.items()},
         "hipblaslt_tflops": {k: tf(v) for k, v in lib.items()},
-        "note": "ours: gemm1 = FP16 GEMM with the fused row-dot (no C written), gemm2 = BF16 "
+        "note": "ours: gemm1 = FP16 GEMM with the fused row-dot (no C written), gemm2 = FP16 "
                 "GEMM forming phi_v*V in staging; library: plain operands, unfused"}),
           flush=True)
 
