@@ -133,7 +133,7 @@ struct gwl_ctx {
   double kernel_scale = 1.0;
   int splitk = 0;  // 0 = automatic
   int fp64_kernel = 1;  // 0 = plain FMA tiles, 1 = MFMA (both precisions)
-  int bf16_tile = 256;  // block tile width of the second BF16 MFMA GEMM
+  int bf16_tile = 256;  // block tile width of the second 16-bit MFMA GEMM
   bool tile_fixed = false;  // set by the caller: the autotuner keeps it
   int tda = 0;          // 1: Tamm-Dancoff (Lanczos on A = Delta + K from (nm|vc))
   int quadrature = 0;   // 1: Lanczos on C + Gauss quadrature (no polynomial)

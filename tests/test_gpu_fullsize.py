@@ -1,14 +1,14 @@
 """Parity at the headline size, in the launch configuration the benchmark
 times: grid64_v128c512 (64^3 grid, 24 bohr box, 128 + 512 orbitals,
-N_vc = 65536), B = 128 pair vectors per product, mixed precision (FP16 first
-GEMM, BF16 second GEMM) and the same batch in FP64.  Sampled outputs against
+N_vc = 65536), B = 128 pair vectors per product, mixed precision (FP16
+operands in both GEMMs) and the same batch in FP64.  Sampled outputs against
 the oracle computed one at a time by its matrix-free FP64 route:
 
 * C x of 128 seeded vectors, rows 0, 77 and 127: FP64 <= 1e-10 relative;
   mixed <= 1e-3 relative, and its coupling part C x - Delta^2 x <= 2e-2
-  relative (the bars of the small cases: FP16 / BF16 operand rounding of
-  about 2^-11 and 2^-9, averaged over the grid sums, on a part that is a
-  small fraction of C x);
+  relative (the bars of the small cases: FP16 operand rounding of about
+  2^-11 per factor, averaged over the grid sums, on a part that is a small
+  fraction of C x);
 * coupling vectors P_nm of the first QP state for n = 0, 300, 639 (FP64
   <= 1e-10);
 * all 128 vectors of a second batch: the Gram matrix x_i . C x_j is
