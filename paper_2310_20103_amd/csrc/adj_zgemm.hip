@@ -18,12 +18,14 @@
 // One kernel computes Z tile by tile on the FP64 matrix cores
 // (v_mfma_f64_16x16x4f64) and contracts each tile at once, so Z never
 // reaches memory: a block owns 64 conduction indices c and 128 grid points r
-// and walks the occupied indices two at a time (one per pair of waves), K
-// over all outer products of the launch.  The conduction gradient stays in
-// registers across the walk and is added once per block (each element has
-// one owner); the occupied gradient of the block's 64 c is written as a
-// partial sum per c tile and reduced in fixed order at the end, so runs are
-// bitwise reproducible.
+// and walks the occupied indices two at a time, K over all outer products of
+// the launch; each wave holds both occupied indices of a pair for half the
+// block's c.  The conduction gradient is added to its grid row in place after
+// every pair (each element has one owner, one wave of one block, so the
+// additions run in a fixed order), which keeps the kernel at two waves per
+// SIMD; the occupied gradient of the block's 64 c is written as a partial sum
+// per c tile and reduced in fixed order at the end, so runs are bitwise
+// reproducible.
 #include "common.h"
 #include "kernels.h"
 
@@ -43,15 +45,15 @@ __device__ inline int xcd_remap_z(int bid, int total) {
   return (bid & 7) * (total >> 3) + (bid >> 3);
 }
 
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 1)))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
 zgemm_kernel(GemmDims d, int nv, ZSeg s0, ZSeg s1, const double* __restrict__ psi_c_rc,
              const double* __restrict__ psi_v_rv, double dv, double* __restrict__ grad_c,
              double* __restrict__ gvpart) {
-  // two operand tiles [ZK][ZLD] during the K loop; the conduction-gradient
-  // exchange between wave pairs at the end ([64][128] doubles) reuses them
-  __shared__ double sm[2 * ZK * ZLD > 64 * 128 ? 2 * ZK * ZLD : 64 * 128];
-  double(*As)[ZLD] = reinterpret_cast<double(*)[ZLD]>(sm);
-  double(*Bs)[ZLD] = reinterpret_cast<double(*)[ZLD]>(sm + ZK * ZLD);
+  // one operand tile pair [ZK][ZLD] during the K loop; the exchange of the
+  // occupied-gradient halves between the wave pairs after it
+  __shared__ double As[ZK][ZLD];
+  __shared__ double Bs[ZK][ZLD];
+  __shared__ double xs[2][ZN];
   const int nct = d.ncp / 64, nrt = d.nrp / ZN;
   const int lid = xcd_remap_z(blockIdx.x, nct * nrt);
   const int rt = lid / nct, ct = lid - rt * nct;
@@ -60,15 +62,16 @@ zgemm_kernel(GemmDims d, int nv, ZSeg s0, ZSeg s1, const double* __restrict__ ps
   const int wm = w >> 1, wn = w & 1;
   const int K = s0.k + s1.k;
   // loader: k row lk of the step, 8 consecutive doubles at column lm
+  // (columns: 64 conduction indices of v0, then 64 of v0 + 1)
   const int lk = t >> 4, lm = (t & 15) * 8;
   const int lvo = lm >> 6, lc = c0 + (lm & 63);
   const long ld_u = (long)d.nvp * d.ncp;
-
-  d4 gc[4][4];
+  // wave (wm, wn) computes Z for both v of the pair, conduction indices
+  // c0 + 32 wm + [0, 32), grid points r0 + 64 wn + [0, 64): MFMA row block i
+  // is v offset i >> 1, conduction offset 32 wm + 16 (i & 1)
+  int acol[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) gc[i][j] = d4{0, 0, 0, 0};
+  for (int i = 0; i < 4; ++i) acol[i] = (i >> 1) * 64 + wm * 32 + 16 * (i & 1) + (l & 15);
 
   for (int v0 = 0; v0 < nv; v0 += 2) {
     d4 acc[4][4];
@@ -114,7 +117,7 @@ zgemm_kernel(GemmDims d, int nv, ZSeg s0, ZSeg s1, const double* __restrict__ ps
       }
     };
     gload(0);
-    __syncthreads();  // the previous walk step's epilogue has left the LDS
+    __syncthreads();  // the previous pair's epilogue has read xs
     lstore();
     __syncthreads();
     for (int k0 = 0; k0 < K; k0 += ZK) {
@@ -126,7 +129,7 @@ zgemm_kernel(GemmDims d, int nv, ZSeg s0, ZSeg s1, const double* __restrict__ ps
         double a[4], b[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          a[i] = As[kk][wm * 64 + 16 * i + (l & 15)];
+          a[i] = As[kk][acol[i]];
           b[i] = Bs[kk][wn * 64 + 16 * i + (l & 15)];
         }
 #pragma unroll
@@ -141,58 +144,62 @@ zgemm_kernel(GemmDims d, int nv, ZSeg s0, ZSeg s1, const double* __restrict__ ps
         __syncthreads();
       }
     }
-    // epilogue of this occupied index v = v0 + wm: acc[i][j][q] is Z at
-    // c = c0 + 16 i + (l >> 4) + 4 q, r = r0 + wn 64 + 16 j + (l & 15)
-    const int v = v0 + wm;
-    if (v < nv) {
+    // epilogue of the pair: acc[i][j][q] is Z at v = v0 + (i >> 1),
+    // c = c0 + 32 wm + 16 (i & 1) + (l >> 4) + 4 q, r = r0 + 64 wn + 16 j + (l & 15).
+    // Conduction gradient: dV (phi_v0 Z_v0 + phi_v0+1 Z_v0+1) added in place
+    // (every element of grad_c has one owner: this block, this wave), pair
+    // after pair.  Occupied gradient: each wave sums its 32 c, the two halves
+    // meet through LDS and go to this c tile's partial row.
+    double sv[2][4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int r = r0 + wn * 64 + 16 * j + (l & 15);
-        const double* wc = psi_c_rc + (long)r * d.ncp + c0 + (l >> 4);
-        const double pv = psi_v_rv[(long)r * d.nvp + v];
-        double s = 0.0;
+    for (int j = 0; j < 4; ++j) {
+      const int r = r0 + wn * 64 + 16 * j + (l & 15);
+      // (v0 + 1 < N_vp: N_vp is a multiple of 64 and v0 is even; padded rows are zero)
+      const double pv0 = psi_v_rv[(long)r * d.nvp + v0];
+      const double pv1 = psi_v_rv[(long)r * d.nvp + v0 + 1];
+      const double* wc = psi_c_rc + (long)r * d.ncp + c0 + wm * 32 + (l >> 4);
+      double a0 = 0.0, a1 = 0.0;
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+      for (int i2 = 0; i2 < 2; ++i2)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            s += wc[16 * i + 4 * q] * acc[i][j][q];
-            gc[i][j][q] += pv * acc[i][j][q];
-          }
-        s += __shfl_xor(s, 16, 64);
-        s += __shfl_xor(s, 32, 64);
-        if (l < 16) {
-          double* o = gvpart + ((long)ct * nv + v) * d.nrp + r;
-          *o += dv * s;
+        for (int q = 0; q < 4; ++q) {
+          const double z0 = acc[i2][j][q], z1 = acc[2 + i2][j][q];
+          const double cw = wc[16 * i2 + 4 * q];
+          a0 += cw * z0;
+          a1 += cw * z1;
+          double* o = grad_c + (long)(c0 + wm * 32 + 16 * i2 + (l >> 4) + 4 * q) * d.nrp + r;
+          *o += dv * (pv0 * z0 + pv1 * z1);
+        }
+      a0 += __shfl_xor(a0, 16, 64);
+      a0 += __shfl_xor(a0, 32, 64);
+      a1 += __shfl_xor(a1, 16, 64);
+      a1 += __shfl_xor(a1, 32, 64);
+      sv[0][j] = a0;
+      sv[1][j] = a1;
+      // one j at a time: hoisting the loads of all four next to the
+      // accumulators would exceed the register budget of two waves per SIMD
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (wm == 1 && l < 16) {
+#pragma unroll
+      for (int vo = 0; vo < 2; ++vo)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) xs[vo][wn * 64 + 16 * j + l] = sv[vo][j];
+    }
+    __syncthreads();
+    if (wm == 0 && l < 16) {
+#pragma unroll
+      for (int vo = 0; vo < 2; ++vo) {
+        const int v = v0 + vo;
+        if (v >= nv) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int rl = wn * 64 + 16 * j + l;
+          double* o = gvpart + ((long)ct * nv + v) * d.nrp + r0 + rl;
+          *o += dv * (sv[vo][j] + xs[vo][rl]);
         }
       }
     }
-  }
-  // conduction gradient: the even-v waves (wm = 0) add the odd-v waves' sums
-  __syncthreads();
-  double(*X)[ZN] = reinterpret_cast<double(*)[ZN]>(sm);
-  if (wm == 1) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          X[16 * i + (l >> 4) + 4 * q][wn * 64 + 16 * j + (l & 15)] = gc[i][j][q];
-  }
-  __syncthreads();
-  if (wm == 0) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int cl = 16 * i + (l >> 4) + 4 * q;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int rl = wn * 64 + 16 * j + (l & 15);
-          double* o = grad_c + (long)(c0 + cl) * d.nrp + r0 + rl;
-          *o += dv * (gc[i][j][q] + X[cl][rl]);
-        }
-      }
   }
 }
 
