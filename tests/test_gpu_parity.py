@@ -190,6 +190,36 @@ def test_potential_product(request, which):
         assert relerr(got[3:], kx) <= tol
 
 
+def test_component_calls_chunked_and_errors(request):
+    """gwl_pair_density and gwl_potential_product over 130 vectors (a batch
+    of 128, then 2): the same values as one call per vector (to rounding:
+    the split of the grid sum depends on the batch size); no vectors is a
+    no-op; the ISDF product refuses both."""
+    import paper_2310_20103_amd as G
+    from oracle import casida as CA
+    case = request.getfixturevalue("ragged")
+    ctx = request.getfixturevalue("ctx_ragged")
+    _say("component calls over 130 vectors")
+    x = gi.random_pair_vectors(130, case.wl.n_vc, seed=23)
+    ref = (np.sqrt(case.pr.delta) * x) @ CA.pair_densities(case.sys.phi, case.wl.n_occ)
+    rho = ctx.pair_density(torch.tensor(x, device="cuda"), "fp64").cpu().numpy()
+    assert relerr(rho, ref) <= 1e-12
+    y = ctx.potential_product(torch.tensor(rho, device="cuda"), "fp64").cpu().numpy()
+    one = np.concatenate([ctx.potential_product(torch.tensor(rho[i:i + 1], device="cuda"),
+                                                "fp64").cpu().numpy() for i in (0, 127, 128, 129)])
+    assert relerr(y[[0, 127, 128, 129]], one) <= 1e-12
+    empty = ctx.potential_product(torch.zeros((0, case.wl.n_r), dtype=torch.float64,
+                                              device="cuda"), "fp64")
+    assert tuple(empty.shape) == (0, case.wl.n_vc)
+    with make_ctx(case.sys, interval=(case.lo, case.hi)) as c2:
+        # 32 spread points (fewer than N_vc = 95, so C C^T is regular)
+        c2.isdf_setup(np.linspace(0, case.wl.n_r - 1, 32).astype(np.int32))
+        with pytest.raises(G.GwlError, match="ISDF"):
+            c2.potential_product(torch.tensor(rho[:2], device="cuda"), "fp64")
+        with pytest.raises(G.GwlError, match="ISDF"):
+            c2.pair_density(torch.tensor(x[:2], device="cuda"), "fp64")
+
+
 @pytest.mark.parametrize("n_emp", [100, 150, 260])
 def test_apply_c_conduction_k_steps(n_emp):
     """C x with N_c padded to 128, 192 and 320: the K loops of the GEMMs over
