@@ -475,6 +475,37 @@ class Context:
         return out
 
 
+_COEFF_KEYS = ("m", "n", "alpha", "beta", "norm2", "lens")
+
+
+def save_coefficients(path, m_idx, n_idx, alpha, beta, norm2, lens, **meta):
+    """Write the Lanczos coefficients of (m, n) start vectors (the output of
+    Context.lanczos_pairs) to an .npz file.  They fix Sigma on any frequency
+    grid and broadening (the continued fraction of Eq. 14), so
+    Context.sigma_from_coeffs on the loaded arrays resumes without another
+    Lanczos run.  meta: scalars or lists describing the run (interval,
+    degree, precision, grid, ...), stored as JSON."""
+    import json
+    arrays = {"m": _i32(m_idx), "n": _i32(n_idx), "alpha": _f64(alpha), "beta": _f64(beta),
+              "norm2": _f64(norm2), "lens": _i32(lens)}
+    P = len(arrays["n"])
+    if not (len(arrays["m"]) == P and arrays["alpha"].shape == arrays["beta"].shape
+            and arrays["alpha"].ndim == 2 and arrays["alpha"].shape[0] == P
+            and len(arrays["norm2"]) == P and len(arrays["lens"]) == P):
+        raise ValueError("coefficient arrays of inconsistent shapes")
+    np.savez(path, meta=np.array(json.dumps(meta)), **arrays)
+
+
+def load_coefficients(path):
+    """(arrays, meta) from save_coefficients: arrays holds m, n, alpha, beta,
+    norm2, lens; nothing in the file is executed (no pickled objects)."""
+    import json
+    with np.load(path, allow_pickle=False) as f:
+        arrays = {k: f[k] for k in _COEFF_KEYS}
+        meta = json.loads(str(f["meta"]))
+    return arrays, meta
+
+
 def qp_solve(omega_ev, sigma_c, eps_ev: float, sigma_x_ev: float, vxc_ev: float = 0.0):
     """(E_qp, Z) from the graphical solution on the frequency grid (eV);
     raises GwlError when the equation has no root on the grid."""

@@ -443,6 +443,37 @@ def test_sigma_from_coeffs(small, ctx_small):
         assert relerr(got[i], ref) <= 1e-12
 
 
+def test_resume_from_coefficient_file(small, ctx_small, tmp_path):
+    """Lanczos coefficients from the GPU written to .npz, read back and turned
+    into Sigma on a second frequency grid and broadening: the same values as
+    from the arrays in memory, bit for bit, and as the oracle's continued
+    fraction on the same coefficients."""
+    import paper_2310_20103_amd as G
+    _say("resume Sigma from a coefficient file")
+    m = int(small.sys.qp_states[0])
+    ns = list(range(0, small.wl.n_orb, 3))
+    L = 12
+    a, b, n2, ol = ctx_small.lanczos_pairs([m] * len(ns), ns, [L] * len(ns))
+    path = tmp_path / "coeffs.npz"
+    lo, hi = ctx_small.interval
+    G.save_coefficients(path, [m] * len(ns), ns, a, b, n2, ol, poly_lo=lo, poly_hi=hi,
+                        poly_degree=small.wl.poly_degree)
+    got, meta = G.load_coefficients(path)
+    assert meta["poly_hi"] == hi
+    om2 = np.linspace(-30.0, 30.0, 77)
+    eta2 = 0.25
+    ref = ctx_small.sigma_from_coeffs(ns, a, b, n2, ol, om2, eta2)
+    res = ctx_small.sigma_from_coeffs(got["n"], got["alpha"], got["beta"], got["norm2"],
+                                      got["lens"], om2, eta2)
+    assert np.array_equal(res, ref)
+    for i, n in enumerate(ns):
+        k = int(ol[i])
+        orc = S.sigma_n_from_tridiag(a[i, :k], b[i, :max(k - 1, 0)], n2[i],
+                                     om2 / oracle.HARTREE_EV, small.pr.eps[n], small.pr.eta(n),
+                                     eta2 / oracle.HARTREE_EV) * oracle.HARTREE_EV
+        assert relerr(res[i], orc) <= 1e-12
+
+
 def test_reorth_modes_close(small):
     _say("reorth none/local vs full")
     wl = small.wl
